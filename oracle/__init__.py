@@ -1,0 +1,2 @@
+"""FP64 CPU oracle (test infrastructure only; see oracle.oracle)."""
+from .oracle import *  # noqa: F401,F403

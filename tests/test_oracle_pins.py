@@ -1,0 +1,346 @@
+"""Pins of the FP64 oracle against mathematics and physics it must satisfy.
+
+None of these re-types an oracle formula: each compares the oracle with an
+independent route (mpmath at 40 digits, quadrature of a defining integral, a
+second formula the paper states for the same quantity, a closed form of a
+special case, a conservation law, or finite differences).
+"""
+import json
+import math
+import os
+
+import mpmath as mp
+import numpy as np
+import pytest
+from scipy import integrate, special
+
+import synth
+from oracle import oracle as O
+
+HERE = os.path.dirname(__file__)
+BOUNDS = json.load(open(os.path.join(HERE, "golden", "paper_bounds.json")))
+
+
+# ---------------------------------------------------------------- Faddeeva
+
+def _mp_w(z):
+    mp.mp.dps = 40
+    zz = mp.mpc(z.real, z.imag)
+    return complex(mp.exp(-zz * zz) * mp.erfc(-1j * zz))
+
+
+@pytest.mark.parametrize("x", [0.0, 1e-3, 0.3, 1.7, 4.0, 9.9, 10.6, 35.0, 400.0, 3e4])
+@pytest.mark.parametrize("y", [1e-9, 1e-3, 0.2, 1.0, 5.0, 80.0])
+def test_faddeeva_vs_mpmath(x, y):
+    z = complex(x, y)
+    ref = _mp_w(z)
+    got = complex(O.faddeeva(z))
+    assert abs(got - ref) <= 1e-13 * abs(ref) + 1e-300
+
+
+def test_w_on_imaginary_axis_is_erfcx():
+    y = np.array([1e-6, 0.1, 1.0, 3.0, 30.0, 1e4])
+    np.testing.assert_allclose(O.faddeeva(1j * y).real, special.erfcx(y), rtol=1e-14)
+
+
+def test_gaussian_limit_and_dawson():
+    x = np.linspace(-6, 6, 241)
+    np.testing.assert_allclose(O.voigt_hjerting(x, 0.0), np.exp(-x * x), rtol=1e-13, atol=1e-300)
+    L = O.faddeeva(x + 0j).imag
+    np.testing.assert_allclose(L, 2.0 * special.dawsn(x) / math.sqrt(math.pi), rtol=1e-13, atol=1e-16)
+
+
+@pytest.mark.parametrize("x,a", [(0.0, 0.5), (1.3, 0.05), (4.0, 2.0), (12.0, 0.3)])
+def test_hjert_defining_integral(x, a):
+    """H(x,a) = a/pi * int exp(-y^2)/((x-y)^2 + a^2) dy by adaptive quadrature (Sec. 2.1.1)."""
+    f = lambda y: math.exp(-y * y) / ((x - y) ** 2 + a * a)
+    pts = sorted({x, 0.0})
+    val = 0.0
+    edges = [-12.0] + pts + [12.0]
+    for lo, hi in zip(edges[:-1], edges[1:]):
+        if hi > lo:
+            val += integrate.quad(f, lo, hi, epsabs=0, epsrel=1e-13, limit=400)[0]
+    val *= a / math.pi
+    assert O.voigt_hjerting(x, a) == pytest.approx(val, rel=1e-9)
+
+
+def test_voigt_symmetry_normalisation_and_limits():
+    beta, gam = 0.0098, 0.04
+    d = np.linspace(0.1, 3.0, 7)
+    np.testing.assert_allclose(O.voigt_profile(d, beta, gam), O.voigt_profile(-d, beta, gam), rtol=1e-15)
+    # unit area: integral over [-Lw, Lw] plus the two Lorentzian tails 2 gamma/(pi Lw)
+    Lw = 50.0
+    val = integrate.quad(lambda t: float(O.voigt_profile(t, beta, gam)), -Lw, Lw,
+                         points=[0.0], limit=2000, epsabs=0, epsrel=1e-12)[0]
+    assert val + 2 * gam / (math.pi * Lw) == pytest.approx(1.0, abs=2e-9)
+    # Lorentz limit (beta -> 0) and Gaussian limit (gamma -> 0)
+    dd = np.array([0.05, 0.3, 2.0])
+    lor = gam / math.pi / (dd ** 2 + gam ** 2)
+    np.testing.assert_allclose(O.voigt_profile(dd, 1e-7, gam), lor, rtol=1e-6)
+    dd = np.array([0.05, 0.3, 0.8])
+    gau = np.exp(-dd ** 2 / (2 * 0.2 ** 2)) / (math.sqrt(2 * math.pi) * 0.2)
+    np.testing.assert_allclose(O.voigt_profile(dd, 0.2, 1e-12), gau, rtol=1e-9)
+
+
+# ---------------------------------------------------------------- line parameters
+
+def test_line_strength_reference_and_exomol_route():
+    """Eq. Slog with s0 from Eq. STexomol at T_ref must equal Eq. STexomol at any T (Sec. 2.2.2)."""
+    nu = np.array([4341.2, 4355.0, 4379.9])
+    E = np.array([0.0, 1234.5, 8000.0])
+    A, gup = np.array([3.1, 0.02, 55.0]), np.array([3.0, 21.0, 7.0])
+    # partition function Q(T) = Q0 (T/296)^1.5: q_r = (T/296)^1.5
+    Q = lambda T: 41.0 * (T / 296.0) ** 1.5
+    # Eq. STexomol with h, c, k_B written separately (not through c2)
+    hck = O.H_PLANCK * O.C_LIGHT / O.K_BOLTZ
+
+    def s_exomol(T):
+        return gup / Q(T) * A / (8 * math.pi * O.C_LIGHT * nu ** 2) * np.exp(-hck * E / T) * (1 - np.exp(-hck * nu / T))
+
+    S0 = s_exomol(296.0)
+    for T in (296.0, 700.0, 1300.0, 2600.0):
+        S = O.line_strength(S0, E, nu, T, O.qr_ratio(T, 0, [1.5]))
+        np.testing.assert_allclose(S, s_exomol(T), rtol=1e-12)
+    # the paper's printed c2
+    assert O.C2 == pytest.approx(BOUNDS["c2_printed_cmK"]["value"], rel=5e-7)
+
+
+def test_doppler_width_from_maxwell_velocity():
+    # 1-D Maxwell velocity dispersion sqrt(kT/m) in SI units, times nu/c
+    kB, mu, c = 1.380649e-23, 1.66053906660e-27, 2.99792458e8
+    v = math.sqrt(kB * 1000.0 / (18 * mu))
+    assert O.doppler_beta(4350.0, 1000.0, 18.0) == pytest.approx(4350.0 * v / c, rel=1e-14)
+    assert O.doppler_beta(4350.0, 1000.0, 18.0) == pytest.approx(9.8616e-3, rel=1e-4)
+
+
+def test_pressure_broadening_scalings():
+    a, n = np.array([0.05]), np.array([0.6])
+    assert O.lorentz_gamma(a, n, 296.0, 1.0)[0] == pytest.approx(0.05, rel=1e-15)
+    assert O.lorentz_gamma(a, n, 592.0, 1.0)[0] == pytest.approx(0.05 * 2 ** -0.6, rel=1e-14)
+    assert O.lorentz_gamma(a, n, 700.0, 3.0)[0] == pytest.approx(3 * O.lorentz_gamma(a, n, 700.0, 1.0)[0], rel=1e-15)
+    assert O.lorentz_gamma(a, n, 700.0, 1.0, 0.01)[0] == pytest.approx(O.lorentz_gamma(a, n, 700.0, 1.0)[0] + 0.01)
+
+
+def test_line_tangents_by_finite_differences():
+    wl = synth.make_config(2, "tiny")
+    ll = wl.lines[0]
+    T, P, h = 1234.0, 0.3, 1e-3
+    st = O.line_state(ll, T, P)
+    sp, sm = O.line_state(ll, T + h, P), O.line_state(ll, T - h, P)
+    np.testing.assert_allclose(st.dlnS_dT, (np.log(sp.S) - np.log(sm.S)) / (2 * h), rtol=1e-7)
+    np.testing.assert_allclose(st.dbeta_dT, (sp.beta - sm.beta) / (2 * h), rtol=1e-8)
+    np.testing.assert_allclose(st.dgamma_dT, (sp.gamma - sm.gamma) / (2 * h), rtol=1e-8)
+
+
+# ---------------------------------------------------------------- cross-section
+
+def test_cross_section_brute_force_mpmath():
+    """sigma = sum_l S_l V_l with every profile from mpmath's erfc (independent of scipy)."""
+    wl = synth.make_config(1, "tiny")
+    ll = wl.lines[0]
+    nu = wl.nu[::7]
+    sig = O.cross_section(ll, 1000.0, 1.0, nu)
+    kB, mu, c = 1.380649e-16, 1.66053906660e-24, 2.99792458e10
+    hck = 6.62607015e-27 * c / kB
+    ref = []
+    for v in nu:
+        acc = mp.mpf(0)
+        for l in range(ll.n):
+            S = ll.S0[l] * (1 - math.exp(-hck * ll.nu_c[l] / 1000.0)) / (1 - math.exp(-hck * ll.nu_c[l] / 296.0))
+            beta = math.sqrt(kB * 1000.0 / (18 * mu)) * ll.nu_c[l] / c
+            gam = ll.alpha_ref[l]
+            z = complex(v - ll.nu_c[l], gam) / (math.sqrt(2) * beta)
+            acc += S * _mp_w(z).real / (math.sqrt(2 * math.pi) * beta)
+        ref.append(float(acc))
+    np.testing.assert_allclose(sig, ref, rtol=1e-12)
+
+
+def test_cross_section_tangent_fd():
+    wl = synth.make_config(2, "tiny")
+    ll = wl.lines[1]
+    nu = wl.nu[::10]
+    T, P, h = 950.0, 0.02, 1e-2
+    s, ds = O.cross_section(ll, T, P, nu, want_dT=True)
+    fd = (O.cross_section(ll, T + h, P, nu) - O.cross_section(ll, T - h, P, nu)) / (2 * h)
+    np.testing.assert_allclose(ds, fd, rtol=1e-6, atol=1e-9 * np.abs(fd).max())
+
+
+# ---------------------------------------------------------------- transmission / RT
+
+def test_transmission_vs_mpmath_and_recurrence():
+    mp.mp.dps = 30
+    x = np.array([1e-8, 1e-4, 0.01, 0.3, 1.0, 2.5, 10.0, 60.0])
+    ref = np.array([float(2 * mp.expint(3, mp.mpf(v))) for v in x])
+    np.testing.assert_allclose(O.transmission(x), ref, rtol=1e-13)
+    assert O.transmission(0.0) == 1.0
+    # E3 = (e^-x - x E2)/2  and  dT/dtau = -2 E2
+    E1 = special.exp1(x)
+    E2 = np.exp(-x) - x * E1
+    E3 = (np.exp(-x) - x * E2) / 2
+    np.testing.assert_allclose(O.transmission(x), 2 * E3, rtol=1e-12)
+    h = 1e-6 * np.maximum(x, 1e-3)
+    fd = (O.transmission(x + h) - O.transmission(x - h)) / (2 * h)
+    np.testing.assert_allclose(O.dtransmission(x), fd, rtol=1e-6)
+
+
+def test_rt_isothermal_and_slab_closed_forms():
+    nu = np.linspace(4300, 4400, 5)
+    B = O.planck_pi(1100.0, nu)
+    rng = np.random.default_rng(3)
+    dtau = rng.uniform(0.0, 0.7, (13, nu.size))
+    FB = O.planck_pi(1500.0, nu)
+    F0, _ = O.rt_recurrence(dtau, np.broadcast_to(B, dtau.shape), FB)
+    Tprod = np.prod(O.transmission(dtau), axis=0)
+    np.testing.assert_allclose(F0, B * (1 - Tprod) + Tprod * FB, rtol=1e-13)
+    # F_B = B: an isothermal atmosphere emits exactly B
+    F0b, _ = O.rt_recurrence(dtau, np.broadcast_to(B, dtau.shape), B)
+    np.testing.assert_allclose(F0b, B, rtol=1e-14)
+    # single slab
+    tau = np.array([[0.4, 3.0, 1e-6, 0.0, 40.0]])
+    F1, _ = O.rt_recurrence(tau, B[None, :], FB)
+    t3 = np.array([float(2 * mp.expint(3, mp.mpf(v))) if v > 0 else 1.0 for v in tau[0]])
+    np.testing.assert_allclose(F1, B * (1 - t3) + t3 * FB, rtol=1e-13)
+    # opaque top layer -> pi B(T_0); transparent -> F_B
+    assert F1[4] == pytest.approx(B[4], rel=1e-15)
+    assert F1[3] == FB[3]
+
+
+def test_rt_recurrence_equals_cumprod_form():
+    """Eq. rerr (recurrence) against Eq. lart, F0 = (Phi o Q)^T u with Q_N = F_B (Sec. 3.1)."""
+    rng = np.random.default_rng(5)
+    N, J = 17, 6
+    dtau = rng.exponential(0.3, (N, J))
+    S = rng.uniform(1e3, 5e3, (N, J))
+    FB = rng.uniform(1e3, 5e3, J)
+    Tm = O.transmission(dtau)
+    Qm = np.vstack([(1 - Tm) * S, FB[None]])
+    tv = np.vstack([np.ones((1, J)), Tm])
+    Phi = np.cumprod(tv, axis=0)
+    np.testing.assert_allclose(O.rt_recurrence(dtau, S, FB)[0], np.sum(Phi * Qm, axis=0), rtol=1e-13)
+
+
+def test_planck_integrates_to_stefan_boltzmann():
+    T = 1300.0
+    sigma_sb = 2 * math.pi ** 5 * O.K_BOLTZ ** 4 / (15 * O.C_LIGHT ** 2 * O.H_PLANCK ** 3)
+    val = integrate.quad(lambda n: float(O.planck_pi(T, n)), 1e-3, 2e5, limit=400, epsrel=1e-12)[0]
+    assert val == pytest.approx(sigma_sb * T ** 4, rel=1e-9)
+
+
+def test_layer_thickness_and_column():
+    P = np.logspace(-8, 2, 100)
+    dP = O.layer_dP_bar(P)
+    r = 10 ** (10 / 99)
+    np.testing.assert_allclose(dP, P * (1 - 1 / r), rtol=1e-12)
+    # the layers tile the column: sum dP telescopes to P_bottom - P_top/r
+    assert np.sum(dP) == pytest.approx(P[-1] - P[0] / r, rel=1e-12)
+
+
+def test_cia_against_number_density_route():
+    """Eq. taucont: n^2 alpha Delta r with Delta r = H dP/P and n = xi P/(k T) (Sec. 2.4)."""
+    atm = synth.make_config(2, "tiny").atmos
+    T, P, dP, nu = 1234.0, 0.7, 0.05, np.array([4350.0, 4370.0])
+    n = atm.vmr_h2 * P * 1e6 / (O.K_BOLTZ * T)
+    Hs = O.K_BOLTZ * T / (atm.mmw * O.M_U * atm.g_cgs)
+    alpha = O.cia_coefficient(T, nu, atm.cia_alpha0, atm.cia_Tpow, atm.cia_slope, atm.cia_nu_c)
+    np.testing.assert_allclose(O.dtau_cia(T, P, dP, nu, atm), n * n * alpha * Hs * dP / P, rtol=1e-14)
+
+
+# ---------------------------------------------------------------- response
+
+def test_rotation_kernel_matches_disk_integral_and_is_normalised():
+    u1, u2 = 0.5367, 0.3578
+
+    def disk(x):
+        s = math.sqrt(1 - x * x)
+        I = lambda y: 1 - u1 * (1 - math.sqrt(max(0.0, 1 - x * x - y * y))) - u2 * (1 - math.sqrt(max(0.0, 1 - x * x - y * y))) ** 2
+        return integrate.quad(I, -s, s, epsabs=0, epsrel=1e-12)[0]
+
+    tot = integrate.quad(disk, -1, 1, epsabs=0, epsrel=1e-10, limit=200)[0]
+    for x in (0.0, 0.3, 0.77, 0.99):
+        assert O.rotation_kernel(x, u1, u2) == pytest.approx(disk(x) / tot, rel=1e-8)
+    assert integrate.quad(lambda x: float(O.rotation_kernel(x, u1, u2)), -1, 1)[0] == pytest.approx(1.0, rel=1e-9)
+    xs = np.linspace(-0.99, 0.99, 9)
+    np.testing.assert_allclose(O.rotation_kernel(xs, 0, 0), 2 * np.sqrt(1 - xs ** 2) / math.pi, rtol=1e-14)
+    h = 1e-6
+    np.testing.assert_allclose(O.drotation_kernel(xs, u1, u2),
+                               (O.rotation_kernel(xs + h, u1, u2) - O.rotation_kernel(xs - h, u1, u2)) / (2 * h), rtol=1e-6)
+
+
+def _eslog(n=3000):
+    return synth.eslog_grid(4340.0, 4380.0, n)
+
+
+def test_response_flat_stays_flat_and_delta_gives_kernel():
+    nu = _eslog()
+    resp = synth.Response(28.1, 16.2, 0.5367, 0.3578, 1e5, 500, 2000)
+    F = O.response(np.full(nu.size, 7.25), nu, resp)
+    np.testing.assert_allclose(F, 7.25, rtol=1e-14)
+    # a delta at j0 through rotation only: G_i = k_R(v_i - v_j0 + RV)/norm
+    j0 = 1500
+    d = np.zeros(nu.size)
+    d[j0] = 1.0
+    v = O.C_KMS * np.log(nu)
+    idx = np.arange(1000, 2000)
+    G = O.rotate(d, nu, idx, 28.1, 16.2, 0.5367, 0.3578)
+    expect = O.rotation_kernel((v[idx] - v[j0] + 28.1) / 16.2, 0.5367, 0.3578)
+    nz = expect > 0
+    ratio = G[nz] / expect[nz]
+    assert np.ptp(ratio) < 2e-3 * ratio.mean()   # one normalisation for all i (up to grid non-uniformity)
+
+
+def test_response_line_centroid_moves_by_rv():
+    nu = _eslog(6000)
+    nu0 = 4360.0
+    F0 = 1.0 - 0.5 * np.exp(-0.5 * ((nu - nu0) / 0.01) ** 2)
+    resp = synth.Response(28.1, 16.2, 0.5367, 0.3578, 1e5, 1200, 3600)
+    F = O.response(F0, nu, resp)
+    nu_out = nu[1200:1200 + 3600]
+    depth = 1.0 - F
+    centroid = np.sum(nu_out * depth) / np.sum(depth)
+    assert centroid == pytest.approx(nu0 * math.exp(-28.1 / O.C_KMS), abs=2e-4)
+
+
+def test_ip_of_gaussian_adds_variances():
+    nu = _eslog(8000)
+    v = O.C_KMS * np.log(nu)
+    vc = v[4000]
+    s0 = 3.0
+    G = np.exp(-0.5 * ((v - vc) / s0) ** 2)
+    idx = np.arange(3000, 5000)
+    F = O.instrumental(G, nu, idx, 1e5)[0]
+    b = O.ip_beta_kms(1e5)
+    s = math.sqrt(s0 ** 2 + b ** 2)
+    expect = (s0 / s) * np.exp(-0.5 * ((v[idx] - vc) / s) ** 2)
+    np.testing.assert_allclose(F, expect, rtol=2e-5, atol=1e-9)
+
+
+# ---------------------------------------------------------------- gradients
+
+def test_flux_tangents_by_central_differences():
+    wl = synth.make_config(4, "tiny")
+    th = wl.theta
+    t = O.flux_tangents(wl, th, per_layer=True)
+    steps = np.array([0.05, 1e-7, 1e-5, 1e-5, 1e-4, 1e-4])
+    for k in range(6):
+        e = np.zeros(6)
+        e[k] = steps[k]
+        fd = (O.emission_flux(wl, th + e) - O.emission_flux(wl, th - e)) / (2 * steps[k])
+        np.testing.assert_allclose(t["dF"][k], fd, rtol=2e-6, atol=1e-7 * np.abs(fd).max(), err_msg=f"param {k}")
+    # per-layer: dF/dT0 = sum_n dF/dT_n * T_n/T0
+    T = O.temperatures(wl.atmos.P_bar, th[0], th[1])
+    np.testing.assert_allclose(t["dF_dTn"].T @ (T / th[0]), t["dF"][0], rtol=1e-10)
+
+
+def test_loss_gradient_by_central_differences():
+    wl = synth.make_config(4, "tiny")
+    F_star = O.emission_flux(wl, wl.theta_star)
+    rng = np.random.default_rng(44)
+    data = F_star * (1 + 0.01 * rng.normal(size=F_star.size))
+    sig = 0.01 * F_star
+    L, g = O.loss_gradient(wl, wl.theta, data, sig)
+    for k, h in enumerate([0.02, 1e-7, 1e-5, 1e-5, 1e-4, 1e-4]):
+        e = np.zeros(6)
+        e[k] = h
+        fd = (O.gaussian_loss(O.emission_flux(wl, wl.theta + e), data, sig)
+              - O.gaussian_loss(O.emission_flux(wl, wl.theta - e), data, sig)) / (2 * h)
+        assert g[k] == pytest.approx(fd, rel=1e-5, abs=1e-8 * abs(L))
