@@ -1,0 +1,100 @@
+// Host-side internals of the exohip library (not part of the C ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/exohip.h"
+#include "exo_launch.h"
+
+namespace exo {
+
+int set_err(int code, const char* fmt, ...);
+bool fail_alloc_hook();
+
+// Grow-only device allocation.
+struct DevBuf {
+  void* p = nullptr;
+  size_t cap = 0;
+  int reserve(size_t bytes);
+  void release();
+};
+
+// All scratch of one in-flight evaluation.  One per context for the
+// synchronous API; the serving engine owns one per slot.
+struct Workspace {
+  static constexpr size_t kStageDoubles = 1 << 14;
+  DevBuf rec, rect, rec64, tau, taut, part, part_t, F0, F0bar, mid, midbar, Fup, taubar, layer,
+      col, taps, partT, partX, partR, gout, params;
+  double* h_stage = nullptr;     // pinned staging for per-call parameters
+  hipEvent_t stage_ev = nullptr; // guards h_stage reuse
+  RtArgs last_rt{};
+  hipEvent_t done_ev = nullptr;  // end of the last evaluation using this workspace
+  hipStream_t last_st = nullptr;
+  // Order this evaluation after the previous one when it runs on another stream.
+  int begin(hipStream_t st);
+  int end(hipStream_t st);
+  ~Workspace();
+  void release();
+  int stage_params(const double* host, size_t n, double* dev, hipStream_t st);
+  size_t bytes() const {
+    size_t b = 0;
+    for (const DevBuf* x : {&rec, &rect, &rec64, &tau, &taut, &part, &part_t, &F0, &F0bar, &mid,
+                            &midbar, &Fup, &taubar, &layer, &col, &taps, &partT, &partX, &partR,
+                            &gout, &params})
+      b += x->cap;
+    return b;
+  }
+};
+
+struct Species {
+  bool set = false;
+  int64_t n = 0;
+  DevBuf nu_c, S0, E_low, alpha_ref, n_texp, gamma_nat, qr;
+  bool has_gnat = false;
+  double mass = 0;
+  int qr_kind = 0, n_qr = 0;
+  double nu_lo = 0, nu_hi = 0;
+  void release();
+};
+
+struct ProfRec {
+  hipEvent_t a = nullptr, b = nullptr;
+  double evals = 0;
+};
+
+}  // namespace exo
+
+struct exo_ctx {
+  int device = 0;
+  exo::Species sp[EXO_MAX_SPECIES];
+  exo::DevBuf d_nu;
+  std::vector<double> h_nu;
+  int64_t n_nu = 0;
+  bool eslog = false;
+  double dv_kms = 0;
+  exo::Workspace ws;
+  std::mutex mu;  // serialises the synchronous API on this context
+  bool profile = false;
+  std::mutex prof_mu;
+  std::vector<exo::ProfRec> prof;
+};
+
+namespace exo {
+int voigt_launch_profiled(exo_ctx* c, const VoigtArgs& A, bool fp64, bool tan, hipStream_t st);
+int species_opacity(exo_ctx* c, Workspace& ws, const Species& sp, const double* d_T,
+                    const double* d_P, const double* d_col, int nlay, double amp_scale, bool fp64,
+                    bool tangent, const double* d_nu, int64_t ng, void* out, float* out_t,
+                    hipStream_t st);
+int validate_atmos(const exo_ctx* c, const exo_atmos* a, int64_t* gb, int64_t* gl);
+int prepare_response(const exo_ctx* c, const exo_response* r, int64_t gl, RespDev* R);
+int forward_core(exo_ctx* c, Workspace& ws, const exo_atmos* a, int64_t gb, int64_t gl, bool fp64,
+                 bool tangent, hipStream_t st);
+int apply_response(Workspace& ws, RespDev& R, const double* F0, void* out, bool out64, hipStream_t st);
+int emission_impl(exo_ctx* c, Workspace& ws, const exo_atmos* a, const exo_response* r,
+                  int precision, void* flux, hipStream_t st);
+int vjp_impl(exo_ctx* c, Workspace& ws, const exo_atmos* a, const exo_response* r, int precision,
+             const void* cot, double* grad, double* dLdT, void* flux, hipStream_t st);
+}  // namespace exo

@@ -1,0 +1,111 @@
+// Kernel argument blocks and launchers shared between the kernels and the
+// host library (internal; not part of the C ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "exo_device.h"
+
+namespace exo {
+
+constexpr int kMaxSpecies = 64;
+constexpr int kVoigtG = 2;  // grid points per thread in the FP32 Voigt sum
+
+struct LinesDev {
+  const double *nu_c, *S0, *E_low, *alpha_ref, *n_texp, *gamma_nat;
+  int64_t n;
+  double mass;
+  int qr_kind;
+  const double* qr_params;
+  int n_qr;
+};
+
+struct VoigtArgs {
+  const double* nu;   // model grid (already offset to the model range)
+  int64_t ng;
+  const double* nu_c;
+  int64_t n_lines;
+  const LineRec* rec;
+  const LineRecT* rect;
+  const LineRec64* rec64;
+  int64_t lines_per_split;
+  int ksplit;
+  int nlay;
+  float out_scale;
+  double out_scale64;
+  float* out;
+  float* out_t;
+  double* out64;
+  int64_t ld_out;
+  float2* part;
+  float2* part_t;
+  double* part64;
+};
+
+// Per-layer quantities of one atmosphere.
+struct AtmosDev {
+  int nlay, nspec, bottom;
+  const double* P;                 // [nlay] bar
+  double T0, alpha, g, mmw;
+  double cia_alpha0, cia_Tpow, cia_slope, cia_nu_c, vmr_h2;
+  double logx[kMaxSpecies];
+  double mass[kMaxSpecies];
+  // outputs
+  double *T, *dP, *lnP, *col, *cia, *dcia;   // col: [nspec][nlay]
+};
+
+// Radiative transfer on the model grid.
+struct RtArgs {
+  const double* nu;      // model grid
+  int64_t ng;
+  int nlay, nspec, bottom;
+  const double *T, *cia, *dcia;
+  double cia_slope, cia_nu_c;
+  const void* tau;       // [nspec][nlay][ng] float or double
+  const void* taut;      // tangent d tau^m / dT_n, same layout (adjoint only)
+  double* F0;            // [ng]
+  // adjoint
+  const double* F0bar;   // [ng]
+  double* Fup;           // scratch [nlay][ng]
+  double* taubar;        // [nlay][ng]
+  double* partT;         // [nblocks][nlay]
+};
+
+// Response (rotation + IP) on the model grid.
+struct RespDev {
+  int64_t dlo, nrot;     // rotation taps for d = dlo .. dlo + nrot - 1, d = i - j
+  int64_t K;             // IP taps for d' = -K .. K
+  double dv, rv, vsini, u1, u2, beta_ip;
+  double *rot, *drot_rv, *drot_vs, *ip;   // normalised taps / derivatives
+  int64_t ob, ol;        // output range on the model grid
+};
+
+hipError_t launch_line_records(const LinesDev& L, const double* T_lay, const double* P_lay,
+                               const double* col_lay, double amp_scale, int layer0, int nlay,
+                               LineRec* rec, LineRecT* rect, LineRec64* rec64, hipStream_t st);
+hipError_t launch_voigt(const VoigtArgs& A, bool fp64, bool tangent, hipStream_t st);
+hipError_t launch_hjert_f32(int64_t n, const float* x, const float* a, float* H, float* L,
+                            hipStream_t st);
+hipError_t launch_hjert_f64(int64_t n, const double* x, const double* a, double* H, hipStream_t st);
+
+hipError_t launch_atmos(const AtmosDev& A, hipStream_t st);
+hipError_t launch_rt_forward(const RtArgs& R, bool tau64, hipStream_t st);
+hipError_t launch_rt_adjoint(const RtArgs& R, bool tau64, int64_t nblocks, hipStream_t st);
+hipError_t launch_grad_x(const double* taubar, const void* tau, bool tau64, int nspec, int nlay,
+                         int64_t ng, double* partX, int64_t nblocks, hipStream_t st);
+hipError_t launch_trans2e3(int64_t n, const double* x, double* T, double* dT, hipStream_t st);
+
+hipError_t launch_taps(const RespDev& R, hipStream_t st);
+hipError_t launch_response(const RespDev& R, const double* F0, double* mid, void* out, bool out64,
+                           hipStream_t st);
+// Transpose of the response: F0bar[ng] from cot[ol]; RV / vsini partials.
+hipError_t launch_response_vjp(const RespDev& R, const double* F0, const void* cot, bool cot64,
+                               double* midbar, double* F0bar, int64_t ng, double* partR,
+                               int64_t nblocks_mid, hipStream_t st);
+hipError_t launch_cast_copy(const double* src, void* dst, bool dst64, int64_t n, hipStream_t st);
+hipError_t launch_to_double(const void* src, bool src64, double* dst, int64_t n, hipStream_t st);
+hipError_t launch_grad_final(const double* partT, int64_t nbT, const double* partX, int64_t nbX,
+                             const double* partR, int64_t nbR, const double* T, const double* lnP,
+                             int nlay, int nspec, double T0, double* out, hipStream_t st);
+
+}  // namespace exo

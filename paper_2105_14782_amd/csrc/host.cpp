@@ -1,0 +1,731 @@
+// exohip host library: context, validation, device memory, launch sequencing.
+// C ABI in include/exohip.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "../../include/exohip.h"
+#include "exo_host.h"
+#include "exo_launch.h"
+
+using namespace exo;
+
+// ---------------------------------------------------------------------------
+// Errors
+// ---------------------------------------------------------------------------
+static thread_local std::string g_err;
+
+int exo::set_err(int code, const char* fmt, ...) {
+  char buf[1024];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                 \
+  do {                                                                                \
+    hipError_t e_ = (expr);                                                           \
+    if (e_ != hipSuccess)                                                             \
+      return set_err(EXO_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));      \
+  } while (0)
+
+extern "C" const char* exo_last_error(void) { return g_err.c_str(); }
+extern "C" const char* exo_version(void) { return "exohip 0.1 (gfx950)"; }
+
+// ---------------------------------------------------------------------------
+// Device buffers
+// ---------------------------------------------------------------------------
+int exo::DevBuf::reserve(size_t bytes) {
+  if (bytes <= cap) return EXO_OK;
+  if (p) {
+    // the old buffer may still be read by queued work
+    (void)hipDeviceSynchronize();
+    (void)hipFree(p);
+    p = nullptr;
+    cap = 0;
+  }
+  size_t want = bytes + bytes / 8 + 256;
+  if (fail_alloc_hook()) return set_err(EXO_ENOMEM, "allocation of %zu bytes failed (test hook)", want);
+  hipError_t e = hipMalloc(&p, want);
+  if (e != hipSuccess) {
+    p = nullptr;
+    (void)hipGetLastError();
+    return set_err(EXO_ENOMEM, "hipMalloc(%zu) failed: %s", want, hipGetErrorString(e));
+  }
+  cap = want;
+  return EXO_OK;
+}
+
+void exo::DevBuf::release() {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+  cap = 0;
+}
+
+// EXO_TEST_FAIL_ALLOC=n makes the n-th subsequent device allocation fail.
+bool exo::fail_alloc_hook() {
+  static std::mutex mu;
+  static long countdown = -2;
+  std::lock_guard<std::mutex> g(mu);
+  if (countdown == -2) {
+    const char* s = getenv("EXO_TEST_FAIL_ALLOC");
+    countdown = s ? atol(s) : -1;
+  }
+  if (countdown < 0) return false;
+  if (countdown == 0) {
+    countdown = -1;
+    return true;
+  }
+  --countdown;
+  return false;
+}
+
+Workspace::~Workspace() { release(); }
+
+void Workspace::release() {
+  for (DevBuf* b : {&rec, &rect, &rec64, &tau, &taut, &part, &part_t, &F0, &F0bar, &mid, &midbar,
+                    &Fup, &taubar, &layer, &col, &taps, &partT, &partX, &partR, &gout, &params})
+    b->release();
+  if (h_stage) (void)hipHostFree(h_stage);
+  h_stage = nullptr;
+  if (stage_ev) (void)hipEventDestroy(stage_ev);
+  stage_ev = nullptr;
+  if (done_ev) (void)hipEventDestroy(done_ev);
+  done_ev = nullptr;
+}
+
+int Workspace::begin(hipStream_t st) {
+  if (done_ev && last_st != st) HIP_TRY(hipStreamWaitEvent(st, done_ev, 0));
+  return EXO_OK;
+}
+
+int Workspace::end(hipStream_t st) {
+  if (!done_ev) HIP_TRY(hipEventCreateWithFlags(&done_ev, hipEventDisableTiming));
+  HIP_TRY(hipEventRecord(done_ev, st));
+  last_st = st;
+  return EXO_OK;
+}
+
+// Runs f(ws, st) between ws.begin and ws.end.
+template <class F>
+static int with_ws(Workspace& ws, hipStream_t st, F&& f) {
+  int rc = ws.begin(st);
+  if (rc) return rc;
+  rc = f();
+  const int rc2 = ws.end(st);
+  return rc ? rc : rc2;
+}
+
+int Workspace::stage_params(const double* host, size_t n, double* dev, hipStream_t st) {
+  if (!h_stage) {
+    HIP_TRY(hipHostMalloc((void**)&h_stage, kStageDoubles * sizeof(double), hipHostMallocDefault));
+    HIP_TRY(hipEventCreateWithFlags(&stage_ev, hipEventDisableTiming));
+  } else {
+    HIP_TRY(hipEventSynchronize(stage_ev));
+  }
+  if (n > kStageDoubles) return set_err(EXO_EINVAL, "parameter block too large (%zu doubles)", n);
+  memcpy(h_stage, host, n * sizeof(double));
+  HIP_TRY(hipMemcpyAsync(dev, h_stage, n * sizeof(double), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipEventRecord(stage_ev, st));
+  return EXO_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Context
+// ---------------------------------------------------------------------------
+extern "C" int exo_create(int device, exo_ctx** out) {
+  if (!out) return set_err(EXO_EINVAL, "out is NULL");
+  *out = nullptr;
+  int n = 0;
+  HIP_TRY(hipGetDeviceCount(&n));
+  if (device < 0 || device >= n) return set_err(EXO_EINVAL, "device %d out of range (%d devices)", device, n);
+  HIP_TRY(hipSetDevice(device));
+  exo_ctx* c = new exo_ctx();
+  c->device = device;
+  *out = c;
+  return EXO_OK;
+}
+
+extern "C" int exo_destroy(exo_ctx* c) {
+  if (!c) return EXO_OK;
+  (void)hipSetDevice(c->device);
+  (void)hipDeviceSynchronize();
+  for (auto& s : c->sp) s.release();
+  c->d_nu.release();
+  c->ws.release();
+  for (auto& p : c->prof) {
+    (void)hipEventDestroy(p.a);
+    (void)hipEventDestroy(p.b);
+  }
+  delete c;
+  return EXO_OK;
+}
+
+void Species::release() {
+  for (DevBuf* b : {&nu_c, &S0, &E_low, &alpha_ref, &n_texp, &gamma_nat, &qr}) b->release();
+  set = false;
+  n = 0;
+}
+
+static bool finite_all(const double* a, int64_t n) {
+  for (int64_t i = 0; i < n; ++i)
+    if (!std::isfinite(a[i])) return false;
+  return true;
+}
+
+extern "C" int exo_set_lines(exo_ctx* c, int s, int64_t n, const double* nu_c, const double* S0,
+                             const double* E_low, const double* alpha_ref, const double* n_texp,
+                             const double* gamma_nat, double mass_amu, int qr_kind,
+                             const double* qr_params, int n_qr) {
+  if (!c) return set_err(EXO_EINVAL, "ctx is NULL");
+  if (s < 0 || s >= EXO_MAX_SPECIES) return set_err(EXO_EINVAL, "species slot %d out of range", s);
+  if (n < 1) return set_err(EXO_EINVAL, "n_lines must be >= 1");
+  if (!nu_c || !S0 || !E_low || !alpha_ref || !n_texp) return set_err(EXO_EINVAL, "NULL line array");
+  if (!(mass_amu > 0) || !std::isfinite(mass_amu)) return set_err(EXO_EINVAL, "mass must be > 0");
+  if (!finite_all(nu_c, n) || !finite_all(S0, n) || !finite_all(E_low, n) ||
+      !finite_all(alpha_ref, n) || !finite_all(n_texp, n) || (gamma_nat && !finite_all(gamma_nat, n)))
+    return set_err(EXO_EINVAL, "non-finite line parameter");
+  for (int64_t i = 0; i < n; ++i) {
+    if (!(nu_c[i] > 0)) return set_err(EXO_EINVAL, "line %lld: nu_c must be > 0", (long long)i);
+    if (S0[i] < 0 || E_low[i] < 0 || alpha_ref[i] < 0 || (gamma_nat && gamma_nat[i] < 0))
+      return set_err(EXO_EINVAL, "line %lld: negative strength/energy/width", (long long)i);
+  }
+  if (qr_kind == EXO_QR_POWER) {
+    if (n_qr != 1 || !qr_params || !std::isfinite(qr_params[0]))
+      return set_err(EXO_EINVAL, "EXO_QR_POWER needs one finite parameter");
+  } else if (qr_kind == EXO_QR_TABLE) {
+    if (n_qr < 4 || (n_qr & 1) || !qr_params || !finite_all(qr_params, n_qr))
+      return set_err(EXO_EINVAL, "EXO_QR_TABLE needs 2n (n >= 2) finite values");
+    const int k = n_qr / 2;
+    for (int i = 0; i < k; ++i) {
+      if (i > 0 && !(qr_params[i] > qr_params[i - 1])) return set_err(EXO_EINVAL, "Q table T nodes must ascend");
+      if (!(qr_params[k + i] > 0)) return set_err(EXO_EINVAL, "Q table values must be > 0");
+    }
+  } else {
+    return set_err(EXO_EINVAL, "unknown qr_kind %d", qr_kind);
+  }
+  HIP_TRY(hipSetDevice(c->device));
+  // sort by line centre
+  std::vector<int64_t> idx(n);
+  std::iota(idx.begin(), idx.end(), 0);
+  std::stable_sort(idx.begin(), idx.end(), [&](int64_t a, int64_t b) { return nu_c[a] < nu_c[b]; });
+  std::vector<double> tmp(n);
+  Species& sp = c->sp[s];
+  HIP_TRY(hipDeviceSynchronize());
+  sp.release();
+  auto up = [&](DevBuf& b, const double* src) -> int {
+    for (int64_t i = 0; i < n; ++i) tmp[i] = src ? src[idx[i]] : 0.0;
+    int rc = b.reserve(n * sizeof(double));
+    if (rc) return rc;
+    HIP_TRY(hipMemcpy(b.p, tmp.data(), n * sizeof(double), hipMemcpyHostToDevice));
+    return EXO_OK;
+  };
+  int rc;
+  if ((rc = up(sp.nu_c, nu_c)) || (rc = up(sp.S0, S0)) || (rc = up(sp.E_low, E_low)) ||
+      (rc = up(sp.alpha_ref, alpha_ref)) || (rc = up(sp.n_texp, n_texp))) {
+    sp.release();
+    return rc;
+  }
+  if (gamma_nat && (rc = up(sp.gamma_nat, gamma_nat))) {
+    sp.release();
+    return rc;
+  }
+  if ((rc = sp.qr.reserve(n_qr * sizeof(double)))) {
+    sp.release();
+    return rc;
+  }
+  HIP_TRY(hipMemcpy(sp.qr.p, qr_params, n_qr * sizeof(double), hipMemcpyHostToDevice));
+  sp.n = n;
+  sp.has_gnat = gamma_nat != nullptr;
+  sp.mass = mass_amu;
+  sp.qr_kind = qr_kind;
+  sp.n_qr = n_qr;
+  sp.nu_lo = tmp.empty() ? 0 : nu_c[idx.front()];
+  sp.nu_hi = nu_c[idx.back()];
+  sp.set = true;
+  return EXO_OK;
+}
+
+extern "C" int exo_set_grid(exo_ctx* c, int64_t n, const double* nu) {
+  if (!c) return set_err(EXO_EINVAL, "ctx is NULL");
+  if (n < 2 || !nu) return set_err(EXO_EINVAL, "grid needs >= 2 points");
+  if (!finite_all(nu, n)) return set_err(EXO_EINVAL, "non-finite grid value");
+  if (!(nu[0] > 0)) return set_err(EXO_EINVAL, "grid must be positive");
+  for (int64_t i = 1; i < n; ++i)
+    if (!(nu[i] > nu[i - 1])) return set_err(EXO_EINVAL, "grid must be strictly ascending (index %lld)", (long long)i);
+  HIP_TRY(hipSetDevice(c->device));
+  HIP_TRY(hipDeviceSynchronize());
+  int rc = c->d_nu.reserve(n * sizeof(double));
+  if (rc) return rc;
+  HIP_TRY(hipMemcpy(c->d_nu.p, nu, n * sizeof(double), hipMemcpyHostToDevice));
+  c->n_nu = n;
+  c->h_nu.assign(nu, nu + n);
+  // log-uniform detection
+  const double mean = std::log(nu[n - 1] / nu[0]) / (double)(n - 1);
+  double dev = 0.0;
+  for (int64_t i = 1; i < n; ++i) dev = std::max(dev, std::fabs(std::log(nu[i] / nu[i - 1]) - mean));
+  c->eslog = dev <= 1e-6 * mean + 1e-14;
+  c->dv_kms = kCkms * mean;
+  return EXO_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Profiling of the Voigt-sum launches
+// ---------------------------------------------------------------------------
+extern "C" int exo_profile_enable(exo_ctx* c, int on) {
+  if (!c) return set_err(EXO_EINVAL, "ctx is NULL");
+  (void)hipSetDevice(c->device);
+  for (auto& p : c->prof) {
+    (void)hipEventSynchronize(p.b);
+    (void)hipEventDestroy(p.a);
+    (void)hipEventDestroy(p.b);
+  }
+  c->prof.clear();
+  c->profile = on != 0;
+  return EXO_OK;
+}
+
+extern "C" int exo_profile_read(exo_ctx* c, int64_t* nl, double* ms, double* evals) {
+  if (!c) return set_err(EXO_EINVAL, "ctx is NULL");
+  HIP_TRY(hipSetDevice(c->device));
+  double tot = 0, ev = 0;
+  for (auto& p : c->prof) {
+    HIP_TRY(hipEventSynchronize(p.b));
+    float t = 0;
+    HIP_TRY(hipEventElapsedTime(&t, p.a, p.b));
+    tot += t;
+    ev += p.evals;
+  }
+  if (nl) *nl = (int64_t)c->prof.size();
+  if (ms) *ms = tot;
+  if (evals) *evals = ev;
+  return EXO_OK;
+}
+
+int exo::voigt_launch_profiled(exo_ctx* c, const VoigtArgs& A, bool fp64, bool tan, hipStream_t st) {
+  ProfRec pr{};
+  const bool prof = c && c->profile;
+  if (prof) {
+    HIP_TRY(hipEventCreate(&pr.a));
+    HIP_TRY(hipEventCreate(&pr.b));
+    HIP_TRY(hipEventRecord(pr.a, st));
+  }
+  HIP_TRY(launch_voigt(A, fp64, tan, st));
+  if (prof) {
+    HIP_TRY(hipEventRecord(pr.b, st));
+    pr.evals = (double)A.n_lines * (double)A.ng * (double)A.nlay;
+    std::lock_guard<std::mutex> g(c->prof_mu);
+    c->prof.push_back(pr);
+  }
+  return EXO_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Voigt sum of one species over a layer range into tau[(layer)][ng]
+// ---------------------------------------------------------------------------
+static LinesDev lines_dev(const Species& sp) {
+  LinesDev L;
+  L.nu_c = (const double*)sp.nu_c.p;
+  L.S0 = (const double*)sp.S0.p;
+  L.E_low = (const double*)sp.E_low.p;
+  L.alpha_ref = (const double*)sp.alpha_ref.p;
+  L.n_texp = (const double*)sp.n_texp.p;
+  L.gamma_nat = sp.has_gnat ? (const double*)sp.gamma_nat.p : nullptr;
+  L.n = sp.n;
+  L.mass = sp.mass;
+  L.qr_kind = sp.qr_kind;
+  L.qr_params = (const double*)sp.qr.p;
+  L.n_qr = sp.n_qr;
+  return L;
+}
+
+// Record-buffer budget per workspace (bytes); layers are processed in chunks
+// that fit it.
+static constexpr size_t kRecBudget = size_t(3) << 30;
+
+int exo::species_opacity(exo_ctx* c, Workspace& ws, const Species& sp, const double* d_T,
+                         const double* d_P, const double* d_col, int nlay, double amp_scale,
+                         bool fp64, bool tangent, const double* d_nu, int64_t ng, void* out,
+                         float* out_t, hipStream_t st) {
+  const LinesDev L = lines_dev(sp);
+  const size_t per_layer = (size_t)sp.n * (fp64 ? sizeof(LineRec64) : sizeof(LineRec) + (tangent ? sizeof(LineRecT) : 0));
+  int nlc = (int)std::max<size_t>(1, std::min<size_t>((size_t)nlay, kRecBudget / per_layer));
+  int rc;
+  if (fp64) {
+    if ((rc = ws.rec64.reserve((size_t)nlc * sp.n * sizeof(LineRec64)))) return rc;
+  } else {
+    if ((rc = ws.rec.reserve((size_t)nlc * sp.n * sizeof(LineRec)))) return rc;
+    if (tangent && (rc = ws.rect.reserve((size_t)nlc * sp.n * sizeof(LineRecT)))) return rc;
+  }
+  const int64_t G = fp64 ? 1 : kVoigtG;
+  for (int l0 = 0; l0 < nlay; l0 += nlc) {
+    const int nl = std::min(nlc, nlay - l0);
+    HIP_TRY(launch_line_records(L, d_T, d_P, d_col, amp_scale, l0, nl,
+                                fp64 ? nullptr : (LineRec*)ws.rec.p,
+                                (!fp64 && tangent) ? (LineRecT*)ws.rect.p : nullptr,
+                                fp64 ? (LineRec64*)ws.rec64.p : nullptr, st));
+    VoigtArgs A{};
+    A.nu = d_nu;
+    A.ng = ng;
+    A.nu_c = L.nu_c;
+    A.n_lines = sp.n;
+    A.rec = (const LineRec*)ws.rec.p;
+    A.rect = (const LineRecT*)ws.rect.p;
+    A.rec64 = (const LineRec64*)ws.rec64.p;
+    A.nlay = nl;
+    A.out_scale = (float)(1.0 / amp_scale);
+    A.out_scale64 = 1.0 / amp_scale;
+    A.ld_out = ng;
+    if (fp64) A.out64 = (double*)out + (int64_t)l0 * ng;
+    else {
+      A.out = (float*)out + (int64_t)l0 * ng;
+      A.out_t = tangent ? out_t + (int64_t)l0 * ng : nullptr;
+    }
+    // split over lines when the grid x layer tiles cannot fill the device
+    const int64_t tiles = (ng + 256 * G - 1) / (256 * G);
+    const int64_t blocks = tiles * nl;
+    int64_t ks = 1;
+    if (blocks < 2048) ks = std::min<int64_t>((2048 + blocks - 1) / blocks, std::max<int64_t>(1, sp.n / 64));
+    int64_t lps = (sp.n + ks - 1) / ks;
+    lps = ((lps + 31) / 32) * 32;
+    ks = (sp.n + lps - 1) / lps;
+    A.lines_per_split = lps;
+    A.ksplit = (int)ks;
+    if (ks > 1) {
+      const size_t pb = (size_t)ks * nl * ng * (fp64 ? sizeof(double) : sizeof(float2));
+      if ((rc = ws.part.reserve(pb))) return rc;
+      if (!fp64 && tangent && (rc = ws.part_t.reserve(pb))) return rc;
+      A.part = (float2*)ws.part.p;
+      A.part_t = (float2*)ws.part_t.p;
+      A.part64 = (double*)ws.part.p;
+    }
+    if ((rc = voigt_launch_profiled(c, A, fp64, tangent, st))) return rc;
+  }
+  return EXO_OK;
+}
+
+extern "C" int exo_cross_section(exo_ctx* c, int s, double T, double P, int precision, void* sigma,
+                                 void* stream) {
+  if (!c) return set_err(EXO_EINVAL, "ctx is NULL");
+  if (s < 0 || s >= EXO_MAX_SPECIES || !c->sp[s].set) return set_err(EXO_ENOTSET, "species %d not set", s);
+  if (c->n_nu < 2) return set_err(EXO_ENOTSET, "grid not set");
+  if (!(T > 0) || !std::isfinite(T) || !(P >= 0) || !std::isfinite(P))
+    return set_err(EXO_EINVAL, "need T > 0 and P >= 0");
+  if (precision != EXO_FP32_KAHAN && precision != EXO_FP64) return set_err(EXO_EINVAL, "bad precision");
+  if (!sigma) return set_err(EXO_EINVAL, "sigma_dev is NULL");
+  HIP_TRY(hipSetDevice(c->device));
+  hipStream_t st = (hipStream_t)stream;
+  std::lock_guard<std::mutex> g(c->mu);
+  Workspace& ws = c->ws;
+  int rc;
+  if ((rc = ws.params.reserve(16 * sizeof(double)))) return rc;
+  double hp[2] = {T, P};
+  double* dp = (double*)ws.params.p;
+  const bool fp64 = precision == EXO_FP64;
+  // FP32 records carry the amplitude times 2^64 so that the small strengths
+  // of single-molecule cross-sections stay far from the FP32 subnormal range.
+  const double scale = fp64 ? 1.0 : std::ldexp(1.0, 64);
+  return with_ws(ws, st, [&] {
+    int r = ws.stage_params(hp, 2, dp, st);
+    if (r) return r;
+    return species_opacity(c, ws, c->sp[s], dp, dp + 1, nullptr, 1, scale, fp64, false,
+                           (const double*)c->d_nu.p, c->n_nu, sigma, nullptr, st);
+  });
+}
+
+// ---------------------------------------------------------------------------
+// Emission
+// ---------------------------------------------------------------------------
+int exo::validate_atmos(const exo_ctx* c, const exo_atmos* a, int64_t* gb, int64_t* gl) {
+  if (!a) return set_err(EXO_EINVAL, "atmos is NULL");
+  if (c->n_nu < 2) return set_err(EXO_ENOTSET, "grid not set");
+  if (a->n_layers < 2 || a->n_layers > 100000 || !a->P_bar) return set_err(EXO_EINVAL, "need >= 2 layers");
+  for (int i = 0; i < a->n_layers; ++i) {
+    if (!(a->P_bar[i] > 0) || !std::isfinite(a->P_bar[i])) return set_err(EXO_EINVAL, "P must be > 0");
+    if (i > 0 && !(a->P_bar[i] > a->P_bar[i - 1])) return set_err(EXO_EINVAL, "P must ascend (top -> bottom)");
+  }
+  if (!(a->T0_K > 0) || !std::isfinite(a->T0_K) || !std::isfinite(a->alpha))
+    return set_err(EXO_EINVAL, "bad T0/alpha");
+  if (a->n_species < 1 || a->n_species > EXO_MAX_SPECIES || !a->species || !a->log10_mmr)
+    return set_err(EXO_EINVAL, "bad species list");
+  for (int m = 0; m < a->n_species; ++m) {
+    const int s = a->species[m];
+    if (s < 0 || s >= EXO_MAX_SPECIES || !c->sp[s].set) return set_err(EXO_ENOTSET, "species slot %d not set", s);
+    if (!std::isfinite(a->log10_mmr[m]) || a->log10_mmr[m] > 0) return set_err(EXO_EINVAL, "log10_mmr must be finite and <= 0");
+  }
+  if (!(a->g_cgs > 0) || !(a->mmw > 0)) return set_err(EXO_EINVAL, "need g > 0 and mmw > 0");
+  if (!std::isfinite(a->cia_alpha0) || a->cia_alpha0 < 0 || !std::isfinite(a->cia_Tpow) ||
+      !std::isfinite(a->cia_slope) || !std::isfinite(a->cia_nu_c) || !(a->vmr_h2 >= 0))
+    return set_err(EXO_EINVAL, "bad CIA parameters");
+  if (a->bottom != EXO_FB_PLANCK_BOTTOM && a->bottom != EXO_FB_ZERO) return set_err(EXO_EINVAL, "bad bottom");
+  const double Tmin = std::min(a->T0_K * std::pow(a->P_bar[0], a->alpha),
+                               a->T0_K * std::pow(a->P_bar[a->n_layers - 1], a->alpha));
+  if (!(Tmin > 1.0) || !std::isfinite(Tmin)) return set_err(EXO_EINVAL, "layer temperatures must exceed 1 K");
+  int64_t b = a->grid_begin, l = a->grid_len;
+  if (l == 0) {
+    if (b != 0) return set_err(EXO_EINVAL, "grid_len 0 requires grid_begin 0");
+    l = c->n_nu;
+  }
+  if (b < 0 || l < 2 || b + l > c->n_nu) return set_err(EXO_EINVAL, "model grid range outside the grid");
+  *gb = b;
+  *gl = l;
+  return EXO_OK;
+}
+
+int exo::prepare_response(const exo_ctx* c, const exo_response* r, int64_t gl, RespDev* R) {
+  if (!c->eslog) return set_err(EXO_EINVAL, "the response needs a log-uniform grid");
+  if (!std::isfinite(r->rv_kms) || !std::isfinite(r->vsini_kms) || !std::isfinite(r->u1) ||
+      !std::isfinite(r->u2) || !(r->R_inst > 0))
+    return set_err(EXO_EINVAL, "bad response parameters");
+  const double dv = c->dv_kms;
+  if (!(r->vsini_kms >= 2.0 * dv)) return set_err(EXO_EINVAL, "vsini must span at least two grid spacings");
+  if (1.0 - r->u1 / 3.0 - r->u2 / 6.0 <= 0) return set_err(EXO_EINVAL, "limb darkening gives a non-positive disk flux");
+  const int64_t dmin = (int64_t)std::ceil((-r->vsini_kms - r->rv_kms) / dv) - 1;
+  const int64_t dmax = (int64_t)std::floor((r->vsini_kms - r->rv_kms) / dv) + 1;
+  R->dlo = dmin;
+  R->nrot = dmax - dmin + 1;
+  R->beta_ip = kCkms / (2.0 * std::sqrt(2.0 * std::log(2.0)) * r->R_inst);
+  R->K = (int64_t)std::floor(6.0 * R->beta_ip / dv);
+  R->dv = dv;
+  R->rv = r->rv_kms;
+  R->vsini = r->vsini_kms;
+  R->u1 = r->u1;
+  R->u2 = r->u2;
+  R->ob = r->out_begin;
+  R->ol = r->out_len;
+  if (r->out_len < 1) return set_err(EXO_EINVAL, "out_len must be >= 1");
+  const int64_t imin = r->out_begin - R->K, imax = r->out_begin + r->out_len - 1 + R->K;
+  if (imin - dmax < 0 || imax - dmin > gl - 1)
+    return set_err(EXO_EINVAL,
+                   "output range [%lld, %lld) needs model points [%lld, %lld] outside [0, %lld)",
+                   (long long)r->out_begin, (long long)(r->out_begin + r->out_len),
+                   (long long)(imin - dmax), (long long)(imax - dmin), (long long)gl);
+  return EXO_OK;
+}
+
+// Forward model into ws.tau (and ws.taut), then F0 into ws.F0.
+int exo::forward_core(exo_ctx* c, Workspace& ws, const exo_atmos* a, int64_t gb, int64_t gl,
+                      bool fp64, bool tangent, hipStream_t st) {
+  const int NL = a->n_layers, M = a->n_species;
+  int rc;
+  // parameter block: P
+  if ((rc = ws.params.reserve((size_t)NL * sizeof(double)))) return rc;
+  if ((rc = ws.stage_params(a->P_bar, NL, (double*)ws.params.p, st))) return rc;
+  if ((rc = ws.layer.reserve((size_t)6 * NL * sizeof(double)))) return rc;
+  if ((rc = ws.col.reserve((size_t)M * NL * sizeof(double)))) return rc;
+  double* lay = (double*)ws.layer.p;
+  AtmosDev A{};
+  A.nlay = NL;
+  A.nspec = M;
+  A.bottom = a->bottom;
+  A.P = (const double*)ws.params.p;
+  A.T0 = a->T0_K;
+  A.alpha = a->alpha;
+  A.g = a->g_cgs;
+  A.mmw = a->mmw;
+  A.cia_alpha0 = a->cia_alpha0;
+  A.cia_Tpow = a->cia_Tpow;
+  A.cia_slope = a->cia_slope;
+  A.cia_nu_c = a->cia_nu_c;
+  A.vmr_h2 = a->vmr_h2;
+  for (int m = 0; m < M; ++m) {
+    A.logx[m] = a->log10_mmr[m];
+    A.mass[m] = c->sp[a->species[m]].mass;
+  }
+  A.T = lay;
+  A.dP = lay + NL;
+  A.lnP = lay + 2 * NL;
+  A.cia = lay + 3 * NL;
+  A.dcia = lay + 4 * NL;
+  A.col = (double*)ws.col.p;
+  HIP_TRY(launch_atmos(A, st));
+
+  const size_t esz = fp64 ? sizeof(double) : sizeof(float);
+  if ((rc = ws.tau.reserve((size_t)M * NL * gl * esz))) return rc;
+  if (tangent && (rc = ws.taut.reserve((size_t)M * NL * gl * sizeof(float)))) return rc;
+  const double* d_nu = (const double*)c->d_nu.p + gb;
+  for (int m = 0; m < M; ++m) {
+    const Species& sp = c->sp[a->species[m]];
+    char* out = (char*)ws.tau.p + (size_t)m * NL * gl * esz;
+    float* out_t = tangent ? (float*)ws.taut.p + (size_t)m * NL * gl : nullptr;
+    if ((rc = species_opacity(c, ws, sp, A.T, A.P, A.col + (size_t)m * NL, NL, 1.0, fp64, tangent,
+                              d_nu, gl, out, out_t, st)))
+      return rc;
+  }
+  if ((rc = ws.F0.reserve((size_t)gl * sizeof(double)))) return rc;
+  RtArgs R{};
+  R.nu = d_nu;
+  R.ng = gl;
+  R.nlay = NL;
+  R.nspec = M;
+  R.bottom = a->bottom;
+  R.T = A.T;
+  R.cia = A.cia;
+  R.dcia = A.dcia;
+  R.cia_slope = a->cia_slope;
+  R.cia_nu_c = a->cia_nu_c;
+  R.tau = ws.tau.p;
+  R.taut = ws.taut.p;
+  R.F0 = (double*)ws.F0.p;
+  HIP_TRY(launch_rt_forward(R, fp64, st));
+  ws.last_rt = R;
+  return EXO_OK;
+}
+
+int exo::apply_response(Workspace& ws, RespDev& R, const double* F0, void* out, bool out64,
+                        hipStream_t st) {
+  int rc;
+  if ((rc = ws.taps.reserve((size_t)(3 * R.nrot + 2 * R.K + 1) * sizeof(double)))) return rc;
+  double* t = (double*)ws.taps.p;
+  R.rot = t;
+  R.drot_rv = t + R.nrot;
+  R.drot_vs = t + 2 * R.nrot;
+  R.ip = t + 3 * R.nrot;
+  HIP_TRY(launch_taps(R, st));
+  if (!out) return EXO_OK;  // taps only (the adjoint needs them without a forward output)
+  if ((rc = ws.mid.reserve((size_t)(R.ol + 2 * R.K) * sizeof(double)))) return rc;
+  HIP_TRY(launch_response(R, F0, (double*)ws.mid.p, out, out64, st));
+  return EXO_OK;
+}
+
+int exo::emission_impl(exo_ctx* c, Workspace& ws, const exo_atmos* a, const exo_response* r,
+                       int precision, void* flux, hipStream_t st) {
+  int64_t gb, gl;
+  int rc;
+  if ((rc = validate_atmos(c, a, &gb, &gl))) return rc;
+  if (precision != EXO_FP32_KAHAN && precision != EXO_FP64) return set_err(EXO_EINVAL, "bad precision");
+  if (!flux) return set_err(EXO_EINVAL, "flux_dev is NULL");
+  RespDev R{};
+  if (r && (rc = prepare_response(c, r, gl, &R))) return rc;
+  const bool fp64 = precision == EXO_FP64;
+  if ((rc = forward_core(c, ws, a, gb, gl, fp64, false, st))) return rc;
+  if (r) return apply_response(ws, R, (const double*)ws.F0.p, flux, fp64, st);
+  HIP_TRY(launch_cast_copy((const double*)ws.F0.p, flux, fp64, gl, st));
+  return EXO_OK;
+}
+
+extern "C" int exo_emission_flux(exo_ctx* c, const exo_atmos* a, const exo_response* r, int precision,
+                                 void* flux, void* stream) {
+  if (!c) return set_err(EXO_EINVAL, "ctx is NULL");
+  HIP_TRY(hipSetDevice(c->device));
+  std::lock_guard<std::mutex> g(c->mu);
+  hipStream_t st = (hipStream_t)stream;
+  return with_ws(c->ws, st, [&] { return emission_impl(c, c->ws, a, r, precision, flux, st); });
+}
+
+int exo::vjp_impl(exo_ctx* c, Workspace& ws, const exo_atmos* a, const exo_response* r,
+                  int precision, const void* cot, double* grad, double* dLdT, void* flux,
+                  hipStream_t st) {
+  int64_t gb, gl;
+  int rc;
+  if ((rc = validate_atmos(c, a, &gb, &gl))) return rc;
+  if (precision != EXO_FP32_KAHAN)
+    return set_err(EXO_EINVAL, "flux_vjp is provided for EXO_FP32_KAHAN");
+  if (!cot || !grad) return set_err(EXO_EINVAL, "cot_dev / grad_host is NULL");
+  RespDev R{};
+  if (r && (rc = prepare_response(c, r, gl, &R))) return rc;
+  const int NL = a->n_layers, M = a->n_species;
+  if ((rc = forward_core(c, ws, a, gb, gl, false, true, st))) return rc;
+  const double* F0 = (const double*)ws.F0.p;
+  const int64_t nbg = (gl + 255) / 256;
+  if ((rc = ws.F0bar.reserve((size_t)gl * sizeof(double)))) return rc;
+  double* F0bar = (double*)ws.F0bar.p;
+  int64_t nbR = 0;
+  if (r) {
+    if ((rc = apply_response(ws, R, F0, flux, false, st))) return rc;
+    const int64_t nmid = R.ol + 2 * R.K;
+    nbR = (nmid + 255) / 256;
+    if ((rc = ws.midbar.reserve((size_t)nmid * sizeof(double)))) return rc;
+    if ((rc = ws.partR.reserve((size_t)2 * nbR * sizeof(double)))) return rc;
+    HIP_TRY(launch_response_vjp(R, F0, cot, false, (double*)ws.midbar.p, F0bar, gl,
+                                (double*)ws.partR.p, nbR, st));
+  } else {
+    if (flux) HIP_TRY(launch_cast_copy(F0, flux, false, gl, st));
+    HIP_TRY(launch_to_double(cot, false, F0bar, gl, st));
+  }
+  if ((rc = ws.Fup.reserve((size_t)NL * gl * sizeof(double)))) return rc;
+  if ((rc = ws.taubar.reserve((size_t)NL * gl * sizeof(double)))) return rc;
+  if ((rc = ws.partT.reserve((size_t)nbg * NL * sizeof(double)))) return rc;
+  if ((rc = ws.partX.reserve((size_t)nbg * M * sizeof(double)))) return rc;
+  if ((rc = ws.gout.reserve((size_t)(4 + M + NL) * sizeof(double)))) return rc;
+  RtArgs Rt = ws.last_rt;
+  Rt.F0bar = F0bar;
+  Rt.Fup = (double*)ws.Fup.p;
+  Rt.taubar = (double*)ws.taubar.p;
+  Rt.partT = (double*)ws.partT.p;
+  HIP_TRY(launch_rt_adjoint(Rt, false, nbg, st));
+  HIP_TRY(launch_grad_x(Rt.taubar, ws.tau.p, false, M, NL, gl, (double*)ws.partX.p, nbg, st));
+  const double* lay = (const double*)ws.layer.p;
+  HIP_TRY(launch_grad_final(Rt.partT, nbg, (const double*)ws.partX.p, nbg, (const double*)ws.partR.p,
+                            nbR, lay, lay + 2 * NL, NL, M, a->T0_K, (double*)ws.gout.p, st));
+  std::vector<double> h(4 + M + NL);
+  HIP_TRY(hipMemcpyAsync(h.data(), ws.gout.p, h.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  for (int k = 0; k < 2 + M + 2; ++k) grad[k] = h[k];
+  if (dLdT)
+    for (int n = 0; n < NL; ++n) dLdT[n] = h[4 + M + n];
+  return EXO_OK;
+}
+
+extern "C" int exo_flux_vjp(exo_ctx* c, const exo_atmos* a, const exo_response* r, int precision,
+                            const void* cot, double* grad, double* dLdT, void* flux, void* stream) {
+  if (!c) return set_err(EXO_EINVAL, "ctx is NULL");
+  HIP_TRY(hipSetDevice(c->device));
+  std::lock_guard<std::mutex> g(c->mu);
+  hipStream_t st = (hipStream_t)stream;
+  return with_ws(c->ws, st, [&] { return vjp_impl(c, c->ws, a, r, precision, cot, grad, dLdT, flux, st); });
+}
+
+extern "C" int exo_broaden(exo_ctx* c, int64_t gb, int64_t gl, const exo_response* r,
+                           const void* F0, void* out, void* stream) {
+  if (!c) return set_err(EXO_EINVAL, "ctx is NULL");
+  if (c->n_nu < 2) return set_err(EXO_ENOTSET, "grid not set");
+  if (!r || !F0 || !out) return set_err(EXO_EINVAL, "NULL argument");
+  if (gl == 0) {
+    if (gb != 0) return set_err(EXO_EINVAL, "grid_len 0 requires grid_begin 0");
+    gl = c->n_nu;
+  }
+  if (gb < 0 || gl < 2 || gb + gl > c->n_nu) return set_err(EXO_EINVAL, "grid range outside the grid");
+  HIP_TRY(hipSetDevice(c->device));
+  std::lock_guard<std::mutex> g(c->mu);
+  RespDev R{};
+  int rc;
+  if ((rc = prepare_response(c, r, gl, &R))) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  return with_ws(c->ws, st, [&] { return apply_response(c->ws, R, (const double*)F0, out, true, st); });
+}
+
+// ---------------------------------------------------------------------------
+// Diagnostics
+// ---------------------------------------------------------------------------
+extern "C" int exo_hjert_f32(int64_t n, const float* x, const float* a, float* H, float* L, void* stream) {
+  if (n < 0 || (n > 0 && (!x || !a || !H))) return set_err(EXO_EINVAL, "bad arguments");
+  if (n == 0) return EXO_OK;
+  HIP_TRY(launch_hjert_f32(n, x, a, H, L, (hipStream_t)stream));
+  return EXO_OK;
+}
+
+extern "C" int exo_hjert_f64(int64_t n, const double* x, const double* a, double* H, void* stream) {
+  if (n < 0 || (n > 0 && (!x || !a || !H))) return set_err(EXO_EINVAL, "bad arguments");
+  if (n == 0) return EXO_OK;
+  HIP_TRY(launch_hjert_f64(n, x, a, H, (hipStream_t)stream));
+  return EXO_OK;
+}
+
+extern "C" int exo_trans2e3(int64_t n, const double* x, double* T, double* dT, void* stream) {
+  if (n < 0 || (n > 0 && (!x || !T))) return set_err(EXO_EINVAL, "bad arguments");
+  if (n == 0) return EXO_OK;
+  HIP_TRY(launch_trans2e3(n, x, T, dT, (hipStream_t)stream));
+  return EXO_OK;
+}

@@ -1,0 +1,389 @@
+// Line-parameter precompute and tiled Voigt sums (direct LPF, Sec. 2.1.1).
+#include "exo_device.h"
+#include "exo_launch.h"
+
+namespace exo {
+
+// ---------------------------------------------------------------------------
+// Line state at one layer (Sec. 2.2 Eq. Slog, Eq. thermal, Eq. gammaexomol,
+// Eq. naturalgamma, Sec. 2.3 partition function), FP64.
+// ---------------------------------------------------------------------------
+__device__ inline void qr_eval(int kind, const double* __restrict__ p, int nq, double T,
+                               double* qr, double* dlnqr) {
+  if (kind == 0) {
+    *qr = pow(T / kTref, p[0]);
+    *dlnqr = p[0] / T;
+    return;
+  }
+  const int n = nq / 2;
+  const double* tn = p;
+  const double* qn = p + n;
+  auto interp = [&](double t, double* slope) {
+    int i = 0;
+    if (t <= tn[0]) i = 0;
+    else if (t >= tn[n - 1]) i = n - 2;
+    else {
+      int lo = 0, hi = n - 1;
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (tn[mid] <= t) lo = mid; else hi = mid;
+      }
+      i = lo;
+    }
+    const double s = (qn[i + 1] - qn[i]) / (tn[i + 1] - tn[i]);
+    if (slope) *slope = s;
+    // constant extrapolation outside the table, like np.interp
+    if (t <= tn[0]) { if (slope) *slope = 0.0; return qn[0]; }
+    if (t >= tn[n - 1]) { if (slope) *slope = 0.0; return qn[n - 1]; }
+    return qn[i] + s * (t - tn[i]);
+  };
+  double s;
+  const double qT = interp(T, &s);
+  const double q0 = interp(kTref, nullptr);
+  *qr = qT / q0;
+  *dlnqr = s / qT;
+}
+
+struct LineState {
+  double S, beta, gam, dlnS, dbeta, dgam;
+};
+
+// Largest FP32 line amplitude (see k_line_records).
+constexpr double kAmpMax = 1e25;
+
+__device__ inline LineState line_state(const LinesDev& L, int64_t l, double T, double P) {
+  LineState s;
+  const double nu = L.nu_c[l];
+  double qr, dlnqr;
+  qr_eval(L.qr_kind, L.qr_params, L.n_qr, T, &qr, &dlnqr);
+  const double E = L.E_low[l];
+  const double eT = exp(-kC2 * nu / T), eR = exp(-kC2 * nu / kTref);
+  s.S = L.S0[l] / qr * exp(-kC2 * E * (1.0 / T - 1.0 / kTref)) * (1.0 - eT) / (1.0 - eR);
+  s.dlnS = -dlnqr + kC2 * E / (T * T) - (kC2 * nu / (T * T)) * eT / (1.0 - eT);
+  s.beta = sqrt(kKB * T / (L.mass * kMU)) * nu / kC;
+  s.dbeta = s.beta / (2.0 * T);
+  const double n = L.n_texp[l];
+  const double gp = L.alpha_ref[l] * pow(T / kTref, -n) * P;
+  s.gam = gp + (L.gamma_nat ? L.gamma_nat[l] : 0.0);
+  s.dgam = -n * gp / T;
+  return s;
+}
+
+// grid: x over lines, y over layers of the chunk.  col == nullptr: column
+// factor 1 (single-layer cross-section).
+__global__ __launch_bounds__(256) void k_line_records(LinesDev L, const double* __restrict__ T_lay,
+                                                      const double* __restrict__ P_lay,
+                                                      const double* __restrict__ col_lay,
+                                                      double amp_scale, int layer0,
+                                                      LineRec* __restrict__ rec,
+                                                      LineRecT* __restrict__ rect,
+                                                      LineRec64* __restrict__ rec64) {
+  const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= L.n) return;
+  const int y = blockIdx.y;
+  const int n = layer0 + y;
+  const double T = T_lay[n], P = P_lay[n];
+  const double col = col_lay ? col_lay[n] : 1.0;
+  const LineState s = line_state(L, l, T, P);
+  double A = s.S * col * amp_scale;
+  double dlnA = s.dlnS;
+  const int64_t o = (int64_t)y * L.n + l;
+  if (rec64) {
+    LineRec64 r;
+    r.A = A;
+    r.beta = s.beta;
+    r.gam = s.gam;
+    r.erfcxa = erfcx(s.gam / (kSqrt2 * s.beta));
+    rec64[o] = r;
+    return;
+  }
+  // FP32 range guard: an amplitude above kAmpMax makes every grid point of
+  // the window optically thick (dtau >> 700, T = 0) whether or not it is
+  // clipped, so clipping it changes no flux; it keeps FP32 sums finite.
+  if (A > kAmpMax) {
+    A = kAmpMax;
+    dlnA = 0.0;
+  }
+  make_line_record(A, s.beta, s.gam, T, dlnA, s.dbeta, s.dgam, rec + o, rect ? rect + o : nullptr);
+}
+
+// ---------------------------------------------------------------------------
+// FP32 Voigt sum with compensated accumulation.
+//
+// Block = 256 threads = 4 waves; thread (wave w, lane) owns grid points
+// j = tile0 + (w*G + g)*64 + lane, g < G.  All lanes walk the same line
+// sequence, so line records are wave-uniform (scalar loads).  The offset
+// nu_j - nu_l is one FP64 subtraction per pair, rounded once to FP32: an
+// FP32 offset would carry an absolute error of ulp(nu) ~ 5e-4 cm^-1, a few
+// percent of a Doppler width.  Contributions of a block of
+// kChunk lines are summed in plain FP32, and every block sum enters a
+// Neumaier-compensated accumulator.
+// ---------------------------------------------------------------------------
+constexpr int kChunk = 32;
+
+__device__ inline void neumaier(float& s, float& c, float v) {
+  const float t = s + v;
+  if (fabsf(s) >= fabsf(v)) c += (s - t) + v;
+  else c += (v - t) + s;
+  s = t;
+}
+
+// Core branch of hjert for one pair, kept out of line: it is taken by ~1% of
+// pairs and inlining it per grid-point slot would bloat the hot loop.
+__device__ __attribute__((noinline)) float core_value(float d, float winv, float a, float erfcxa,
+                                                      float acore) {
+  return acore * hjert_core_f32(d * winv, a, erfcxa, nullptr);
+}
+
+__device__ __attribute__((noinline)) float2 core_value_tan(float d, float winv, float a,
+                                                           float erfcxa, float acore, float kA,
+                                                           float kw, float da) {
+  const float x = d * winv;
+  float L;
+  const float H = hjert_core_f32(x, a, erfcxa, &L);
+  // custom derivatives of Sec. 2.1.1: dH/dx = 2aL - 2xH, dH/da = 2xL + 2aH - 2/sqrt(pi)
+  const float Hx = 2.0f * (a * L - x * H);
+  const float Ha = 2.0f * (x * L + a * H) - 1.1283791670955126f;
+  return make_float2(acore * H, acore * (kA * H + Hx * x * kw + Ha * da));
+}
+
+template <bool TAN, int G>
+__global__ __launch_bounds__(256) void k_voigt_f32(VoigtArgs A) {
+  const int y = blockIdx.y;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t tile0 = (int64_t)blockIdx.x * (256 * G);
+  const double* __restrict__ nu = A.nu;
+  double nuj[G];
+  int64_t jj[G];
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+    const int64_t j = tile0 + (int64_t)(w * G + g) * 64 + lane;
+    jj[g] = j;
+    nuj[g] = nu[j < A.ng ? j : A.ng - 1];
+  }
+  const int64_t lb = (int64_t)blockIdx.z * A.lines_per_split;
+  const int64_t le = lb + A.lines_per_split < A.n_lines ? lb + A.lines_per_split : A.n_lines;
+  const LineRec* __restrict__ R = A.rec + (int64_t)y * A.n_lines;
+  const LineRecT* __restrict__ RT = TAN ? A.rect + (int64_t)y * A.n_lines : nullptr;
+  const double* __restrict__ nuc = A.nu_c;
+
+  float s[G], c[G], ts[G], tc[G];
+#pragma unroll
+  for (int g = 0; g < G; ++g) s[g] = c[g] = ts[g] = tc[g] = 0.f;
+
+  for (int64_t l0 = lb; l0 < le; l0 += kChunk) {
+    const int64_t l1 = l0 + kChunk < le ? l0 + kChunk : le;
+    float blk[G], tblk[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) blk[g] = tblk[g] = 0.f;
+#pragma unroll 2
+    for (int64_t l = l0; l < l1; ++l) {
+      const LineRec q = R[l];
+      const double nul = nuc[l];
+      LineRecT qt;
+      if (TAN) qt = RT[l];
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        const float d = (float)(nuj[g] - nul);  // FP64 offset, rounded once
+        const float D = fmaf(d, d, q.gam2);
+        const float r = __builtin_amdgcn_rcpf(D);
+        float h = fmaf(q.e[6], r, q.e[5]);
+        h = fmaf(h, r, q.e[4]);
+        h = fmaf(h, r, q.e[3]);
+        h = fmaf(h, r, q.e[2]);
+        h = fmaf(h, r, q.e[1]);
+        h = fmaf(h, r, q.e[0]);
+        float f = h * r;
+        float ft = 0.f;
+        if (TAN) {
+          float ht = fmaf(qt.t[7], r, qt.t[6]);
+          ht = fmaf(ht, r, qt.t[5]);
+          ht = fmaf(ht, r, qt.t[4]);
+          ht = fmaf(ht, r, qt.t[3]);
+          ht = fmaf(ht, r, qt.t[2]);
+          ht = fmaf(ht, r, qt.t[1]);
+          ht = fmaf(ht, r, qt.t[0]);
+          ft = ht * r;
+        }
+        if (D < q.thr) {  // x^2 + a^2 < 111: Algorithm-916 series
+          if (TAN) {
+            const float2 v = core_value_tan(d, q.winv, q.a, q.erfcxa, q.acore, qt.kA, qt.kw, qt.da);
+            f = v.x;
+            ft = v.y;
+          } else {
+            f = core_value(d, q.winv, q.a, q.erfcxa, q.acore);
+          }
+        }
+        blk[g] += f;
+        if (TAN) tblk[g] += ft;
+      }
+    }
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      neumaier(s[g], c[g], blk[g]);
+      if (TAN) neumaier(ts[g], tc[g], tblk[g]);
+    }
+  }
+
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+    const int64_t j = jj[g];
+    if (j >= A.ng) continue;
+    const int64_t o = (int64_t)y * A.ld_out + j;
+    if (A.ksplit == 1) {
+      A.out[o] = (s[g] + c[g]) * A.out_scale;
+      if (TAN) A.out_t[o] = (ts[g] + tc[g]) * A.out_scale;
+    } else {
+      const int64_t p = ((int64_t)blockIdx.z * A.nlay + y) * A.ng + j;
+      A.part[p] = make_float2(s[g], c[g]);
+      if (TAN) A.part_t[p] = make_float2(ts[g], tc[g]);
+    }
+  }
+}
+
+// Fixed-order combine of split-K partials.
+template <bool TAN>
+__global__ __launch_bounds__(256) void k_voigt_combine(VoigtArgs A) {
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int y = blockIdx.y;
+  if (j >= A.ng) return;
+  float s = 0.f, c = 0.f, ts = 0.f, tc = 0.f;
+  for (int z = 0; z < A.ksplit; ++z) {
+    const int64_t p = ((int64_t)z * A.nlay + y) * A.ng + j;
+    const float2 v = A.part[p];
+    neumaier(s, c, v.x);
+    c += v.y;
+    if (TAN) {
+      const float2 t = A.part_t[p];
+      neumaier(ts, tc, t.x);
+      tc += t.y;
+    }
+  }
+  const int64_t o = (int64_t)y * A.ld_out + j;
+  A.out[o] = (s + c) * A.out_scale;
+  if (TAN) A.out_t[o] = (ts + tc) * A.out_scale;
+}
+
+// ---------------------------------------------------------------------------
+// The plain FP64 form: per pair x = dnu/(sqrt2 beta), a = gamma/(sqrt2 beta),
+// H from hjert_f64, contribution A/(sqrt(2 pi) beta) H; plain accumulation.
+// Same thread-to-grid mapping as the FP32 kernel (G = 1).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_voigt_f64(VoigtArgs A) {
+  const int y = blockIdx.y;
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const double nuj = A.nu[j < A.ng ? j : A.ng - 1];
+  const int64_t lb = (int64_t)blockIdx.z * A.lines_per_split;
+  const int64_t le = lb + A.lines_per_split < A.n_lines ? lb + A.lines_per_split : A.n_lines;
+  const LineRec64* __restrict__ R = A.rec64 + (int64_t)y * A.n_lines;
+  double acc = 0.0;
+  for (int64_t l = lb; l < le; ++l) {
+    const LineRec64 q = R[l];
+    const double dn = nuj - A.nu_c[l];
+    const double x = dn / (kSqrt2 * q.beta);
+    const double a = q.gam / (kSqrt2 * q.beta);
+    acc += q.A / (sqrt(2.0 * kPi) * q.beta) * hjert_f64(x, a, q.erfcxa);
+  }
+  if (j >= A.ng) return;
+  if (A.ksplit == 1) {
+    A.out64[(int64_t)y * A.ld_out + j] = acc * A.out_scale64;
+  } else {
+    A.part64[((int64_t)blockIdx.z * A.nlay + y) * A.ng + j] = acc;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_voigt_combine64(VoigtArgs A) {
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int y = blockIdx.y;
+  if (j >= A.ng) return;
+  double s = 0.0;
+  for (int z = 0; z < A.ksplit; ++z) s += A.part64[((int64_t)z * A.nlay + y) * A.ng + j];
+  A.out64[(int64_t)y * A.ld_out + j] = s * A.out_scale64;
+}
+
+// ---------------------------------------------------------------------------
+// Diagnostics: H (and L) of the FP32 path through the same record and pair
+// arithmetic as the Voigt sum (beta = 1/sqrt2, so dnu = x, gamma = a and the
+// contribution with amplitude sqrt(pi) equals H).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_hjert_f32(int64_t n, const float* __restrict__ x,
+                                                   const float* __restrict__ a, float* __restrict__ H,
+                                                   float* __restrict__ L) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const double beta = 1.0 / kSqrt2;
+  LineRec q;
+  make_line_record(kSqrtPi, beta, (double)a[i], 1.0, 0.0, 0.0, 0.0, &q, nullptr);
+  const float d = x[i];
+  const float D = fmaf(d, d, q.gam2);
+  const float r = __builtin_amdgcn_rcpf(D);
+  float h = fmaf(q.e[6], r, q.e[5]);
+  h = fmaf(h, r, q.e[4]);
+  h = fmaf(h, r, q.e[3]);
+  h = fmaf(h, r, q.e[2]);
+  h = fmaf(h, r, q.e[1]);
+  h = fmaf(h, r, q.e[0]);
+  float f = h * r;
+  float l = 0.f;
+  if (D < q.thr) {
+    f = q.acore * hjert_core_f32(d * q.winv, q.a, q.erfcxa, &l);
+  } else if (L) {
+    hjert_asy_f32(d, q.a, &l);
+  }
+  H[i] = f;
+  if (L) L[i] = l;
+}
+
+__global__ __launch_bounds__(256) void k_hjert_f64(int64_t n, const double* __restrict__ x,
+                                                   const double* __restrict__ a, double* __restrict__ H) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  H[i] = hjert_f64(x[i], a[i], erfcx(a[i]));
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+hipError_t launch_line_records(const LinesDev& L, const double* T_lay, const double* P_lay,
+                               const double* col_lay, double amp_scale, int layer0, int nlay,
+                               LineRec* rec, LineRecT* rect, LineRec64* rec64, hipStream_t st) {
+  dim3 grid((unsigned)((L.n + 255) / 256), (unsigned)nlay);
+  hipLaunchKernelGGL(k_line_records, grid, dim3(256), 0, st, L, T_lay, P_lay, col_lay, amp_scale,
+                     layer0, rec, rect, rec64);
+  return hipGetLastError();
+}
+
+hipError_t launch_voigt(const VoigtArgs& A, bool fp64, bool tangent, hipStream_t st) {
+  if (fp64) {
+    dim3 grid((unsigned)((A.ng + 255) / 256), (unsigned)A.nlay, (unsigned)A.ksplit);
+    hipLaunchKernelGGL(k_voigt_f64, grid, dim3(256), 0, st, A);
+    if (A.ksplit > 1) {
+      dim3 g2((unsigned)((A.ng + 255) / 256), (unsigned)A.nlay);
+      hipLaunchKernelGGL(k_voigt_combine64, g2, dim3(256), 0, st, A);
+    }
+    return hipGetLastError();
+  }
+  constexpr int G = kVoigtG;
+  dim3 grid((unsigned)((A.ng + 256 * G - 1) / (256 * G)), (unsigned)A.nlay, (unsigned)A.ksplit);
+  if (tangent) hipLaunchKernelGGL((k_voigt_f32<true, G>), grid, dim3(256), 0, st, A);
+  else hipLaunchKernelGGL((k_voigt_f32<false, G>), grid, dim3(256), 0, st, A);
+  if (A.ksplit > 1) {
+    dim3 g2((unsigned)((A.ng + 255) / 256), (unsigned)A.nlay);
+    if (tangent) hipLaunchKernelGGL(k_voigt_combine<true>, g2, dim3(256), 0, st, A);
+    else hipLaunchKernelGGL(k_voigt_combine<false>, g2, dim3(256), 0, st, A);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_hjert_f32(int64_t n, const float* x, const float* a, float* H, float* L,
+                            hipStream_t st) {
+  hipLaunchKernelGGL(k_hjert_f32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, x, a, H, L);
+  return hipGetLastError();
+}
+
+hipError_t launch_hjert_f64(int64_t n, const double* x, const double* a, double* H, hipStream_t st) {
+  hipLaunchKernelGGL(k_hjert_f64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, x, a, H);
+  return hipGetLastError();
+}
+
+}  // namespace exo

@@ -138,7 +138,7 @@ def make_config(k: int, size: str = "full", seed: Optional[int] = None) -> Workl
     if k in (2, 4):
         # lines per species, grid points, layers, output margin (grid points)
         n_lines, n_nu, n_lay, margin = {
-            "tiny": (9, 301, 12, 40),
+            "tiny": (9, 1201, 12, 60),
             "small": (401, 1537, 100, 160),
             "medium": (20011, 20000, 100, 600),
             "full": (100000, 20000, 100, 600),

@@ -1,0 +1,287 @@
+"""Parity of the HIP path (through the C ABI) against the FP64 oracle.
+
+Tolerances: 1e-4 relative (max over points) on cross-sections and fluxes,
+1e-3 on gradients (per component, relative to max(|g*|, 1e-6 ||g*||_inf)).
+The GPU's hjert approximates Re w to ~1e-6; FP32 rounding and the blocked
+compensated sum add ~1e-6.
+"""
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+RTOL_FLUX = 1e-4
+RTOL_GRAD = 1e-3
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def exo():
+    import paper_2105_14782_amd as pkg
+    pkg.load_library()
+    from paper_2105_14782_amd import api
+    return api
+
+
+def maxrel(a, b):
+    a, b = np.asarray(a, float), np.asarray(b, float)
+    return float(np.max(np.abs(a - b) / np.abs(b)))
+
+
+# ------------------------------------------------------------------ special functions
+
+def test_hjert_f32_error_map(exo):
+    _say("hjert_f32 error map")
+    xs = np.concatenate([[0.0], np.logspace(-4, 5, 181)])
+    as_ = np.concatenate([[0.0], np.logspace(-4, 5, 91)])
+    X, A = np.meshgrid(xs, as_)
+    x, a = X.ravel(), A.ravel()
+    H, Lg = exo.hjert_f32(torch.tensor(x, dtype=torch.float32, device="cuda"),
+                          torch.tensor(a, dtype=torch.float32, device="cuda"), want_L=True)
+    H, Lg = H.cpu().double().numpy(), Lg.cpu().double().numpy()
+    w = O.faddeeva(x.astype(np.float32).astype(float) + 1j * a.astype(np.float32).astype(float))
+    errH = np.abs(H - w.real)
+    # paper bound (Sec. 2.1.1, App. A): |hjert - Re wofz| < 1e-6
+    assert errH.max() < 1e-6, (errH.max(), x[errH.argmax()], a[errH.argmax()])
+    # relative accuracy wherever H is not vanishingly small
+    big = w.real > 1e-30
+    rel = errH[big] / w.real[big]
+    assert np.max(rel[(x[big] ** 2 + a[big] ** 2) >= 111]) < 2e-6
+    core = (x ** 2 + a ** 2) < 111
+    assert np.max(np.abs(Lg[core] - w.imag[core])) < 2e-6
+
+
+def test_hjert_f64_error_map(exo):
+    xs = np.concatenate([[0.0], np.logspace(-4, 5, 121)])
+    as_ = np.concatenate([[0.0], np.logspace(-4, 5, 61)])
+    X, A = np.meshgrid(xs, as_)
+    x, a = X.ravel(), A.ravel()
+    H = exo.hjert_f64(torch.tensor(x, device="cuda"), torch.tensor(a, device="cuda")).cpu().numpy()
+    w = O.faddeeva(x + 1j * a).real
+    assert np.max(np.abs(H - w)) < 1e-6
+
+
+def test_trans2e3_against_exact(exo):
+    x = np.concatenate([[0.0], np.logspace(-8, 2.5, 400)])
+    T, dT = exo.trans2e3(torch.tensor(x, device="cuda"))
+    T, dT = T.cpu().numpy(), dT.cpu().numpy()
+    exact = O.transmission(x)
+    # paper: AS70 2E3 within 5e-8 in F64 (App. A, Table 4)
+    assert np.max(np.abs(T - exact)) < 5e-8
+    np.testing.assert_allclose(dT, O.dtransmission(x), rtol=2e-6, atol=1e-12)
+
+
+# ------------------------------------------------------------------ cross-section
+
+def _ctx_with(exo, wl, grid=None):
+    c = exo.Context(0)
+    for s, ll in enumerate(wl.lines):
+        c.set_lines(s, ll)
+    c.set_grid(wl.nu if grid is None else grid)
+    return c
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_cross_section_config1(exo, prec):
+    _say(f"cross_section config1 {prec}")
+    wl = synth.make_config(1, "full")
+    c = _ctx_with(exo, wl)
+    sig = c.cross_section(0, wl.T, wl.P_bar, prec).cpu().double().numpy()
+    ref = O.cross_section(wl.lines[0], wl.T, wl.P_bar, wl.nu)
+    err = maxrel(sig, ref)
+    _say(f"  max rel err {err:.3e}")
+    assert err < (RTOL_FLUX if prec == "fp32" else 1e-5)
+
+
+@pytest.mark.parametrize("n_lines,n_nu", [(1, 2), (1, 7), (33, 257), (97, 1023), (200, 4097)])
+def test_cross_section_ragged_shapes(exo, n_lines, n_nu):
+    rng = np.random.default_rng(n_lines * 7919 + n_nu)
+    nu = np.sort(rng.uniform(4340, 4350, n_nu)) if n_nu > 2 else np.array([4344.0, 4345.0])
+    ll = synth.LineList(np.sort(rng.uniform(4339, 4351, n_lines)), 10 ** rng.uniform(-25, -20, n_lines),
+                        rng.exponential(1000, n_lines), rng.uniform(0.01, 0.1, n_lines),
+                        rng.uniform(0.5, 0.8, n_lines), 18.0, 0, np.array([1.5]))
+    c = exo.Context(0)
+    c.set_lines(3, ll)
+    c.set_grid(nu)
+    for T, P in [(800.0, 0.01), (1500.0, 3.0)]:
+        ref = O.cross_section(ll, T, P, nu)
+        for prec, tol in [("fp32", RTOL_FLUX), ("fp64", 1e-5)]:
+            got = c.cross_section(3, T, P, prec).cpu().double().numpy()
+            assert maxrel(got, ref) < tol, (prec, T, P)
+
+
+def test_cross_section_degenerate_widths(exo):
+    """P = 0 (pure Doppler, a = 0), huge pressure (a^2 >= 111 everywhere), natural width."""
+    rng = np.random.default_rng(11)
+    n = 50
+    nu = np.linspace(4340, 4345, 3001)
+    ll = synth.LineList(np.sort(rng.uniform(4340.5, 4344.5, n)), 10 ** rng.uniform(-23, -20, n),
+                        np.zeros(n), rng.uniform(0.01, 0.1, n), rng.uniform(0.5, 0.8, n), 28.0, 0,
+                        np.array([1.0]), gamma_nat=rng.uniform(0, 1e-3, n))
+    c = exo.Context(0)
+    c.set_lines(0, ll)
+    c.set_grid(nu)
+    for T, P in [(600.0, 0.0), (1200.0, 300.0), (2500.0, 1e-6)]:
+        ref = O.cross_section(ll, T, P, nu)
+        got = c.cross_section(0, T, P, "fp32").cpu().double().numpy()
+        assert maxrel(got, ref) < RTOL_FLUX, (T, P)
+
+
+def test_cross_section_is_deterministic(exo):
+    wl = synth.make_config(1, "full")
+    c = _ctx_with(exo, wl)
+    a = c.cross_section(0, 1000.0, 1.0).cpu()
+    b = c.cross_section(0, 1000.0, 1.0).cpu()
+    assert torch.equal(a, b)
+
+
+# ------------------------------------------------------------------ emission
+
+def _atmos(exo, wl, theta=None, **kw):
+    return exo.Atmos.from_workload(wl.atmos, list(range(len(wl.lines))), theta, **kw)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_emission_small_with_response(exo, prec):
+    _say(f"emission small {prec}")
+    wl = synth.make_config(2, "small")
+    c = _ctx_with(exo, wl)
+    F = c.emission_flux(_atmos(exo, wl), exo.Response.from_workload(wl.response), prec).cpu().double().numpy()
+    ref = O.emission_flux(wl, wl.theta_star)
+    err = maxrel(F, ref)
+    _say(f"  max rel err {err:.3e}")
+    assert err < (RTOL_FLUX if prec == "fp32" else 1e-5)
+
+
+def test_emission_small_F0_zero_bottom(exo):
+    wl = synth.make_config(2, "small")
+    wl.atmos.bottom = 1
+    c = _ctx_with(exo, wl)
+    F0 = c.emission_flux(_atmos(exo, wl), None, "fp32").cpu().double().numpy()
+    ref = O.emission_F0(wl, wl.theta_star)
+    assert maxrel(F0, ref) < RTOL_FLUX
+
+
+def test_emission_sub_grid_window(exo):
+    """A model grid that is a window of the registered grid gives the window's spectrum."""
+    wl = synth.make_config(2, "small")
+    c = _ctx_with(exo, wl)
+    b, n = 311, 700
+    F0w = c.emission_flux(_atmos(exo, wl, grid_begin=b, grid_len=n), None, "fp32").cpu()
+    F0 = c.emission_flux(_atmos(exo, wl), None, "fp32").cpu()
+    np.testing.assert_allclose(F0w.numpy(), F0[b:b + n].numpy(), rtol=1e-6)
+
+
+def test_emission_full_config2_sampled(exo):
+    """Full configuration-2 size: F0 at sampled grid points against the oracle (all lines, all layers)."""
+    _say("emission full config2 sampled")
+    wl = synth.make_config(2, "full")
+    c = _ctx_with(exo, wl)
+    rng = np.random.default_rng(2024)
+    idx = np.sort(rng.choice(wl.nu.size, 12, replace=False))
+    idx[0], idx[-1] = 0, wl.nu.size - 1
+    for prec, tol in [("fp32", RTOL_FLUX), ("fp64", 1e-5)]:
+        F0 = c.emission_flux(_atmos(exo, wl), None, prec).cpu().double().numpy()
+        ref = O.emission_F0(wl, wl.theta_star, nu_idx=idx)
+        err = maxrel(F0[idx], ref)
+        _say(f"  {prec} max rel err {err:.3e}")
+        assert err < tol
+    # the response stage at full size, on a seeded synthetic input spectrum
+    F0s = 1e4 * (1 + 0.3 * np.sin(np.arange(wl.nu.size) / 37.0) * np.cos(np.arange(wl.nu.size) / 5.1))
+    r = exo.Response.from_workload(wl.response)
+    got = c.broaden(torch.tensor(F0s, device="cuda"), r).cpu().numpy()
+    ref = O.response(F0s, wl.nu, wl.response)
+    assert maxrel(got, ref) < 1e-11
+
+
+def test_response_rejects_out_of_range(exo):
+    import paper_2105_14782_amd as pkg
+    wl = synth.make_config(2, "small")
+    c = _ctx_with(exo, wl)
+    r = exo.Response.from_workload(wl.response)
+    r.out_begin, r.out_len = 0, wl.nu.size      # taps would reach past both grid ends
+    with pytest.raises(pkg.ExoError) as e:
+        c.emission_flux(_atmos(exo, wl), r)
+    assert e.value.code == pkg.EXO_EINVAL
+    r = exo.Response.from_workload(wl.response)
+    r.vsini_kms = 0.1                            # narrower than two grid spacings
+    with pytest.raises(pkg.ExoError) as e:
+        c.emission_flux(_atmos(exo, wl), r)
+    assert e.value.code == pkg.EXO_EINVAL
+    bad = _atmos(exo, wl)
+    bad.P_bar = bad.P_bar[::-1].copy()          # pressures must ascend
+    with pytest.raises(pkg.ExoError) as e:
+        c.emission_flux(bad, None)
+    assert e.value.code == pkg.EXO_EINVAL
+    bad = _atmos(exo, wl)
+    bad.species = [0, 7]                         # slot 7 was never registered
+    with pytest.raises(pkg.ExoError) as e:
+        c.emission_flux(bad, None)
+    assert e.value.code == pkg.EXO_ENOTSET
+
+
+# ------------------------------------------------------------------ gradients
+
+def _grad_case(size):
+    wl = synth.make_config(4, size)
+    F_star = O.emission_flux(wl, wl.theta_star)
+    rng = np.random.default_rng(4004)
+    data = F_star * (1 + 0.01 * rng.normal(size=F_star.size))
+    sigma = 0.01 * F_star
+    return wl, data, sigma
+
+
+def _check_grad(g, g_ref, tol):
+    scale = np.maximum(np.abs(g_ref), 1e-6 * np.max(np.abs(g_ref)))
+    err = np.abs(g - g_ref) / scale
+    return err
+
+
+def test_flux_vjp_small_against_oracle(exo):
+    _say("flux_vjp small")
+    wl, data, sigma = _grad_case("small")
+    c = _ctx_with(exo, wl)
+    th = wl.theta
+    atm = _atmos(exo, wl, th)
+    resp = exo.Response.from_workload(wl.response, th)
+    F = c.emission_flux(atm, resp, "fp32").double()
+    d = torch.tensor(data, device="cuda")
+    s = torch.tensor(sigma, device="cuda")
+    cot = (-(d - F) / s ** 2).float().contiguous()
+    g, gl, Fv = c.flux_vjp(atm, resp, cot, want_layers=True, want_flux=True)
+    assert torch.equal(Fv.cpu(), F.float().cpu())
+    # oracle gradient of the same loss with the oracle's F
+    Lo, g_ref, gl_ref = O.loss_gradient(wl, th, data, sigma, per_layer=True)
+    err = _check_grad(g, g_ref, RTOL_GRAD)
+    _say(f"  grad rel err {err}")
+    assert np.all(err < RTOL_GRAD), (g, g_ref)
+    errl = np.abs(gl - gl_ref) / np.maximum(np.abs(gl_ref), 1e-6 * np.abs(gl_ref).max())
+    assert np.max(errl) < 5e-3
+
+
+def test_emission_autograd_function(exo):
+    wl, data, sigma = _grad_case("tiny")
+    c = _ctx_with(exo, wl)
+    atm = _atmos(exo, wl)
+    resp = exo.Response.from_workload(wl.response)
+    theta = torch.tensor(wl.theta, dtype=torch.float64, requires_grad=True)
+    F = exo.EmissionFlux.apply(theta, c, atm, resp)
+    d = torch.tensor(data, device="cuda", dtype=torch.float32)
+    s = torch.tensor(sigma, device="cuda", dtype=torch.float32)
+    loss = 0.5 * torch.sum(((d - F) / s) ** 2)
+    loss.backward()
+    _, g_ref = O.loss_gradient(wl, wl.theta, data, sigma)
+    err = _check_grad(theta.grad.numpy(), g_ref, RTOL_GRAD)
+    assert np.all(err < 5e-3), (theta.grad, g_ref)
