@@ -10,7 +10,7 @@ import ctypes
 import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libexohip.so")
+LIB_PATH = os.environ.get("EXO_LIB_PATH") or os.path.join(_HERE, "libexohip.so")
 
 EXO_OK, EXO_EINVAL, EXO_ENOMEM, EXO_ENOTSET, EXO_EDEVICE = 0, -1, -2, -3, -4
 EXO_FP32_KAHAN, EXO_FP64 = 0, 1

@@ -44,9 +44,29 @@ struct LineRec {
   float a;        // gamma / (sqrt2 beta)
   float erfcxa;   // erfcx(a)
   float acore;    // amplitude / (sqrt(2 pi) beta): contribution = acore * H(x, a)
-  float pad[3];
+  float C1;       // sum_n v0_n e^{-eta^2 n^2}  (S1 = e^{-x^2} C1)
+  float pad[2];
 };
 static_assert(sizeof(LineRec) == 64, "LineRec layout");
+
+// Series weights of the core branch for one (line, layer):
+// v0_n = 1 / (eta^2 n^2 + a^2), n = 1..27.
+struct LineCore {
+  float v0[32];
+};
+static_assert(sizeof(LineCore) == 128, "LineCore layout");
+
+// e^{-eta^2 n^2} for eta = 1/2, n = 1..27.
+__device__ constexpr double kGauss916[27] = {
+    0.77880078307140488, 0.36787944117144233, 0.10539922456186433, 0.018315638888734179,
+    0.0019304541362277093, 0.00012340980408667956, 4.7851173921290088e-06,
+    1.1253517471925912e-07, 1.6052280551856116e-09, 1.3887943864964021e-11,
+    7.2877240958196922e-14, 2.3195228302435696e-16, 4.4777324417183015e-19,
+    5.2428856633634639e-22, 3.7233631217505106e-25, 1.6038108905486379e-28,
+    4.1900931944943974e-32, 6.6396771995807348e-36, 6.3815034480607908e-40,
+    3.7200759760208361e-44, 1.3153258948574645e-48, 2.8207700884601352e-53,
+    3.6690596154291634e-58, 2.8946403116483003e-63, 1.3851193699226017e-68,
+    4.0200602157433552e-74, 7.0766981754295491e-80};
 
 // d/dT of the same contribution (tangent mode).
 struct LineRecT {
@@ -71,7 +91,7 @@ struct LineRec64 {
 // ---------------------------------------------------------------------------
 __device__ inline void make_line_record(double A, double beta, double gam, double T,
                                         double dlnA, double dbeta, double dgam,
-                                        LineRec* R, LineRecT* RT) {
+                                        LineRec* R, LineRecT* RT, LineCore* RC) {
   const double b = beta * beta, g = gam * gam;
   const double E0 = A * gam / kPi;
   double c[7];
@@ -92,7 +112,21 @@ __device__ inline void make_line_record(double A, double beta, double gam, doubl
   r.a = (float)(gam * winv);
   r.erfcxa = (float)erfcx(gam * winv);
   r.acore = (float)(A * winv / kSqrtPi);
-  r.pad[0] = r.pad[1] = r.pad[2] = 0.f;
+  {
+    const double a = gam * winv;
+    double c1 = 0.0;
+    LineCore core;
+    for (int n = 1; n <= kM916; ++n) {
+      const double en = 0.5 * n;
+      const double v0 = 1.0 / (en * en + a * a);
+      core.v0[n - 1] = (float)v0;
+      c1 += (double)core.v0[n - 1] * kGauss916[n - 1];
+    }
+    for (int n = kM916; n < 32; ++n) core.v0[n] = 0.f;
+    r.C1 = (float)c1;
+    if (RC) *RC = core;
+  }
+  r.pad[0] = r.pad[1] = 0.f;
   *R = r;
   if (RT) {
     // db/dT, dg/dT
@@ -168,6 +202,50 @@ __device__ inline float hjert_core_f32(float x, float a, float erfcxa, float* L)
     *L = -ex2 * erfcxa * s2 + t2l + twoeta_pi * (a * s2 * S1 - 0.5f * S4 + 0.5f * S5);
   }
   return H;
+}
+
+// The same Algorithm-916 series evaluated through an exact factorisation of
+// its Gaussians, e^{-(eta n -/+ x)^2} = e^{-x^2} e^{-eta^2 n^2} e^{+/-2 eta n x}
+// (eta = 1/2, so e^{2 eta n x} = X^n with X = e^x), accumulated in FP64 where
+// X^27 e^{-x^2} and e^{-n^2/4} stay in range.  v0[n-1] = 1/(eta^2 n^2 + a^2)
+// and C1 = sum_n v0_n e^{-eta^2 n^2} come with the line record.  Same terms,
+// same M = 27; only the order of the multiplications differs.
+template <bool WANT_L>
+__device__ __forceinline__ float hjert_core_fac(float xf, float af, float erfcxa, float C1,
+                                                const float* __restrict__ v0, float* Lout) {
+  constexpr double twoeta_pi = 1.0 / kPi;  // 2 eta / pi
+  const double x = (double)xf, a = (double)af;
+  const double ex2 = exp(-x * x);
+  const double X = exp(x), Y = 1.0 / X;
+  double Xn = 1.0, Yn = 1.0, s2 = 0.0, s3 = 0.0, s4 = 0.0, s5 = 0.0;
+#pragma unroll 1
+  for (int n = 1; n <= kM916; ++n) {
+    Xn *= X;
+    Yn *= Y;
+    const double w = (double)v0[n - 1] * kGauss916[n - 1];
+    s3 = fma(w, Xn, s3);   // sum v0 e^{-(eta n - x)^2} / e^{-x^2}
+    s2 = fma(w, Yn, s2);   // sum v0 e^{-(eta n + x)^2} / e^{-x^2}
+    if (WANT_L) {
+      const double ew = (0.5 * n) * w;
+      s5 = fma(ew, Xn, s5);
+      s4 = fma(ew, Yn, s4);
+    }
+  }
+  const double S1 = ex2 * (double)C1;
+  const float ax = af * xf;
+  float s2xa, c2xa;
+  sincosf(2.0f * ax, &s2xa, &c2xa);
+  const float sax = sinf(ax);
+  // (2 eta x sin(ax)/pi) e^{-x^2} sinc(ax/pi) = (2 eta/pi) e^{-x^2} sin^2(ax)/a
+  const double t2 = (ax != 0.f) ? twoeta_pi * ex2 * (double)sax * (double)sax / a : 0.0;
+  const double H = ex2 * (double)erfcxa * (double)c2xa + t2 +
+                   twoeta_pi * a * (-(double)c2xa * S1 + 0.5 * ex2 * (s2 + s3));
+  if (WANT_L) {
+    const double t2l = (ax != 0.f) ? twoeta_pi * ex2 * (double)s2xa / (2.0 * a) : twoeta_pi * ex2 * x;
+    *Lout = (float)(-ex2 * (double)erfcxa * (double)s2xa + t2l +
+                    twoeta_pi * (a * (double)s2xa * S1 + 0.5 * ex2 * (s5 - s4)));
+  }
+  return (float)H;
 }
 
 // Asymptotic branch Re/Im of w_2^asy(x + i a) in FP32 (diagnostics).

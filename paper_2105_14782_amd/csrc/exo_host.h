@@ -26,7 +26,7 @@ struct DevBuf {
 // synchronous API; the serving engine owns one per slot.
 struct Workspace {
   static constexpr size_t kStageDoubles = 1 << 14;
-  DevBuf rec, rect, rec64, tau, taut, part, part_t, F0, F0bar, mid, midbar, Fup, taubar, layer,
+  DevBuf rec, rect, core, rec64, tau, taut, part, part_t, F0, F0bar, mid, midbar, Fup, taubar, layer,
       col, taps, partT, partX, partR, gout, params;
   double* h_stage = nullptr;     // pinned staging for per-call parameters
   hipEvent_t stage_ev = nullptr; // guards h_stage reuse
@@ -41,7 +41,7 @@ struct Workspace {
   int stage_params(const double* host, size_t n, double* dev, hipStream_t st);
   size_t bytes() const {
     size_t b = 0;
-    for (const DevBuf* x : {&rec, &rect, &rec64, &tau, &taut, &part, &part_t, &F0, &F0bar, &mid,
+    for (const DevBuf* x : {&rec, &rect, &core, &rec64, &tau, &taut, &part, &part_t, &F0, &F0bar, &mid,
                             &midbar, &Fup, &taubar, &layer, &col, &taps, &partT, &partX, &partR,
                             &gout, &params})
       b += x->cap;

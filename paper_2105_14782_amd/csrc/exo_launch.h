@@ -9,7 +9,10 @@
 namespace exo {
 
 constexpr int kMaxSpecies = 64;
-constexpr int kVoigtG = 2;  // grid points per thread in the FP32 Voigt sum
+#ifndef EXO_VOIGT_G
+#define EXO_VOIGT_G 4
+#endif
+constexpr int kVoigtG = EXO_VOIGT_G;  // grid points per thread in the FP32 Voigt sum
 
 struct LinesDev {
   const double *nu_c, *S0, *E_low, *alpha_ref, *n_texp, *gamma_nat;
@@ -27,6 +30,7 @@ struct VoigtArgs {
   int64_t n_lines;
   const LineRec* rec;
   const LineRecT* rect;
+  const LineCore* core;
   const LineRec64* rec64;
   int64_t lines_per_split;
   int ksplit;
@@ -82,7 +86,8 @@ struct RespDev {
 
 hipError_t launch_line_records(const LinesDev& L, const double* T_lay, const double* P_lay,
                                const double* col_lay, double amp_scale, int layer0, int nlay,
-                               LineRec* rec, LineRecT* rect, LineRec64* rec64, hipStream_t st);
+                               LineRec* rec, LineRecT* rect, LineCore* core, LineRec64* rec64,
+                               hipStream_t st);
 hipError_t launch_voigt(const VoigtArgs& A, bool fp64, bool tangent, hipStream_t st);
 hipError_t launch_hjert_f32(int64_t n, const float* x, const float* a, float* H, float* L,
                             hipStream_t st);

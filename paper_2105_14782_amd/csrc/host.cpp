@@ -94,7 +94,7 @@ bool exo::fail_alloc_hook() {
 Workspace::~Workspace() { release(); }
 
 void Workspace::release() {
-  for (DevBuf* b : {&rec, &rect, &rec64, &tau, &taut, &part, &part_t, &F0, &F0bar, &mid, &midbar,
+  for (DevBuf* b : {&rec, &rect, &core, &rec64, &tau, &taut, &part, &part_t, &F0, &F0bar, &mid, &midbar,
                     &Fup, &taubar, &layer, &col, &taps, &partT, &partX, &partR, &gout, &params})
     b->release();
   if (h_stage) (void)hipHostFree(h_stage);
@@ -190,7 +190,7 @@ extern "C" int exo_set_lines(exo_ctx* c, int s, int64_t n, const double* nu_c, c
                              const double* qr_params, int n_qr) {
   if (!c) return set_err(EXO_EINVAL, "ctx is NULL");
   if (s < 0 || s >= EXO_MAX_SPECIES) return set_err(EXO_EINVAL, "species slot %d out of range", s);
-  if (n < 1) return set_err(EXO_EINVAL, "n_lines must be >= 1");
+  if (n < 1 || n >= ((int64_t)1 << 31)) return set_err(EXO_EINVAL, "n_lines must be in [1, 2^31)");
   if (!nu_c || !S0 || !E_low || !alpha_ref || !n_texp) return set_err(EXO_EINVAL, "NULL line array");
   if (!(mass_amu > 0) || !std::isfinite(mass_amu)) return set_err(EXO_EINVAL, "mass must be > 0");
   if (!finite_all(nu_c, n) || !finite_all(S0, n) || !finite_all(E_low, n) ||
@@ -359,13 +359,15 @@ int exo::species_opacity(exo_ctx* c, Workspace& ws, const Species& sp, const dou
                          bool fp64, bool tangent, const double* d_nu, int64_t ng, void* out,
                          float* out_t, hipStream_t st) {
   const LinesDev L = lines_dev(sp);
-  const size_t per_layer = (size_t)sp.n * (fp64 ? sizeof(LineRec64) : sizeof(LineRec) + (tangent ? sizeof(LineRecT) : 0));
+  const size_t per_layer = (size_t)sp.n * (fp64 ? sizeof(LineRec64)
+                                                : sizeof(LineRec) + sizeof(LineCore) + (tangent ? sizeof(LineRecT) : 0));
   int nlc = (int)std::max<size_t>(1, std::min<size_t>((size_t)nlay, kRecBudget / per_layer));
   int rc;
   if (fp64) {
     if ((rc = ws.rec64.reserve((size_t)nlc * sp.n * sizeof(LineRec64)))) return rc;
   } else {
     if ((rc = ws.rec.reserve((size_t)nlc * sp.n * sizeof(LineRec)))) return rc;
+    if ((rc = ws.core.reserve((size_t)nlc * sp.n * sizeof(LineCore)))) return rc;
     if (tangent && (rc = ws.rect.reserve((size_t)nlc * sp.n * sizeof(LineRecT)))) return rc;
   }
   const int64_t G = fp64 ? 1 : kVoigtG;
@@ -374,6 +376,7 @@ int exo::species_opacity(exo_ctx* c, Workspace& ws, const Species& sp, const dou
     HIP_TRY(launch_line_records(L, d_T, d_P, d_col, amp_scale, l0, nl,
                                 fp64 ? nullptr : (LineRec*)ws.rec.p,
                                 (!fp64 && tangent) ? (LineRecT*)ws.rect.p : nullptr,
+                                fp64 ? nullptr : (LineCore*)ws.core.p,
                                 fp64 ? (LineRec64*)ws.rec64.p : nullptr, st));
     VoigtArgs A{};
     A.nu = d_nu;
@@ -382,6 +385,7 @@ int exo::species_opacity(exo_ctx* c, Workspace& ws, const Species& sp, const dou
     A.n_lines = sp.n;
     A.rec = (const LineRec*)ws.rec.p;
     A.rect = (const LineRecT*)ws.rect.p;
+    A.core = (const LineCore*)ws.core.p;
     A.rec64 = (const LineRec64*)ws.rec64.p;
     A.nlay = nl;
     A.out_scale = (float)(1.0 / amp_scale);

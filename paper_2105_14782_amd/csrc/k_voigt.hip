@@ -77,6 +77,7 @@ __global__ __launch_bounds__(256) void k_line_records(LinesDev L, const double* 
                                                       double amp_scale, int layer0,
                                                       LineRec* __restrict__ rec,
                                                       LineRecT* __restrict__ rect,
+                                                      LineCore* __restrict__ core,
                                                       LineRec64* __restrict__ rec64) {
   const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (l >= L.n) return;
@@ -104,7 +105,8 @@ __global__ __launch_bounds__(256) void k_line_records(LinesDev L, const double* 
     A = kAmpMax;
     dlnA = 0.0;
   }
-  make_line_record(A, s.beta, s.gam, T, dlnA, s.dbeta, s.dgam, rec + o, rect ? rect + o : nullptr);
+  make_line_record(A, s.beta, s.gam, T, dlnA, s.dbeta, s.dgam, rec + o, rect ? rect + o : nullptr,
+                   core + o);
 }
 
 // ---------------------------------------------------------------------------
@@ -128,23 +130,11 @@ __device__ inline void neumaier(float& s, float& c, float v) {
   s = t;
 }
 
-// Core branch of hjert for one pair, kept out of line: it is taken by ~1% of
-// pairs and inlining it per grid-point slot would bloat the hot loop.
-__device__ __attribute__((noinline)) float core_value(float d, float winv, float a, float erfcxa,
-                                                      float acore) {
-  return acore * hjert_core_f32(d * winv, a, erfcxa, nullptr);
-}
-
-__device__ __attribute__((noinline)) float2 core_value_tan(float d, float winv, float a,
-                                                           float erfcxa, float acore, float kA,
-                                                           float kw, float da) {
-  const float x = d * winv;
-  float L;
-  const float H = hjert_core_f32(x, a, erfcxa, &L);
-  // custom derivatives of Sec. 2.1.1: dH/dx = 2aL - 2xH, dH/da = 2xL + 2aH - 2/sqrt(pi)
-  const float Hx = 2.0f * (a * L - x * H);
-  const float Ha = 2.0f * (x * L + a * H) - 1.1283791670955126f;
-  return make_float2(acore * H, acore * (kA * H + Hx * x * kw + Ha * da));
+// Forward-only core evaluation kept out of line: its FP64 temporaries would
+// otherwise set the register budget of the whole loop and halve occupancy.
+__device__ __attribute__((noinline)) float core_value(float x, float a, float erfcxa, float C1,
+                                                      const float* __restrict__ v0) {
+  return hjert_core_fac<false>(x, a, erfcxa, C1, v0, nullptr);
 }
 
 template <bool TAN, int G>
@@ -154,47 +144,58 @@ __global__ __launch_bounds__(256) void k_voigt_f32(VoigtArgs A) {
   const int64_t tile0 = (int64_t)blockIdx.x * (256 * G);
   const double* __restrict__ nu = A.nu;
   double nuj[G];
-  int64_t jj[G];
 #pragma unroll
   for (int g = 0; g < G; ++g) {
     const int64_t j = tile0 + (int64_t)(w * G + g) * 64 + lane;
-    jj[g] = j;
     nuj[g] = nu[j < A.ng ? j : A.ng - 1];
   }
-  const int64_t lb = (int64_t)blockIdx.z * A.lines_per_split;
-  const int64_t le = lb + A.lines_per_split < A.n_lines ? lb + A.lines_per_split : A.n_lines;
+  // line range of this split (n_lines < 2^31 is checked on the host)
+  const int lb = (int)blockIdx.z * (int)A.lines_per_split;
+  const int le = min(lb + (int)A.lines_per_split, (int)A.n_lines);
   const LineRec* __restrict__ R = A.rec + (int64_t)y * A.n_lines;
   const LineRecT* __restrict__ RT = TAN ? A.rect + (int64_t)y * A.n_lines : nullptr;
+  const LineCore* __restrict__ RC = A.core + (int64_t)y * A.n_lines;
   const double* __restrict__ nuc = A.nu_c;
 
   float s[G], c[G], ts[G], tc[G];
 #pragma unroll
   for (int g = 0; g < G; ++g) s[g] = c[g] = ts[g] = tc[g] = 0.f;
 
-  for (int64_t l0 = lb; l0 < le; l0 += kChunk) {
-    const int64_t l1 = l0 + kChunk < le ? l0 + kChunk : le;
+  for (int l0 = lb; l0 < le; l0 += kChunk) {
+    const int l1 = min(l0 + kChunk, le);
     float blk[G], tblk[G];
 #pragma unroll
     for (int g = 0; g < G; ++g) blk[g] = tblk[g] = 0.f;
+    // the next line's record is requested one iteration ahead so that the
+    // scalar-load latency overlaps the current line's arithmetic
+    LineRec qn = R[l0];
+    double nun = nuc[l0];
+    LineRecT qtn;
+    if (TAN) qtn = RT[l0];
 #pragma unroll 2
-    for (int64_t l = l0; l < l1; ++l) {
-      const LineRec q = R[l];
-      const double nul = nuc[l];
+    for (int l = l0; l < l1; ++l) {
+      const LineRec q = qn;
+      const double nul = nun;
       LineRecT qt;
-      if (TAN) qt = RT[l];
+      if (TAN) qt = qtn;
+      const int ln = l + 1 < l1 ? l + 1 : l;
+      qn = R[ln];
+      nun = nuc[ln];
+      if (TAN) qtn = RT[ln];
+      float dd[G], D[G], f[G], ft[G];
+      bool core = false;
 #pragma unroll
       for (int g = 0; g < G; ++g) {
-        const float d = (float)(nuj[g] - nul);  // FP64 offset, rounded once
-        const float D = fmaf(d, d, q.gam2);
-        const float r = __builtin_amdgcn_rcpf(D);
+        dd[g] = (float)(nuj[g] - nul);  // FP64 offset, rounded once
+        D[g] = fmaf(dd[g], dd[g], q.gam2);
+        const float r = __builtin_amdgcn_rcpf(D[g]);
         float h = fmaf(q.e[6], r, q.e[5]);
         h = fmaf(h, r, q.e[4]);
         h = fmaf(h, r, q.e[3]);
         h = fmaf(h, r, q.e[2]);
         h = fmaf(h, r, q.e[1]);
         h = fmaf(h, r, q.e[0]);
-        float f = h * r;
-        float ft = 0.f;
+        f[g] = h * r;
         if (TAN) {
           float ht = fmaf(qt.t[7], r, qt.t[6]);
           ht = fmaf(ht, r, qt.t[5]);
@@ -203,19 +204,35 @@ __global__ __launch_bounds__(256) void k_voigt_f32(VoigtArgs A) {
           ht = fmaf(ht, r, qt.t[2]);
           ht = fmaf(ht, r, qt.t[1]);
           ht = fmaf(ht, r, qt.t[0]);
-          ft = ht * r;
+          ft[g] = ht * r;
         }
-        if (D < q.thr) {  // x^2 + a^2 < 111: Algorithm-916 series
-          if (TAN) {
-            const float2 v = core_value_tan(d, q.winv, q.a, q.erfcxa, q.acore, qt.kA, qt.kw, qt.da);
-            f = v.x;
-            ft = v.y;
-          } else {
-            f = core_value(d, q.winv, q.a, q.erfcxa, q.acore);
+        core |= D[g] < q.thr;
+      }
+      // x^2 + a^2 < 111 for some point of this thread: Algorithm-916 series
+      if (__builtin_expect(core, 0)) {
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+          if (D[g] < q.thr) {
+            const float x = dd[g] * q.winv;
+            if (TAN) {
+              float L;
+              const float H = hjert_core_fac<true>(x, q.a, q.erfcxa, q.C1, RC[l].v0, &L);
+              // custom derivatives of Sec. 2.1.1:
+              //   dH/dx = 2aL - 2xH,  dH/da = 2xL + 2aH - 2/sqrt(pi)
+              const float Hx = 2.0f * (q.a * L - x * H);
+              const float Ha = 2.0f * (x * L + q.a * H) - 1.1283791670955126f;
+              f[g] = q.acore * H;
+              ft[g] = q.acore * (qt.kA * H + Hx * x * qt.kw + Ha * qt.da);
+            } else {
+              f[g] = q.acore * core_value(x, q.a, q.erfcxa, q.C1, RC[l].v0);
+            }
           }
         }
-        blk[g] += f;
-        if (TAN) tblk[g] += ft;
+      }
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        blk[g] += f[g];
+        if (TAN) tblk[g] += ft[g];
       }
     }
 #pragma unroll
@@ -227,7 +244,7 @@ __global__ __launch_bounds__(256) void k_voigt_f32(VoigtArgs A) {
 
 #pragma unroll
   for (int g = 0; g < G; ++g) {
-    const int64_t j = jj[g];
+    const int64_t j = tile0 + (int64_t)(w * G + g) * 64 + lane;
     if (j >= A.ng) continue;
     const int64_t o = (int64_t)y * A.ld_out + j;
     if (A.ksplit == 1) {
@@ -313,7 +330,8 @@ __global__ __launch_bounds__(256) void k_hjert_f32(int64_t n, const float* __res
   if (i >= n) return;
   const double beta = 1.0 / kSqrt2;
   LineRec q;
-  make_line_record(kSqrtPi, beta, (double)a[i], 1.0, 0.0, 0.0, 0.0, &q, nullptr);
+  LineCore qc;
+  make_line_record(kSqrtPi, beta, (double)a[i], 1.0, 0.0, 0.0, 0.0, &q, nullptr, &qc);
   const float d = x[i];
   const float D = fmaf(d, d, q.gam2);
   const float r = __builtin_amdgcn_rcpf(D);
@@ -326,7 +344,7 @@ __global__ __launch_bounds__(256) void k_hjert_f32(int64_t n, const float* __res
   float f = h * r;
   float l = 0.f;
   if (D < q.thr) {
-    f = q.acore * hjert_core_f32(d * q.winv, q.a, q.erfcxa, &l);
+    f = q.acore * hjert_core_fac<true>(d * q.winv, q.a, q.erfcxa, q.C1, qc.v0, &l);
   } else if (L) {
     hjert_asy_f32(d, q.a, &l);
   }
@@ -346,10 +364,11 @@ __global__ __launch_bounds__(256) void k_hjert_f64(int64_t n, const double* __re
 // ---------------------------------------------------------------------------
 hipError_t launch_line_records(const LinesDev& L, const double* T_lay, const double* P_lay,
                                const double* col_lay, double amp_scale, int layer0, int nlay,
-                               LineRec* rec, LineRecT* rect, LineRec64* rec64, hipStream_t st) {
+                               LineRec* rec, LineRecT* rect, LineCore* core, LineRec64* rec64,
+                               hipStream_t st) {
   dim3 grid((unsigned)((L.n + 255) / 256), (unsigned)nlay);
   hipLaunchKernelGGL(k_line_records, grid, dim3(256), 0, st, L, T_lay, P_lay, col_lay, amp_scale,
-                     layer0, rec, rect, rec64);
+                     layer0, rec, rect, core, rec64);
   return hipGetLastError();
 }
 
