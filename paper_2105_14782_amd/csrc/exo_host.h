@@ -18,6 +18,7 @@ bool fail_alloc_hook();
 struct DevBuf {
   void* p = nullptr;
   size_t cap = 0;
+  bool owned = true;   // false: carved from a workspace arena
   int reserve(size_t bytes);
   void release();
 };
@@ -31,6 +32,16 @@ struct Workspace {
   double* h_stage = nullptr;     // pinned staging for per-call parameters
   hipEvent_t stage_ev = nullptr; // guards h_stage reuse
   RtArgs last_rt{};
+  // Arena mode (serving): buffers are carved from [arena, arena + arena_cap)
+  // instead of being allocated; no allocation happens while serving.
+  char* arena = nullptr;
+  size_t arena_cap = 0, arena_used = 0;
+  int reserve(DevBuf& b, size_t bytes);
+  void bind_arena(char* base, size_t cap);
+  std::vector<DevBuf*> bufs() {
+    return {&rec, &rect, &core, &rec64, &tau, &taut, &part, &part_t, &F0, &F0bar, &mid, &midbar,
+            &Fup, &taubar, &layer, &col, &taps, &partT, &partX, &partR, &gout, &params};
+  }
   hipEvent_t done_ev = nullptr;  // end of the last evaluation using this workspace
   hipStream_t last_st = nullptr;
   // Order this evaluation after the previous one when it runs on another stream.
@@ -83,6 +94,17 @@ struct exo_ctx {
 };
 
 namespace exo {
+struct OpacityPlan {
+  int nlc;  // layers per record chunk
+  size_t rec, core, rect, rec64, part, part_t;
+};
+OpacityPlan plan_opacity(int64_t n_lines, int nlay, int64_t ng, bool fp64, bool tangent);
+// component-wise largest plan over the species of an atmosphere
+OpacityPlan plan_opacity_all(const exo_ctx* c, const exo_atmos* a, int64_t gl, bool fp64, bool tangent);
+int reserve_opacity(Workspace& ws, const OpacityPlan& P);
+// Upper bound of the workspace bytes one evaluation reserves (arena sizing).
+size_t estimate_workspace(const exo_ctx* c, const exo_atmos* a, const exo_response* r, bool fp64,
+                          bool vjp);
 int voigt_launch_profiled(exo_ctx* c, const VoigtArgs& A, bool fp64, bool tan, hipStream_t st);
 int species_opacity(exo_ctx* c, Workspace& ws, const Species& sp, const double* d_T,
                     const double* d_P, const double* d_col, int nlay, double amp_scale, bool fp64,

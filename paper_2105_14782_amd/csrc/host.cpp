@@ -68,9 +68,10 @@ int exo::DevBuf::reserve(size_t bytes) {
 }
 
 void exo::DevBuf::release() {
-  if (p) (void)hipFree(p);
+  if (p && owned) (void)hipFree(p);
   p = nullptr;
   cap = 0;
+  owned = true;
 }
 
 // EXO_TEST_FAIL_ALLOC=n makes the n-th subsequent device allocation fail.
@@ -94,15 +95,40 @@ bool exo::fail_alloc_hook() {
 Workspace::~Workspace() { release(); }
 
 void Workspace::release() {
-  for (DevBuf* b : {&rec, &rect, &core, &rec64, &tau, &taut, &part, &part_t, &F0, &F0bar, &mid, &midbar,
-                    &Fup, &taubar, &layer, &col, &taps, &partT, &partX, &partR, &gout, &params})
-    b->release();
+  for (DevBuf* b : bufs()) b->release();
+  arena = nullptr;
+  arena_cap = arena_used = 0;
   if (h_stage) (void)hipHostFree(h_stage);
   h_stage = nullptr;
   if (stage_ev) (void)hipEventDestroy(stage_ev);
   stage_ev = nullptr;
   if (done_ev) (void)hipEventDestroy(done_ev);
   done_ev = nullptr;
+}
+
+int Workspace::reserve(DevBuf& b, size_t bytes) {
+  if (bytes <= b.cap) return EXO_OK;
+  if (!arena) return b.reserve(bytes);
+  const size_t need = (bytes + 255) & ~size_t(255);
+  if (arena_used + need > arena_cap)
+    return set_err(EXO_ENOMEM, "request needs more than its %zu-byte memory region", arena_cap);
+  b.p = arena + arena_used;
+  b.cap = need;
+  b.owned = false;
+  arena_used += need;
+  return EXO_OK;
+}
+
+void Workspace::bind_arena(char* base, size_t cap) {
+  for (DevBuf* b : bufs()) {
+    if (b->owned) b->release();
+    b->p = nullptr;
+    b->cap = 0;
+    b->owned = false;
+  }
+  arena = base;
+  arena_cap = cap;
+  arena_used = 0;
 }
 
 int Workspace::begin(hipStream_t st) {
@@ -354,23 +380,83 @@ static LinesDev lines_dev(const Species& sp) {
 // that fit it.
 static constexpr size_t kRecBudget = size_t(3) << 30;
 
+// Split over lines when the grid x layer tiles of one launch cannot fill the
+// device (fixed by the shape only, so results never depend on the load).
+static void split_plan(int64_t ng, int nl, int64_t n_lines, bool fp64, int64_t* ks_out,
+                       int64_t* lps_out) {
+  const int64_t G = fp64 ? 1 : kVoigtG;
+  const int64_t tiles = (ng + 256 * G - 1) / (256 * G);
+  const int64_t blocks = tiles * nl;
+  int64_t ks = 1;
+  if (blocks < 2048) ks = std::min<int64_t>((2048 + blocks - 1) / blocks, std::max<int64_t>(1, n_lines / 64));
+  int64_t lps = (n_lines + ks - 1) / ks;
+  lps = ((lps + 31) / 32) * 32;
+  ks = (n_lines + lps - 1) / lps;
+  *ks_out = ks;
+  *lps_out = lps;
+}
+
+OpacityPlan exo::plan_opacity(int64_t n_lines, int nlay, int64_t ng, bool fp64, bool tangent) {
+  OpacityPlan P{};
+  const size_t per_layer = (size_t)n_lines * (fp64 ? sizeof(LineRec64)
+                                                   : sizeof(LineRec) + sizeof(LineCore) + (tangent ? sizeof(LineRecT) : 0));
+  P.nlc = (int)std::max<size_t>(1, std::min<size_t>((size_t)nlay, kRecBudget / per_layer));
+  if (fp64) {
+    P.rec64 = (size_t)P.nlc * n_lines * sizeof(LineRec64);
+  } else {
+    P.rec = (size_t)P.nlc * n_lines * sizeof(LineRec);
+    P.core = (size_t)P.nlc * n_lines * sizeof(LineCore);
+    if (tangent) P.rect = (size_t)P.nlc * n_lines * sizeof(LineRecT);
+  }
+  // partial sums: the largest over the chunk sizes that occur
+  for (int nl : {P.nlc, nlay % P.nlc}) {
+    if (nl <= 0) continue;
+    int64_t ks, lps;
+    split_plan(ng, nl, n_lines, fp64, &ks, &lps);
+    if (ks > 1) {
+      const size_t pb = (size_t)ks * nl * ng * (fp64 ? sizeof(double) : sizeof(float2));
+      P.part = std::max(P.part, pb);
+      if (!fp64 && tangent) P.part_t = std::max(P.part_t, pb);
+    }
+  }
+  return P;
+}
+
+OpacityPlan exo::plan_opacity_all(const exo_ctx* c, const exo_atmos* a, int64_t gl, bool fp64,
+                                  bool tangent) {
+  OpacityPlan P{};
+  for (int m = 0; m < a->n_species; ++m) {
+    const OpacityPlan Q = plan_opacity(c->sp[a->species[m]].n, a->n_layers, gl, fp64, tangent);
+    P.rec = std::max(P.rec, Q.rec);
+    P.core = std::max(P.core, Q.core);
+    P.rect = std::max(P.rect, Q.rect);
+    P.rec64 = std::max(P.rec64, Q.rec64);
+    P.part = std::max(P.part, Q.part);
+    P.part_t = std::max(P.part_t, Q.part_t);
+  }
+  return P;
+}
+
+int exo::reserve_opacity(Workspace& ws, const OpacityPlan& P) {
+  int rc;
+  if (P.rec64 && (rc = ws.reserve(ws.rec64, P.rec64))) return rc;
+  if (P.rec && (rc = ws.reserve(ws.rec, P.rec))) return rc;
+  if (P.core && (rc = ws.reserve(ws.core, P.core))) return rc;
+  if (P.rect && (rc = ws.reserve(ws.rect, P.rect))) return rc;
+  if (P.part && (rc = ws.reserve(ws.part, P.part))) return rc;
+  if (P.part_t && (rc = ws.reserve(ws.part_t, P.part_t))) return rc;
+  return EXO_OK;
+}
+
 int exo::species_opacity(exo_ctx* c, Workspace& ws, const Species& sp, const double* d_T,
                          const double* d_P, const double* d_col, int nlay, double amp_scale,
                          bool fp64, bool tangent, const double* d_nu, int64_t ng, void* out,
                          float* out_t, hipStream_t st) {
   const LinesDev L = lines_dev(sp);
-  const size_t per_layer = (size_t)sp.n * (fp64 ? sizeof(LineRec64)
-                                                : sizeof(LineRec) + sizeof(LineCore) + (tangent ? sizeof(LineRecT) : 0));
-  int nlc = (int)std::max<size_t>(1, std::min<size_t>((size_t)nlay, kRecBudget / per_layer));
+  const OpacityPlan P = plan_opacity(sp.n, nlay, ng, fp64, tangent);
   int rc;
-  if (fp64) {
-    if ((rc = ws.rec64.reserve((size_t)nlc * sp.n * sizeof(LineRec64)))) return rc;
-  } else {
-    if ((rc = ws.rec.reserve((size_t)nlc * sp.n * sizeof(LineRec)))) return rc;
-    if ((rc = ws.core.reserve((size_t)nlc * sp.n * sizeof(LineCore)))) return rc;
-    if (tangent && (rc = ws.rect.reserve((size_t)nlc * sp.n * sizeof(LineRecT)))) return rc;
-  }
-  const int64_t G = fp64 ? 1 : kVoigtG;
+  if ((rc = reserve_opacity(ws, P))) return rc;
+  const int nlc = P.nlc;
   for (int l0 = 0; l0 < nlay; l0 += nlc) {
     const int nl = std::min(nlc, nlay - l0);
     HIP_TRY(launch_line_records(L, d_T, d_P, d_col, amp_scale, l0, nl,
@@ -396,20 +482,11 @@ int exo::species_opacity(exo_ctx* c, Workspace& ws, const Species& sp, const dou
       A.out = (float*)out + (int64_t)l0 * ng;
       A.out_t = tangent ? out_t + (int64_t)l0 * ng : nullptr;
     }
-    // split over lines when the grid x layer tiles cannot fill the device
-    const int64_t tiles = (ng + 256 * G - 1) / (256 * G);
-    const int64_t blocks = tiles * nl;
-    int64_t ks = 1;
-    if (blocks < 2048) ks = std::min<int64_t>((2048 + blocks - 1) / blocks, std::max<int64_t>(1, sp.n / 64));
-    int64_t lps = (sp.n + ks - 1) / ks;
-    lps = ((lps + 31) / 32) * 32;
-    ks = (sp.n + lps - 1) / lps;
+    int64_t ks, lps;
+    split_plan(ng, nl, sp.n, fp64, &ks, &lps);
     A.lines_per_split = lps;
     A.ksplit = (int)ks;
     if (ks > 1) {
-      const size_t pb = (size_t)ks * nl * ng * (fp64 ? sizeof(double) : sizeof(float2));
-      if ((rc = ws.part.reserve(pb))) return rc;
-      if (!fp64 && tangent && (rc = ws.part_t.reserve(pb))) return rc;
       A.part = (float2*)ws.part.p;
       A.part_t = (float2*)ws.part_t.p;
       A.part64 = (double*)ws.part.p;
@@ -433,7 +510,7 @@ extern "C" int exo_cross_section(exo_ctx* c, int s, double T, double P, int prec
   std::lock_guard<std::mutex> g(c->mu);
   Workspace& ws = c->ws;
   int rc;
-  if ((rc = ws.params.reserve(16 * sizeof(double)))) return rc;
+  if ((rc = ws.reserve(ws.params, 16 * sizeof(double)))) return rc;
   double hp[2] = {T, P};
   double* dp = (double*)ws.params.p;
   const bool fp64 = precision == EXO_FP64;
@@ -524,10 +601,10 @@ int exo::forward_core(exo_ctx* c, Workspace& ws, const exo_atmos* a, int64_t gb,
   const int NL = a->n_layers, M = a->n_species;
   int rc;
   // parameter block: P
-  if ((rc = ws.params.reserve((size_t)NL * sizeof(double)))) return rc;
+  if ((rc = ws.reserve(ws.params, (size_t)NL * sizeof(double)))) return rc;
   if ((rc = ws.stage_params(a->P_bar, NL, (double*)ws.params.p, st))) return rc;
-  if ((rc = ws.layer.reserve((size_t)6 * NL * sizeof(double)))) return rc;
-  if ((rc = ws.col.reserve((size_t)M * NL * sizeof(double)))) return rc;
+  if ((rc = ws.reserve(ws.layer, (size_t)6 * NL * sizeof(double)))) return rc;
+  if ((rc = ws.reserve(ws.col, (size_t)M * NL * sizeof(double)))) return rc;
   double* lay = (double*)ws.layer.p;
   AtmosDev A{};
   A.nlay = NL;
@@ -556,8 +633,10 @@ int exo::forward_core(exo_ctx* c, Workspace& ws, const exo_atmos* a, int64_t gb,
   HIP_TRY(launch_atmos(A, st));
 
   const size_t esz = fp64 ? sizeof(double) : sizeof(float);
-  if ((rc = ws.tau.reserve((size_t)M * NL * gl * esz))) return rc;
-  if (tangent && (rc = ws.taut.reserve((size_t)M * NL * gl * sizeof(float)))) return rc;
+  if ((rc = ws.reserve(ws.tau, (size_t)M * NL * gl * esz))) return rc;
+  if (tangent && (rc = ws.reserve(ws.taut, (size_t)M * NL * gl * sizeof(float)))) return rc;
+  // every species' buffers fit in the largest plan, reserved once up front
+  if ((rc = reserve_opacity(ws, plan_opacity_all(c, a, gl, fp64, tangent)))) return rc;
   const double* d_nu = (const double*)c->d_nu.p + gb;
   for (int m = 0; m < M; ++m) {
     const Species& sp = c->sp[a->species[m]];
@@ -567,7 +646,7 @@ int exo::forward_core(exo_ctx* c, Workspace& ws, const exo_atmos* a, int64_t gb,
                               d_nu, gl, out, out_t, st)))
       return rc;
   }
-  if ((rc = ws.F0.reserve((size_t)gl * sizeof(double)))) return rc;
+  if ((rc = ws.reserve(ws.F0, (size_t)gl * sizeof(double)))) return rc;
   RtArgs R{};
   R.nu = d_nu;
   R.ng = gl;
@@ -590,7 +669,7 @@ int exo::forward_core(exo_ctx* c, Workspace& ws, const exo_atmos* a, int64_t gb,
 int exo::apply_response(Workspace& ws, RespDev& R, const double* F0, void* out, bool out64,
                         hipStream_t st) {
   int rc;
-  if ((rc = ws.taps.reserve((size_t)(3 * R.nrot + 2 * R.K + 1) * sizeof(double)))) return rc;
+  if ((rc = ws.reserve(ws.taps, (size_t)(3 * R.nrot + 2 * R.K + 1) * sizeof(double)))) return rc;
   double* t = (double*)ws.taps.p;
   R.rot = t;
   R.drot_rv = t + R.nrot;
@@ -598,9 +677,37 @@ int exo::apply_response(Workspace& ws, RespDev& R, const double* F0, void* out, 
   R.ip = t + 3 * R.nrot;
   HIP_TRY(launch_taps(R, st));
   if (!out) return EXO_OK;  // taps only (the adjoint needs them without a forward output)
-  if ((rc = ws.mid.reserve((size_t)(R.ol + 2 * R.K) * sizeof(double)))) return rc;
+  if ((rc = ws.reserve(ws.mid, (size_t)(R.ol + 2 * R.K) * sizeof(double)))) return rc;
   HIP_TRY(launch_response(R, F0, (double*)ws.mid.p, out, out64, st));
   return EXO_OK;
+}
+
+size_t exo::estimate_workspace(const exo_ctx* c, const exo_atmos* a, const exo_response* r,
+                               bool fp64, bool vjp) {
+  // mirrors the reservations of forward_core, apply_response and vjp_impl
+  int64_t gb, gl;
+  if (validate_atmos(c, a, &gb, &gl)) return 0;
+  auto R = [](size_t b) { return (b + 255) & ~size_t(255); };
+  const size_t NL = a->n_layers, M = a->n_species;
+  const size_t esz = fp64 ? sizeof(double) : sizeof(float);
+  size_t t = R(NL * 8) + R(6 * NL * 8) + R(M * NL * 8) + R(M * NL * gl * esz) + R(gl * 8);
+  if (vjp) t += R(M * NL * gl * sizeof(float));
+  const OpacityPlan P = plan_opacity_all(c, a, gl, fp64, vjp);
+  for (size_t b : {P.rec, P.core, P.rect, P.rec64, P.part, P.part_t}) t += b ? R(b) : 0;
+  int64_t nmid = 0;
+  if (r) {
+    RespDev RD{};
+    if (prepare_response(c, r, gl, &RD)) return 0;
+    nmid = RD.ol + 2 * RD.K;
+    t += R((3 * RD.nrot + 2 * RD.K + 1) * 8) + R(nmid * 8);
+  }
+  if (vjp) {
+    const size_t nbg = (gl + 255) / 256;
+    t += R(gl * 8);
+    if (r) t += R(nmid * 8) + R(2 * ((nmid + 255) / 256) * 8);
+    t += R(NL * gl * 8) * 2 + R(nbg * NL * 8) + R(nbg * M * 8) + R((4 + M + NL) * 8);
+  }
+  return t;
 }
 
 int exo::emission_impl(exo_ctx* c, Workspace& ws, const exo_atmos* a, const exo_response* r,
@@ -643,26 +750,26 @@ int exo::vjp_impl(exo_ctx* c, Workspace& ws, const exo_atmos* a, const exo_respo
   if ((rc = forward_core(c, ws, a, gb, gl, false, true, st))) return rc;
   const double* F0 = (const double*)ws.F0.p;
   const int64_t nbg = (gl + 255) / 256;
-  if ((rc = ws.F0bar.reserve((size_t)gl * sizeof(double)))) return rc;
+  if ((rc = ws.reserve(ws.F0bar, (size_t)gl * sizeof(double)))) return rc;
   double* F0bar = (double*)ws.F0bar.p;
   int64_t nbR = 0;
   if (r) {
     if ((rc = apply_response(ws, R, F0, flux, false, st))) return rc;
     const int64_t nmid = R.ol + 2 * R.K;
     nbR = (nmid + 255) / 256;
-    if ((rc = ws.midbar.reserve((size_t)nmid * sizeof(double)))) return rc;
-    if ((rc = ws.partR.reserve((size_t)2 * nbR * sizeof(double)))) return rc;
+    if ((rc = ws.reserve(ws.midbar, (size_t)nmid * sizeof(double)))) return rc;
+    if ((rc = ws.reserve(ws.partR, (size_t)2 * nbR * sizeof(double)))) return rc;
     HIP_TRY(launch_response_vjp(R, F0, cot, false, (double*)ws.midbar.p, F0bar, gl,
                                 (double*)ws.partR.p, nbR, st));
   } else {
     if (flux) HIP_TRY(launch_cast_copy(F0, flux, false, gl, st));
     HIP_TRY(launch_to_double(cot, false, F0bar, gl, st));
   }
-  if ((rc = ws.Fup.reserve((size_t)NL * gl * sizeof(double)))) return rc;
-  if ((rc = ws.taubar.reserve((size_t)NL * gl * sizeof(double)))) return rc;
-  if ((rc = ws.partT.reserve((size_t)nbg * NL * sizeof(double)))) return rc;
-  if ((rc = ws.partX.reserve((size_t)nbg * M * sizeof(double)))) return rc;
-  if ((rc = ws.gout.reserve((size_t)(4 + M + NL) * sizeof(double)))) return rc;
+  if ((rc = ws.reserve(ws.Fup, (size_t)NL * gl * sizeof(double)))) return rc;
+  if ((rc = ws.reserve(ws.taubar, (size_t)NL * gl * sizeof(double)))) return rc;
+  if ((rc = ws.reserve(ws.partT, (size_t)nbg * NL * sizeof(double)))) return rc;
+  if ((rc = ws.reserve(ws.partX, (size_t)nbg * M * sizeof(double)))) return rc;
+  if ((rc = ws.reserve(ws.gout, (size_t)(4 + M + NL) * sizeof(double)))) return rc;
   RtArgs Rt = ws.last_rt;
   Rt.F0bar = F0bar;
   Rt.Fup = (double*)ws.Fup.p;

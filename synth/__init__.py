@@ -6,5 +6,5 @@ response).  Both the HIP path and the oracle consume what it returns.
 """
 from .workloads import (  # noqa: F401
     LineList, Atmosphere, Response, Workload, ServingRequest, make_config,
-    eslog_grid, serving_pool, serving_requests, hmc_walk, CONFIG_SEEDS,
+    eslog_grid, serving_pool, serving_requests, serving_atmosphere, hmc_walk, CONFIG_SEEDS,
 )

@@ -255,3 +255,11 @@ def serving_requests(n: int, rate_hz: float, seed: int = CONFIG_SEEDS[5] + 17,
         nl = int(rng.integers(min_layers, max_layers + 1))
         reqs.append(ServingRequest(float(t[i]), sp, j0, nlen, nl, thetas[i]))
     return reqs
+
+
+def serving_atmosphere(req: ServingRequest, log10_mmr_floor: float = -12.0):
+    """(P_bar, T0, alpha, log10 MMR pair, RV, vsini) of a serving request."""
+    P = np.logspace(-8.0, 2.0, req.n_layers)
+    th = req.theta
+    logx = np.log10(np.maximum(th[2:4], 10.0 ** log10_mmr_floor))
+    return P, float(th[0]), float(th[1]), logx, float(th[4]), float(th[5])
