@@ -4,7 +4,8 @@
  *
  * The workload is the one the paper's sampler generates (Sec. 5.3): a stream
  * of spectrum evaluations at nearby parameters, against line lists that stay
- * resident in GPU memory (Sec. 2.5: "reuses the values in the GPU memory").
+ * resident in GPU memory between evaluations (Sec. 2.5 keeps them on the
+ * device across calls for the same reason).
  *
  * Model of operation:
  *   - Requests are queued in arrival order (exo_server_submit copies every
