@@ -44,17 +44,18 @@ struct LineRec {
   float a;        // gamma / (sqrt2 beta)
   float erfcxa;   // erfcx(a)
   float acore;    // amplitude / (sqrt(2 pi) beta): contribution = acore * H(x, a)
-  float C1;       // sum_n v0_n e^{-eta^2 n^2}  (S1 = e^{-x^2} C1)
+  float C1;       // sum_n w_n of LineCore  (S1 = e^{-x^2} C1)
   float pad[2];
 };
 static_assert(sizeof(LineRec) == 64, "LineRec layout");
 
 // Series weights of the core branch for one (line, layer):
-// v0_n = 1 / (eta^2 n^2 + a^2), n = 1..27.
+// w_n = e^{-eta^2 n^2} / (eta^2 n^2 + a^2), n = 1..27 (w[27..31] = 0), in
+// FP64 because e^{-eta^2 n^2} falls below the FP32 range for n >= 19.
 struct LineCore {
-  float v0[32];
+  double w[32];
 };
-static_assert(sizeof(LineCore) == 128, "LineCore layout");
+static_assert(sizeof(LineCore) == 256, "LineCore layout");
 
 // e^{-eta^2 n^2} for eta = 1/2, n = 1..27.
 __device__ constexpr double kGauss916[27] = {
@@ -118,11 +119,10 @@ __device__ inline void make_line_record(double A, double beta, double gam, doubl
     LineCore core;
     for (int n = 1; n <= kM916; ++n) {
       const double en = 0.5 * n;
-      const double v0 = 1.0 / (en * en + a * a);
-      core.v0[n - 1] = (float)v0;
-      c1 += (double)core.v0[n - 1] * kGauss916[n - 1];
+      core.w[n - 1] = kGauss916[n - 1] / (en * en + a * a);
+      c1 += core.w[n - 1];
     }
-    for (int n = kM916; n < 32; ++n) core.v0[n] = 0.f;
+    for (int n = kM916; n < 32; ++n) core.w[n] = 0.0;
     r.C1 = (float)c1;
     if (RC) *RC = core;
   }
@@ -161,89 +161,59 @@ __device__ inline void make_line_record(double A, double beta, double gam, doubl
 }
 
 // ---------------------------------------------------------------------------
-// Algorithm-916 series (Eq. algo916) with eta = 1/2, M = 27, in FP32.  With
-// L != nullptr also the imaginary part (App. C), read as
+// Algorithm-916 series (Eq. algo916) with eta = 1/2, M = 27.  With
+// Lout != nullptr also the imaginary part (App. C), read as
 //   L = -e^{-x^2} erfcx(a) sin 2xa + (2 eta x/pi) e^{-x^2} sinc(2ax/pi)
 //       + (2 eta/pi) [a sin(2ax) S1 - S4/2 + S5/2],
 // the reading that reproduces the Dawson limit L(x, 0) = 2 D(x)/sqrt(pi).
+//
+// Evaluation: the Gaussians factorise exactly,
+//   e^{-(eta n -/+ x)^2} = e^{-x^2} e^{-eta^2 n^2} X^{+/-n},  X = e^x,
+// so with the per-(line, layer) weights w_n = e^{-eta^2 n^2}/(eta^2 n^2 + a^2)
+// and C1 = sum_n w_n,
+//   S1 = e^{-x^2} C1,  S2 + S3 = e^{-x^2} sum_n w_n (X^n + X^-n),
+//   S5 - S4 = e^{-x^2} sum_n (eta n) w_n (X^n - X^-n).
+// X^n + X^-n and X^n - X^-n obey u_{n+1} = (X + 1/X) u_n - u_{n-1}, one FMA
+// per term in FP64, where e^{-x^2} X^27 (x^2 + a^2 < 111) stays in range.
+// sin 2ax and cos 2ax come from sin ax, cos ax by the double-angle formulas.
+// Same terms and same M as the series; only the order of operations differs.
 // ---------------------------------------------------------------------------
-__device__ inline float hjert_core_f32(float x, float a, float erfcxa, float* L) {
-  constexpr float twoeta_pi = 2.0f * 0.5f / 3.14159265358979f;
-  const float ex2 = __expf(-x * x);
-  float s2, c2;
-  sincosf(2.0f * x * a, &s2, &c2);
-  const float a2 = a * a;
-  float S1 = 0.f, S2 = 0.f, S3 = 0.f, S4 = 0.f, S5 = 0.f;
-#pragma unroll 3
-  for (int n = 1; n <= kM916; ++n) {
-    const float en = kEta * (float)n;
-    const float v0 = 1.0f / (en * en + a2);
-    const float gn = __expf(-en * en);          // constant per n
-    const float tp = en + x, tm = en - x;
-    const float e2 = __expf(-tp * tp), e3 = __expf(-tm * tm);
-    S1 = fmaf(v0, gn, S1);
-    S2 = fmaf(v0, e2, S2);
-    S3 = fmaf(v0, e3, S3);
-    if (L) {
-      const float w = en * v0;
-      S4 = fmaf(w, e2, S4);
-      S5 = fmaf(w, e3, S5);
-    }
-  }
-  S1 *= ex2;
-  const float ax = a * x;
-  float sax = sinf(ax);
-  // (2 eta x sin(ax)/pi) e^{-x^2} sinc(ax/pi), sinc(u) = sin(pi u)/(pi u)
-  const float t2 = (ax != 0.f) ? twoeta_pi * ex2 * sax * sax / a : 0.f;
-  const float H = ex2 * erfcxa * c2 + t2 + twoeta_pi * a * (-c2 * S1 + 0.5f * S2 + 0.5f * S3);
-  if (L) {
-    // (2 eta x/pi) e^{-x^2} sinc(2ax/pi) = (2 eta/pi) e^{-x^2} x sin(2ax)/(2ax)
-    const float t2l = (ax != 0.f) ? twoeta_pi * ex2 * s2 / (2.0f * a) : twoeta_pi * ex2 * x;
-    *L = -ex2 * erfcxa * s2 + t2l + twoeta_pi * (a * s2 * S1 - 0.5f * S4 + 0.5f * S5);
-  }
-  return H;
-}
-
-// The same Algorithm-916 series evaluated through an exact factorisation of
-// its Gaussians, e^{-(eta n -/+ x)^2} = e^{-x^2} e^{-eta^2 n^2} e^{+/-2 eta n x}
-// (eta = 1/2, so e^{2 eta n x} = X^n with X = e^x), accumulated in FP64 where
-// X^27 e^{-x^2} and e^{-n^2/4} stay in range.  v0[n-1] = 1/(eta^2 n^2 + a^2)
-// and C1 = sum_n v0_n e^{-eta^2 n^2} come with the line record.  Same terms,
-// same M = 27; only the order of the multiplications differs.
 template <bool WANT_L>
 __device__ __forceinline__ float hjert_core_fac(float xf, float af, float erfcxa, float C1,
-                                                const float* __restrict__ v0, float* Lout) {
+                                                const double* __restrict__ wn, float* Lout) {
   constexpr double twoeta_pi = 1.0 / kPi;  // 2 eta / pi
   const double x = (double)xf, a = (double)af;
   const double ex2 = exp(-x * x);
   const double X = exp(x), Y = 1.0 / X;
-  double Xn = 1.0, Yn = 1.0, s2 = 0.0, s3 = 0.0, s4 = 0.0, s5 = 0.0;
-#pragma unroll 1
+  const double k = X + Y;
+  double c0 = 2.0, c1 = k, d0 = 0.0, d1 = X - Y, sc = 0.0, sd = 0.0;
+  constexpr int kUnroll = WANT_L ? 9 : 3;
+#pragma unroll kUnroll
   for (int n = 1; n <= kM916; ++n) {
-    Xn *= X;
-    Yn *= Y;
-    const double w = (double)v0[n - 1] * kGauss916[n - 1];
-    s3 = fma(w, Xn, s3);   // sum v0 e^{-(eta n - x)^2} / e^{-x^2}
-    s2 = fma(w, Yn, s2);   // sum v0 e^{-(eta n + x)^2} / e^{-x^2}
+    const double w = wn[n - 1];
+    sc = fma(w, c1, sc);
+    const double c2 = fma(k, c1, -c0);
+    c0 = c1;
+    c1 = c2;
     if (WANT_L) {
-      const double ew = (0.5 * n) * w;
-      s5 = fma(ew, Xn, s5);
-      s4 = fma(ew, Yn, s4);
+      sd = fma(w * (0.5 * n), d1, sd);
+      const double d2 = fma(k, d1, -d0);
+      d0 = d1;
+      d1 = d2;
     }
   }
   const double S1 = ex2 * (double)C1;
   const float ax = af * xf;
-  float s2xa, c2xa;
-  sincosf(2.0f * ax, &s2xa, &c2xa);
-  const float sax = sinf(ax);
+  float sax, cax;
+  sincosf(ax, &sax, &cax);
+  const double sa = (double)sax, ca = (double)cax;
+  const double s2xa = 2.0 * sa * ca, c2xa = 1.0 - 2.0 * sa * sa;
   // (2 eta x sin(ax)/pi) e^{-x^2} sinc(ax/pi) = (2 eta/pi) e^{-x^2} sin^2(ax)/a
-  const double t2 = (ax != 0.f) ? twoeta_pi * ex2 * (double)sax * (double)sax / a : 0.0;
-  const double H = ex2 * (double)erfcxa * (double)c2xa + t2 +
-                   twoeta_pi * a * (-(double)c2xa * S1 + 0.5 * ex2 * (s2 + s3));
+  const double t2 = (ax != 0.f) ? twoeta_pi * ex2 * sa * sa / a : 0.0;
+  const double H = ex2 * (double)erfcxa * c2xa + t2 + twoeta_pi * a * (-c2xa * S1 + 0.5 * ex2 * sc);
   if (WANT_L) {
-    const double t2l = (ax != 0.f) ? twoeta_pi * ex2 * (double)s2xa / (2.0 * a) : twoeta_pi * ex2 * x;
-    *Lout = (float)(-ex2 * (double)erfcxa * (double)s2xa + t2l +
-                    twoeta_pi * (a * (double)s2xa * S1 + 0.5 * ex2 * (s5 - s4)));
+    const double t2l = (ax != 0.f) ? twoeta_pi * ex2 * s2xa / (2.0 * a) : twoeta_pi * ex2 * x;
+    *Lout = (float)(-ex2 * (double)erfcxa * s2xa + t2l + twoeta_pi * (a * s2xa * S1 + 0.5 * ex2 * sd));
   }
   return (float)H;
 }

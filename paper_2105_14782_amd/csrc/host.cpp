@@ -378,7 +378,7 @@ static LinesDev lines_dev(const Species& sp) {
 
 // Record-buffer budget per workspace (bytes); layers are processed in chunks
 // that fit it.
-static constexpr size_t kRecBudget = size_t(3) << 30;
+static constexpr size_t kRecBudget = size_t(4) << 30;
 
 // Split over lines when the grid x layer tiles of one launch cannot fill the
 // device (fixed by the shape only, so results never depend on the load).
@@ -408,12 +408,13 @@ OpacityPlan exo::plan_opacity(int64_t n_lines, int nlay, int64_t ng, bool fp64, 
     P.core = (size_t)P.nlc * n_lines * sizeof(LineCore);
     if (tangent) P.rect = (size_t)P.nlc * n_lines * sizeof(LineRecT);
   }
-  // partial sums: the largest over the chunk sizes that occur
+  // partial sums (the FP32 sum always passes its far-line state through
+  // them): the largest over the chunk sizes that occur
   for (int nl : {P.nlc, nlay % P.nlc}) {
     if (nl <= 0) continue;
     int64_t ks, lps;
     split_plan(ng, nl, n_lines, fp64, &ks, &lps);
-    if (ks > 1) {
+    if (ks > 1 || !fp64) {
       const size_t pb = (size_t)ks * nl * ng * (fp64 ? sizeof(double) : sizeof(float2));
       P.part = std::max(P.part, pb);
       if (!fp64 && tangent) P.part_t = std::max(P.part_t, pb);
@@ -486,7 +487,7 @@ int exo::species_opacity(exo_ctx* c, Workspace& ws, const Species& sp, const dou
     split_plan(ng, nl, sp.n, fp64, &ks, &lps);
     A.lines_per_split = lps;
     A.ksplit = (int)ks;
-    if (ks > 1) {
+    if (ks > 1 || !fp64) {
       A.part = (float2*)ws.part.p;
       A.part_t = (float2*)ws.part_t.p;
       A.part64 = (double*)ws.part.p;

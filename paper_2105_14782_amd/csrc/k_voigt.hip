@@ -123,6 +123,35 @@ __global__ __launch_bounds__(256) void k_line_records(LinesDev L, const double* 
 // ---------------------------------------------------------------------------
 constexpr int kChunk = 32;
 
+// ---------------------------------------------------------------------------
+// Far tier.  In the asymptotic branch the contribution is r P(r) with
+// r = 1/D and the degree-6 polynomial of make_line_record, whose k-th term is
+// of order (beta^2 r)^ceil(k/2) relative to 1 (gamma^2 r <= 1).  Where
+// beta^2 r <= kFarU, the terms after r^2 change the sum by at most 8e-9
+// relative and the tangent terms after r^3 by at most 4e-8 of the tangent's
+// scale: below FP32 rounding.  Those pairs drop the higher terms and the core
+// test.
+//
+// The Doppler width is proportional to the line centre (Eq. thermal) and the
+// lines are sorted by centre, so the last line of a layer has the largest
+// beta^2.  Every line farther than reach = sqrt(beta_max^2 / kFarU) from all
+// grid points a wave owns satisfies the bound at all of them, and these lines
+// are a prefix and a suffix of the sorted list, found by binary search.
+// ---------------------------------------------------------------------------
+constexpr double kFarU = 2e-5;
+
+// first index i in [lo, hi) with a[i] >= v (strict: a[i] > v); hi if none
+template <bool STRICT>
+__device__ inline int search_sorted(const double* __restrict__ a, int lo, int hi, double v) {
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    const bool left = STRICT ? a[mid] <= v : a[mid] < v;
+    if (left) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
 __device__ inline void neumaier(float& s, float& c, float v) {
   const float t = s + v;
   if (fabsf(s) >= fabsf(v)) c += (s - t) + v;
@@ -133,41 +162,108 @@ __device__ inline void neumaier(float& s, float& c, float v) {
 // Forward-only core evaluation kept out of line: its FP64 temporaries would
 // otherwise set the register budget of the whole loop and halve occupancy.
 __device__ __attribute__((noinline)) float core_value(float x, float a, float erfcxa, float C1,
-                                                      const float* __restrict__ v0) {
-  return hjert_core_fac<false>(x, a, erfcxa, C1, v0, nullptr);
+                                                      const double* __restrict__ wn) {
+  return hjert_core_fac<false>(x, a, erfcxa, C1, wn, nullptr);
 }
 
-template <bool TAN, int G>
-__global__ __launch_bounds__(256) void k_voigt_f32(VoigtArgs A) {
-  const int y = blockIdx.y;
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int64_t tile0 = (int64_t)blockIdx.x * (256 * G);
-  const double* __restrict__ nu = A.nu;
-  double nuj[G];
+// Tangent-mode core evaluation, (H, L), likewise out of line.
+__device__ __attribute__((noinline)) float2 core_value_tan(float x, float a, float erfcxa, float C1,
+                                                           const double* __restrict__ wn) {
+  float L;
+  const float H = hjert_core_fac<true>(x, a, erfcxa, C1, wn, &L);
+  return make_float2(H, L);
+}
+
+// Grid points of thread (wave w, lane): j = tile0 + (w*G + g)*64 + lane.
+// Points past the end repeat the last one (their sums are not stored).
+template <int G>
+__device__ __forceinline__ void load_points(const VoigtArgs& A, int64_t tile0, int w, int lane,
+                                            double (&nuj)[G]) {
 #pragma unroll
   for (int g = 0; g < G; ++g) {
     const int64_t j = tile0 + (int64_t)(w * G + g) * 64 + lane;
-    nuj[g] = nu[j < A.ng ? j : A.ng - 1];
+    nuj[g] = A.nu[j < A.ng ? j : A.ng - 1];
   }
-  // line range of this split (n_lines < 2^31 is checked on the host)
-  const int lb = (int)blockIdx.z * (int)A.lines_per_split;
-  const int le = min(lb + (int)A.lines_per_split, (int)A.n_lines);
-  const LineRec* __restrict__ R = A.rec + (int64_t)y * A.n_lines;
-  const LineRecT* __restrict__ RT = TAN ? A.rect + (int64_t)y * A.n_lines : nullptr;
-  const LineCore* __restrict__ RC = A.core + (int64_t)y * A.n_lines;
-  const double* __restrict__ nuc = A.nu_c;
+}
 
-  float s[G], c[G], ts[G], tc[G];
-#pragma unroll
-  for (int g = 0; g < G; ++g) s[g] = c[g] = ts[g] = tc[g] = 0.f;
+// Near lines [i0, i1) of wave w within [lb, le); the rest of [lb, le) is far.
+template <int G>
+__device__ __forceinline__ void near_range(const VoigtArgs& A, const LineRec* __restrict__ R,
+                                           int64_t tile0, int w, int lb, int le, int& i0, int& i1) {
+  const int64_t jw = tile0 + (int64_t)w * G * 64, jlast = A.ng - 1;
+  const double lo = A.nu[jw < jlast ? jw : jlast];
+  const double hi = A.nu[jw + G * 64 - 1 < jlast ? jw + G * 64 - 1 : jlast];
+  // beta_max^2 from the threshold 2 * 111 beta^2, with margin for its rounding
+  const double bmax = (double)R[A.n_lines - 1].thr * (1.001 / (2.0 * kHjertSwitch));
+  const double reach = sqrt(bmax / kFarU);
+  i0 = __builtin_amdgcn_readfirstlane(search_sorted<false>(A.nu_c, lb, le, lo - reach));
+  i1 = __builtin_amdgcn_readfirstlane(search_sorted<true>(A.nu_c, i0, le, hi + reach));
+}
 
-  for (int l0 = lb; l0 < le; l0 += kChunk) {
-    const int l1 = min(l0 + kChunk, le);
+// Far lines [sb, se): truncated wing polynomial, no core branch.
+template <bool TAN, int G>
+__device__ __forceinline__ void far_lines(int sb, int se, const LineRec* __restrict__ R,
+                                          const LineRecT* __restrict__ RT,
+                                          const double* __restrict__ nuc, const double (&nuj)[G],
+                                          float (&s)[G], float (&c)[G], float (&ts)[G],
+                                          float (&tc)[G]) {
+  for (int l0 = sb; l0 < se; l0 += kChunk) {
+    const int l1 = min(l0 + kChunk, se);
     float blk[G], tblk[G];
 #pragma unroll
     for (int g = 0; g < G; ++g) blk[g] = tblk[g] = 0.f;
     // the next line's record is requested one iteration ahead so that the
     // scalar-load latency overlaps the current line's arithmetic
+    float4 en = *reinterpret_cast<const float4*>(R[l0].e);
+    float g2n = R[l0].gam2;
+    double nun = nuc[l0];
+    float4 tn;
+    if (TAN) tn = *reinterpret_cast<const float4*>(RT[l0].t);
+#pragma unroll 2
+    for (int l = l0; l < l1; ++l) {
+      const float4 e = en;
+      const float g2 = g2n;
+      const double nul = nun;
+      float4 t;
+      if (TAN) t = tn;
+      const int ln = l + 1 < l1 ? l + 1 : l;
+      en = *reinterpret_cast<const float4*>(R[ln].e);
+      g2n = R[ln].gam2;
+      nun = nuc[ln];
+      if (TAN) tn = *reinterpret_cast<const float4*>(RT[ln].t);
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        const float d = (float)(nuj[g] - nul);  // FP64 offset, rounded once
+        const float r = __builtin_amdgcn_rcpf(fmaf(d, d, g2));
+        const float h = fmaf(fmaf(e.z, r, e.y), r, e.x);
+        blk[g] = fmaf(h, r, blk[g]);
+        if (TAN) {
+          const float ht = fmaf(fmaf(fmaf(t.w, r, t.z), r, t.y), r, t.x);
+          tblk[g] = fmaf(ht, r, tblk[g]);
+        }
+      }
+    }
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      neumaier(s[g], c[g], blk[g]);
+      if (TAN) neumaier(ts[g], tc[g], tblk[g]);
+    }
+  }
+}
+
+// Near lines [sb, se): full wing polynomial, Algorithm-916 series in the core.
+template <bool TAN, int G>
+__device__ __forceinline__ void near_lines(int sb, int se, const LineRec* __restrict__ R,
+                                           const LineRecT* __restrict__ RT,
+                                           const LineCore* __restrict__ RC,
+                                           const double* __restrict__ nuc, const double (&nuj)[G],
+                                           float (&s)[G], float (&c)[G], float (&ts)[G],
+                                           float (&tc)[G]) {
+  for (int l0 = sb; l0 < se; l0 += kChunk) {
+    const int l1 = min(l0 + kChunk, se);
+    float blk[G], tblk[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) blk[g] = tblk[g] = 0.f;
     LineRec qn = R[l0];
     double nun = nuc[l0];
     LineRecT qtn;
@@ -215,8 +311,8 @@ __global__ __launch_bounds__(256) void k_voigt_f32(VoigtArgs A) {
           if (D[g] < q.thr) {
             const float x = dd[g] * q.winv;
             if (TAN) {
-              float L;
-              const float H = hjert_core_fac<true>(x, q.a, q.erfcxa, q.C1, RC[l].v0, &L);
+              const float2 HL = core_value_tan(x, q.a, q.erfcxa, q.C1, RC[l].w);
+              const float H = HL.x, L = HL.y;
               // custom derivatives of Sec. 2.1.1:
               //   dH/dx = 2aL - 2xH,  dH/da = 2xL + 2aH - 2/sqrt(pi)
               const float Hx = 2.0f * (q.a * L - x * H);
@@ -224,7 +320,7 @@ __global__ __launch_bounds__(256) void k_voigt_f32(VoigtArgs A) {
               f[g] = q.acore * H;
               ft[g] = q.acore * (qt.kA * H + Hx * x * qt.kw + Ha * qt.da);
             } else {
-              f[g] = q.acore * core_value(x, q.a, q.erfcxa, q.C1, RC[l].v0);
+              f[g] = q.acore * core_value(x, q.a, q.erfcxa, q.C1, RC[l].w);
             }
           }
         }
@@ -241,13 +337,44 @@ __global__ __launch_bounds__(256) void k_voigt_f32(VoigtArgs A) {
       if (TAN) neumaier(ts[g], tc[g], tblk[g]);
     }
   }
+}
+
+// One (tile, layer, split): far prefix, near lines, far suffix, each summed
+// in blocks of kChunk lines into the compensated accumulator.
+template <bool TAN, int G>
+__global__ __launch_bounds__(256) void k_voigt_f32(VoigtArgs A) {
+  const int y = blockIdx.y;
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t tile0 = (int64_t)blockIdx.x * (256 * G);
+  double nuj[G];
+  load_points<G>(A, tile0, w, lane, nuj);
+  // line range of this split (n_lines < 2^31 is checked on the host)
+  const int lb = (int)blockIdx.z * (int)A.lines_per_split;
+  const int le = min(lb + (int)A.lines_per_split, (int)A.n_lines);
+  const LineRec* __restrict__ R = A.rec + (int64_t)y * A.n_lines;
+  const LineRecT* __restrict__ RT = TAN ? A.rect + (int64_t)y * A.n_lines : nullptr;
+  const LineCore* __restrict__ RC = A.core + (int64_t)y * A.n_lines;
+  int i0, i1;
+  near_range<G>(A, R, tile0, w, lb, le, i0, i1);
+
+  float s[G], c[G], ts[G], tc[G];
+#pragma unroll
+  for (int g = 0; g < G; ++g) s[g] = c[g] = ts[g] = tc[g] = 0.f;
+#pragma unroll 1
+  for (int seg = 0; seg < 2; ++seg) {
+    const int sb = seg == 0 ? lb : i1;
+    const int se = seg == 0 ? i0 : le;
+    far_lines<TAN, G>(sb, se, R, RT, A.nu_c, nuj, s, c, ts, tc);
+    if (seg == 0) near_lines<TAN, G>(i0, i1, R, RT, RC, A.nu_c, nuj, s, c, ts, tc);
+  }
 
 #pragma unroll
   for (int g = 0; g < G; ++g) {
     const int64_t j = tile0 + (int64_t)(w * G + g) * 64 + lane;
     if (j >= A.ng) continue;
-    const int64_t o = (int64_t)y * A.ld_out + j;
     if (A.ksplit == 1) {
+      const int64_t o = (int64_t)y * A.ld_out + j;
       A.out[o] = (s[g] + c[g]) * A.out_scale;
       if (TAN) A.out_t[o] = (ts[g] + tc[g]) * A.out_scale;
     } else {
@@ -344,7 +471,7 @@ __global__ __launch_bounds__(256) void k_hjert_f32(int64_t n, const float* __res
   float f = h * r;
   float l = 0.f;
   if (D < q.thr) {
-    f = q.acore * hjert_core_fac<true>(d * q.winv, q.a, q.erfcxa, q.C1, qc.v0, &l);
+    f = q.acore * hjert_core_fac<true>(d * q.winv, q.a, q.erfcxa, q.C1, qc.w, &l);
   } else if (L) {
     hjert_asy_f32(d, q.a, &l);
   }
