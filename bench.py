@@ -28,10 +28,13 @@ sys.path.insert(0, ROOT)
 METRIC = "Voigt evals/s (lines×grid×layers) + spectra/s & p99 latency, FP32 vs FP64 @1e-4"
 PEAK_FP32_TFLOPS = 157.3      # MI355X published FP32 vector peak (packed FMA)
 # Algorithmic FP32 operations per (line, grid point, layer) pair of the Voigt
-# sum in tangent mode (wing branch, FMA = 2): offset 1, D 2, 1/D 1, value
-# polynomial 12 + 1, tangent polynomial 14 + 1, two accumulations 2.
-FLOPS_PER_EVAL_TANGENT = 34.0
-FLOPS_PER_EVAL_FORWARD = 18.0
+# sum in tangent mode (FMA = 2).  Near tier (full wing polynomial; core pairs
+# are counted at this rate too): offset 1, D 2, 1/D 1, value polynomial
+# 12 + 1, tangent polynomial 14 + 1, two accumulations 2.  Far tier
+# (polynomial truncated below FP32 rounding): offset 1, D 2, 1/D 1, value
+# polynomial 4, tangent polynomial 6, two accumulations 4.
+FLOPS_PER_EVAL_NEAR = 34.0
+FLOPS_PER_EVAL_FAR = 18.0
 
 
 def parse():
@@ -42,11 +45,15 @@ def parse():
     ap.add_argument("--size", default="full", choices=["small", "medium", "full"])
     ap.add_argument("--fp64-reps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-points", type=int, default=16)
+    ap.add_argument("--cpu-points", type=int, default=192)
     ap.add_argument("--serve-requests", type=int, default=48,
                     help="requests of the Poisson serving run (0: skip)")
     ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write the traffic summary from two --pmc runs of --counters and exit")
+    ap.add_argument("--summarize-valu", metavar="VALU_CSV",
+                    help="write the VALU-issue summary from a --pmc run of --counters and exit")
+    ap.add_argument("--summarize-stats", metavar="STATS_CSV",
+                    help="write the kernel-time summary from a rocprofv3 --stats run and exit")
     ap.add_argument("--counters", action="store_true",
                     help="one step plus a 512 MiB device copy (calibration), for rocprofv3 --pmc runs")
     return ap.parse_args()
@@ -148,6 +155,76 @@ def summarize_counters(fetch_csv, write_csv, out_path):
     print("\n".join(lines))
 
 
+VALU_PROFILE = "profiles/voigt_tangent_config2_valu.md"
+STATS_PROFILE = "profiles/voigt_config2_kernel_stats.md"
+VALU_COUNTERS = "SQ_INSTS_VALU SQ_INSTS_VALU_TRANS_F32 SQ_ACTIVE_INST_VALU SQ_BUSY_CYCLES GRBM_GUI_ACTIVE"
+
+
+def summarize_valu(csv_path, out_path):
+    """VALU issue of the tangent Voigt launches from one rocprofv3 --pmc run of
+    `bench.py --counters`: wave instructions per 64 pairs and the fraction of
+    the SIMDs' issue cycles they occupy (a non-packed FP32 or FP64 VALU
+    instruction of a 64-wide wave holds a 16-lane SIMD for 4 cycles)."""
+    import csv
+    acc = {}
+    for r in csv.DictReader(open(csv_path)):
+        if "k_voigt_f32<true" in r["Kernel_Name"]:
+            acc.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    m = {k: float(np.mean(v)) for k, v in acc.items()}
+    n = len(acc["SQ_INSTS_VALU"])
+    pairs = 1e5 * 2e4 * 100
+    groups = pairs / 64.0
+    xcd = 8
+    cycles = m["GRBM_GUI_ACTIVE"] / xcd          # summed over the 8 XCDs
+    simds = 256 * 4
+    issue = m["SQ_INSTS_VALU"] * 4.0 / (simds * cycles)
+    lines = [
+        "# VALU issue of the tangent-mode Voigt sum (config-2 emission, one species per launch)", "",
+        "Command (repository root, one MI355X):", "", "```",
+        f"rocprofv3 --pmc {VALU_COUNTERS} --output-format csv -d gpurun_out/pmc_valu -o run -- "
+        "python3 bench.py --counters --warmup 1",
+        "python3 bench.py --summarize-valu gpurun_out/pmc_valu/run_counter_collection.csv", "```", "",
+        f"Launches measured: {n} (1e5 lines x 20,000 points x 100 layers = 2e11 pairs each).", "",
+        f"- SQ_INSTS_VALU per launch: {m['SQ_INSTS_VALU']:.4e} wave instructions "
+        f"= {m['SQ_INSTS_VALU'] / groups:.2f} per 64 pairs",
+        f"- SQ_INSTS_VALU_TRANS_F32 per launch: {m['SQ_INSTS_VALU_TRANS_F32']:.4e} "
+        f"= {m['SQ_INSTS_VALU_TRANS_F32'] / groups:.3f} per 64 pairs (the reciprocal 1/D, plus core-branch transcendentals)",
+        f"- GRBM_GUI_ACTIVE per launch: {m['GRBM_GUI_ACTIVE']:.4e} (8 XCDs) = {cycles:.4e} cycles per XCD",
+        f"- SQ_BUSY_CYCLES per launch: {m['SQ_BUSY_CYCLES']:.4e}",
+        f"- SQ_ACTIVE_INST_VALU per launch: {m['SQ_ACTIVE_INST_VALU']:.4e}",
+        f"- VALU issue occupancy (instructions x 4 cycles / (1024 SIMDs x cycles)): {issue:.3f}",
+        "",
+        "Transcendental instructions (v_rcp_f32 and the like) run at a quarter of the",
+        "VALU rate, so with them the SIMDs are busier than the occupancy above; the",
+        "kernel is bound by VALU issue, not by memory.",
+    ]
+    open(out_path, "w").write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def summarize_stats(csv_path, out_path):
+    """Markdown table of a rocprofv3 --kernel-trace --stats run of the bench."""
+    import csv
+    rows = list(csv.DictReader(open(csv_path)))
+    lines = [
+        "# Kernel trace summary: config-2 emission bench (rocprofv3 --kernel-trace --stats)", "",
+        "Command (repository root, one MI355X):", "", "```",
+        "rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/prof_bench -o bench -- \\",
+        "    python3 bench.py --steps 3 --warmup 1 --no-cpu-baseline --fp64-reps 1 --serve-requests 0",
+        "python3 bench.py --summarize-stats gpurun_out/prof_bench/bench_kernel_stats.csv", "```", "",
+        "Workload: 2 species x 1e5 lines, 20,000-point log-uniform grid, 100 layers.",
+        "The run does 1 warm-up + 3 timed flux_vjp steps (two tangent-mode Voigt sums each),",
+        "then 4 FP32 forward spectra and 2 plain-FP64 forward spectra (two Voigt sums each).", "",
+        "| kernel | calls | avg ms | total ms | % |", "|---|---:|---:|---:|---:|",
+    ]
+    for r in rows:
+        name = r["Name"] if len(r["Name"]) <= 70 else r["Name"][:67] + "..."
+        lines.append(f"| `{name}` | {r['Calls']} | {float(r['AverageNs']) / 1e6:.3f} | "
+                     f"{float(r['TotalDurationNs']) / 1e6:.2f} | {float(r['Percentage']):.2f} |")
+    open(out_path, "w").write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 SERVE_MARGIN = 260   # output margin (points) at R0 = 1e6: rotation + RV + 6-sigma IP reach < 200
 
 
@@ -204,6 +281,12 @@ def main():
     if args.summarize_counters:
         summarize_counters(*args.summarize_counters, os.path.join(ROOT, TRAFFIC_PROFILE))
         return
+    if args.summarize_valu:
+        summarize_valu(args.summarize_valu, os.path.join(ROOT, VALU_PROFILE))
+        return
+    if args.summarize_stats:
+        summarize_stats(args.summarize_stats, os.path.join(ROOT, STATS_PROFILE))
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
                           "n_gpus": args.gpus}))
@@ -256,6 +339,7 @@ def main():
     torch.cuda.synchronize()
     T = time.perf_counter() - t0
     nl, kms, kevals = ctx.profile_read()
+    knear = ctx.profile_read_near()
     ctx.profile(False)
     lat = np.array([a.elapsed_time(b) for a, b in ev])
     ms = 1e3 * T / args.steps
@@ -274,7 +358,7 @@ def main():
     t64 = time_fwd("fp64", args.fp64_reps)
 
     avg_launch_ms = kms / max(nl, 1)
-    flops_per_launch = FLOPS_PER_EVAL_TANGENT * kevals / max(nl, 1)
+    flops_per_launch = (FLOPS_PER_EVAL_NEAR * knear + FLOPS_PER_EVAL_FAR * (kevals - knear)) / max(nl, 1)
     achieved = flops_per_launch / (avg_launch_ms * 1e-3) / 1e12
     out = {
         "metric": METRIC,
@@ -302,7 +386,10 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS, "traffic": recorded_traffic(),
                      "kernel": "k_voigt_f32<tangent>", "avg_launch_ms": avg_launch_ms,
-                     "launches": nl, "flops_per_eval": FLOPS_PER_EVAL_TANGENT},
+                     "launches": nl, "evals_per_launch": kevals / max(nl, 1),
+                     "near_fraction": knear / max(kevals, 1.0),
+                     "flops_per_eval": {"near": FLOPS_PER_EVAL_NEAR, "far": FLOPS_PER_EVAL_FAR},
+                     "evals_per_s": kevals / (kms * 1e-3)},
     }
     ctx.close()
     if args.serve_requests > 0:

@@ -224,6 +224,11 @@ int exo_profile_enable(exo_ctx* ctx, int on);
  * (lines x grid points x layers) they performed. */
 int exo_profile_read(exo_ctx* ctx, int64_t* n_launches, double* total_ms,
                      double* total_evals);
+/* Of those evaluations, the number the FP32 launches summed with the full
+ * wing polynomial and the core test (the near tier); the rest used the
+ * truncated far-tier polynomial.  Synchronises like exo_profile_read.
+ * Errors: EXO_EINVAL, EXO_EDEVICE. */
+int exo_profile_read_near(exo_ctx* ctx, double* near_evals);
 
 #ifdef __cplusplus
 }

@@ -90,6 +90,7 @@ def load_library(path: str = LIB_PATH):
         "exo_trans2e3": ([I64, V, V, V, V], I),
         "exo_profile_enable": ([V, I], I),
         "exo_profile_read": ([V, ctypes.POINTER(I64), ctypes.POINTER(D), ctypes.POINTER(D)], I),
+        "exo_profile_read_near": ([V, ctypes.POINTER(D)], I),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)

@@ -209,6 +209,12 @@ class Context:
         L.check(self._lib.exo_profile_read(self._h, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(ev)))
         return n.value, ms.value, ev.value
 
+    def profile_read_near(self) -> float:
+        """Pair evaluations of the profiled FP32 launches done in the near tier."""
+        ev = ctypes.c_double()
+        L.check(self._lib.exo_profile_read_near(self._h, ctypes.byref(ev)))
+        return ev.value
+
 
 def hjert_f32(x: torch.Tensor, a: torch.Tensor, want_L: bool = False, stream=None):
     lib = L.load_library()

@@ -45,7 +45,8 @@ struct LineRec {
   float erfcxa;   // erfcx(a)
   float acore;    // amplitude / (sqrt(2 pi) beta): contribution = acore * H(x, a)
   float C1;       // sum_n w_n of LineCore  (S1 = e^{-x^2} C1)
-  float pad[2];
+  float ainv;     // 1 / a (infinite for a = 0, where it is not used)
+  float pad;
 };
 static_assert(sizeof(LineRec) == 64, "LineRec layout");
 
@@ -126,7 +127,8 @@ __device__ inline void make_line_record(double A, double beta, double gam, doubl
     r.C1 = (float)c1;
     if (RC) *RC = core;
   }
-  r.pad[0] = r.pad[1] = 0.f;
+  r.ainv = (float)(1.0 / (gam * winv));
+  r.pad = 0.f;
   *R = r;
   if (RT) {
     // db/dT, dg/dT
@@ -178,13 +180,17 @@ __device__ inline void make_line_record(double A, double beta, double gam, doubl
 // sin 2ax and cos 2ax come from sin ax, cos ax by the double-angle formulas.
 // Same terms and same M as the series; only the order of operations differs.
 // ---------------------------------------------------------------------------
-template <bool WANT_L>
-__device__ __forceinline__ float hjert_core_fac(float xf, float af, float erfcxa, float C1,
-                                                const double* __restrict__ wn, float* Lout) {
+template <bool WANT_L, typename WeightPtr>
+__device__ __forceinline__ float hjert_core_fac(float xf, float af, float ainv, float erfcxa, float C1,
+                                                WeightPtr wn, float* Lout) {
   constexpr double twoeta_pi = 1.0 / kPi;  // 2 eta / pi
-  const double x = (double)xf, a = (double)af;
+  const double x = (double)xf;
   const double ex2 = exp(-x * x);
-  const double X = exp(x), Y = 1.0 / X;
+  const double X = exp(x);
+  // 1/X: hardware reciprocal and two Newton steps (X lies in [e^-10.6, e^10.6])
+  double Y = __builtin_amdgcn_rcp(X);
+  Y = fma(Y, fma(-X, Y, 1.0), Y);
+  Y = fma(Y, fma(-X, Y, 1.0), Y);
   const double k = X + Y;
   double c0 = 2.0, c1 = k, d0 = 0.0, d1 = X - Y, sc = 0.0, sd = 0.0;
   constexpr int kUnroll = WANT_L ? 9 : 3;
@@ -202,17 +208,18 @@ __device__ __forceinline__ float hjert_core_fac(float xf, float af, float erfcxa
       d1 = d2;
     }
   }
-  const double S1 = ex2 * (double)C1;
+  const double a = (double)af, S1 = ex2 * (double)C1;
   const float ax = af * xf;
   float sax, cax;
   sincosf(ax, &sax, &cax);
   const double sa = (double)sax, ca = (double)cax;
   const double s2xa = 2.0 * sa * ca, c2xa = 1.0 - 2.0 * sa * sa;
   // (2 eta x sin(ax)/pi) e^{-x^2} sinc(ax/pi) = (2 eta/pi) e^{-x^2} sin^2(ax)/a
-  const double t2 = (ax != 0.f) ? twoeta_pi * ex2 * sa * sa / a : 0.0;
+  const double t2 = (ax != 0.f) ? twoeta_pi * ex2 * sa * sa * (double)ainv : 0.0;
   const double H = ex2 * (double)erfcxa * c2xa + t2 + twoeta_pi * a * (-c2xa * S1 + 0.5 * ex2 * sc);
   if (WANT_L) {
-    const double t2l = (ax != 0.f) ? twoeta_pi * ex2 * s2xa / (2.0 * a) : twoeta_pi * ex2 * x;
+    // (2 eta x/pi) e^{-x^2} sinc(2ax/pi) = (2 eta/pi) e^{-x^2} sin(2ax)/(2a)
+    const double t2l = (ax != 0.f) ? twoeta_pi * ex2 * s2xa * (0.5 * (double)ainv) : twoeta_pi * ex2 * x;
     *Lout = (float)(-ex2 * (double)erfcxa * s2xa + t2l + twoeta_pi * (a * s2xa * S1 + 0.5 * ex2 * sd));
   }
   return (float)H;

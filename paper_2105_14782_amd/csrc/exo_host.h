@@ -91,6 +91,7 @@ struct exo_ctx {
   bool profile = false;
   std::mutex prof_mu;
   std::vector<exo::ProfRec> prof;
+  exo::DevBuf prof_near;  // near-tier pair counter of the profiled FP32 launches
 };
 
 namespace exo {

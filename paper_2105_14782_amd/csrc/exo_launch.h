@@ -44,6 +44,7 @@ struct VoigtArgs {
   float2* part;
   float2* part_t;
   double* part64;
+  unsigned long long* near_pairs;  // profiling only: pairs summed by the near tier
 };
 
 // Per-layer quantities of one atmosphere.

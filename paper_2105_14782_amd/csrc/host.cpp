@@ -190,6 +190,7 @@ extern "C" int exo_destroy(exo_ctx* c) {
   for (auto& s : c->sp) s.release();
   c->d_nu.release();
   c->ws.release();
+  c->prof_near.release();
   for (auto& p : c->prof) {
     (void)hipEventDestroy(p.a);
     (void)hipEventDestroy(p.b);
@@ -318,7 +319,22 @@ extern "C" int exo_profile_enable(exo_ctx* c, int on) {
     (void)hipEventDestroy(p.b);
   }
   c->prof.clear();
+  if (on) {
+    if (c->prof_near.reserve(sizeof(unsigned long long))) return EXO_ENOMEM;
+    HIP_TRY(hipMemset(c->prof_near.p, 0, sizeof(unsigned long long)));
+  }
   c->profile = on != 0;
+  return EXO_OK;
+}
+
+extern "C" int exo_profile_read_near(exo_ctx* c, double* near_evals) {
+  if (!c) return set_err(EXO_EINVAL, "ctx is NULL");
+  if (!near_evals) return set_err(EXO_EINVAL, "near_evals is NULL");
+  HIP_TRY(hipSetDevice(c->device));
+  for (auto& p : c->prof) HIP_TRY(hipEventSynchronize(p.b));
+  unsigned long long n = 0;
+  if (c->prof_near.p) HIP_TRY(hipMemcpy(&n, c->prof_near.p, sizeof(n), hipMemcpyDeviceToHost));
+  *near_evals = (double)n;
   return EXO_OK;
 }
 
@@ -347,7 +363,9 @@ int exo::voigt_launch_profiled(exo_ctx* c, const VoigtArgs& A, bool fp64, bool t
     HIP_TRY(hipEventCreate(&pr.b));
     HIP_TRY(hipEventRecord(pr.a, st));
   }
-  HIP_TRY(launch_voigt(A, fp64, tan, st));
+  VoigtArgs Ap = A;
+  if (prof && !fp64) Ap.near_pairs = (unsigned long long*)c->prof_near.p;
+  HIP_TRY(launch_voigt(Ap, fp64, tan, st));
   if (prof) {
     HIP_TRY(hipEventRecord(pr.b, st));
     pr.evals = (double)A.n_lines * (double)A.ng * (double)A.nlay;

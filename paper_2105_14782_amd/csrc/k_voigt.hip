@@ -159,18 +159,28 @@ __device__ inline void neumaier(float& s, float& c, float v) {
   s = t;
 }
 
-// Forward-only core evaluation kept out of line: its FP64 temporaries would
-// otherwise set the register budget of the whole loop and halve occupancy.
-__device__ __attribute__((noinline)) float core_value(float x, float a, float erfcxa, float C1,
-                                                      const double* __restrict__ wn) {
-  return hjert_core_fac<false>(x, a, erfcxa, C1, wn, nullptr);
+// Core evaluations are kept out of line: their FP64 temporaries would
+// otherwise set the register budget of the whole loop and cut occupancy.
+// The weight pointer is wave-uniform; reading it into scalar registers and
+// addressing it as constant memory lets the forward core's weights arrive by
+// scalar loads.  (The tangent core keeps vector loads: with scalar loads its
+// register budget, and with it the kernel's occupancy, grows.)
+__device__ inline const double __attribute__((address_space(4)))* uniform_weights(const double* wn) {
+  const uint64_t p = (uint64_t)wn;
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)p);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(p >> 32));
+  return (const double __attribute__((address_space(4)))*)(((uint64_t)hi << 32) | lo);
 }
 
-// Tangent-mode core evaluation, (H, L), likewise out of line.
-__device__ __attribute__((noinline)) float2 core_value_tan(float x, float a, float erfcxa, float C1,
-                                                           const double* __restrict__ wn) {
+__device__ __attribute__((noinline)) float core_value(float x, float a, float ainv, float erfcxa,
+                                                      float C1, const double* __restrict__ wn) {
+  return hjert_core_fac<false>(x, a, ainv, erfcxa, C1, uniform_weights(wn), nullptr);
+}
+
+__device__ __attribute__((noinline)) float2 core_value_tan(float x, float a, float ainv, float erfcxa,
+                                                           float C1, const double* __restrict__ wn) {
   float L;
-  const float H = hjert_core_fac<true>(x, a, erfcxa, C1, wn, &L);
+  const float H = hjert_core_fac<true>(x, a, ainv, erfcxa, C1, wn, &L);
   return make_float2(H, L);
 }
 
@@ -268,7 +278,9 @@ __device__ __forceinline__ void near_lines(int sb, int se, const LineRec* __rest
     double nun = nuc[l0];
     LineRecT qtn;
     if (TAN) qtn = RT[l0];
-#pragma unroll 2
+    // (the forward loop does not unroll once its core call is in place)
+    constexpr int kUnroll = TAN ? 2 : 1;
+#pragma unroll kUnroll
     for (int l = l0; l < l1; ++l) {
       const LineRec q = qn;
       const double nul = nun;
@@ -311,7 +323,7 @@ __device__ __forceinline__ void near_lines(int sb, int se, const LineRec* __rest
           if (D[g] < q.thr) {
             const float x = dd[g] * q.winv;
             if (TAN) {
-              const float2 HL = core_value_tan(x, q.a, q.erfcxa, q.C1, RC[l].w);
+              const float2 HL = core_value_tan(x, q.a, q.ainv, q.erfcxa, q.C1, RC[l].w);
               const float H = HL.x, L = HL.y;
               // custom derivatives of Sec. 2.1.1:
               //   dH/dx = 2aL - 2xH,  dH/da = 2xL + 2aH - 2/sqrt(pi)
@@ -320,7 +332,7 @@ __device__ __forceinline__ void near_lines(int sb, int se, const LineRec* __rest
               f[g] = q.acore * H;
               ft[g] = q.acore * (qt.kA * H + Hx * x * qt.kw + Ha * qt.da);
             } else {
-              f[g] = q.acore * core_value(x, q.a, q.erfcxa, q.C1, RC[l].w);
+              f[g] = q.acore * core_value(x, q.a, q.ainv, q.erfcxa, q.C1, RC[l].w);
             }
           }
         }
@@ -367,6 +379,10 @@ __global__ __launch_bounds__(256) void k_voigt_f32(VoigtArgs A) {
     const int se = seg == 0 ? i0 : le;
     far_lines<TAN, G>(sb, se, R, RT, A.nu_c, nuj, s, c, ts, tc);
     if (seg == 0) near_lines<TAN, G>(i0, i1, R, RT, RC, A.nu_c, nuj, s, c, ts, tc);
+  }
+  if (A.near_pairs && lane == 0) {
+    const int64_t npts = min((int64_t)G * 64, A.ng - (tile0 + (int64_t)w * G * 64));
+    if (npts > 0) atomicAdd(A.near_pairs, (unsigned long long)(i1 - i0) * (unsigned long long)npts);
   }
 
 #pragma unroll
@@ -471,7 +487,7 @@ __global__ __launch_bounds__(256) void k_hjert_f32(int64_t n, const float* __res
   float f = h * r;
   float l = 0.f;
   if (D < q.thr) {
-    f = q.acore * hjert_core_fac<true>(d * q.winv, q.a, q.erfcxa, q.C1, qc.w, &l);
+    f = q.acore * hjert_core_fac<true>(d * q.winv, q.a, q.ainv, q.erfcxa, q.C1, qc.w, &l);
   } else if (L) {
     hjert_asy_f32(d, q.a, &l);
   }

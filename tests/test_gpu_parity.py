@@ -147,6 +147,72 @@ def test_cross_section_is_deterministic(exo):
     assert torch.equal(a, b)
 
 
+def _lines(rng, centres, mass=18.0):
+    n = centres.size
+    return synth.LineList(np.sort(centres), 10 ** rng.uniform(-23, -20, n), rng.exponential(1000, n),
+                          rng.uniform(0.01, 0.1, n), rng.uniform(0.5, 0.8, n), mass, 0, np.array([1.5]))
+
+
+def test_cross_section_far_lines_only(exo):
+    """Every line is farther than the far-tier reach from the whole grid, so the
+    sum runs only the truncated wing polynomial; it must still match the exact
+    profile to FP32 accuracy, far inside the 1e-4 bound."""
+    _say("cross_section far lines only")
+    rng = np.random.default_rng(21)
+    centres = np.concatenate([rng.uniform(4250.0, 4330.0, 300), rng.uniform(4356.0, 4450.0, 300)])
+    ll = _lines(rng, centres)
+    nu = np.linspace(4340.0, 4345.0, 2501)
+    c = exo.Context(0)
+    c.set_lines(1, ll)
+    c.set_grid(nu)
+    for T, P in [(2500.0, 1e-3), (1000.0, 30.0)]:
+        c.profile(True)
+        got = c.cross_section(1, T, P, "fp32").cpu().double().numpy()
+        near = c.profile_read_near()
+        c.profile(False)
+        assert near == 0.0, near
+        err = maxrel(got, O.cross_section(ll, T, P, nu))
+        _say(f"  T={T} P={P}: max rel err {err:.2e}")
+        assert err < 2e-6
+
+
+def _near_pairs_expected(ll, T, nu, wave_points=256):
+    """Pairs the near tier should take: lines within reach of the points a wave owns."""
+    kKB, kMU, kC = 1.380649e-16, 1.66053906660e-24, 2.99792458e10
+    beta_last = math.sqrt(kKB * T / (ll.mass_amu * kMU)) * ll.nu_c[-1] / kC
+    thr = float(np.float32(2.0 * 111.0 * beta_last * beta_last))
+    reach = math.sqrt(thr * (1.001 / 222.0) / 2e-5)
+    total = 0
+    for j0 in range(0, nu.size, wave_points):
+        j1 = min(j0 + wave_points, nu.size) - 1
+        lo, hi = nu[j0] - reach, nu[j1] + reach
+        n_near = np.searchsorted(ll.nu_c, hi, side="right") - np.searchsorted(ll.nu_c, lo, side="left")
+        total += int(n_near) * (j1 - j0 + 1)
+    return total
+
+
+@pytest.mark.parametrize("n_nu", [1000, 4097])
+def test_near_tier_pair_count(exo, n_nu):
+    """The kernel's near/far split equals the classification it is designed to
+    make (lines sorted by centre, reach from the largest Doppler width)."""
+    rng = np.random.default_rng(n_nu)
+    ll = _lines(rng, rng.uniform(4330.0, 4370.0, 3000))
+    nu = np.linspace(4340.0, 4360.0, n_nu)
+    c = exo.Context(0)
+    c.set_lines(0, ll)
+    c.set_grid(nu)
+    for T in (300.0, 2000.0):
+        c.profile(True)
+        c.cross_section(0, T, 1.0, "fp32")
+        n, ms, evals = c.profile_read()
+        near = c.profile_read_near()
+        c.profile(False)
+        exp = _near_pairs_expected(ll, T, nu)
+        _say(f"  n_nu={n_nu} T={T}: near {near:.0f} expected {exp} of {evals:.0f}")
+        assert evals == ll.n * n_nu
+        assert near == exp
+
+
 # ------------------------------------------------------------------ emission
 
 def _atmos(exo, wl, theta=None, **kw):
