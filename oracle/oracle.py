@@ -226,6 +226,15 @@ def temperatures(P_bar, T0, alpha):
     return T0 * np.asarray(P_bar, float) ** alpha
 
 
+def layer_temperatures(atm, T0, alpha):
+    """T_n of every layer: the atmosphere's own layer-by-layer profile when it
+    has one (the layer-by-layer temperature model of Sec. 6.1), else the
+    power law in (T0, alpha)."""
+    if getattr(atm, "T_layers", None) is not None:
+        return np.asarray(atm.T_layers, float).copy()
+    return temperatures(atm.P_bar, T0, alpha)
+
+
 def layer_dP_bar(P_bar):
     """dP_n = P_n - P_{n-1}, with P_{-1} = P_0^2/P_1 (the top layer keeps the grid ratio)."""
     P = np.asarray(P_bar, float)
@@ -452,7 +461,7 @@ def optical_depths(wl, theta, nu_idx=None, want_dT=False) -> Columns:
     nm = len(wl.lines)
     logx = np.asarray(theta[2:2 + nm], float)
     P = atm.P_bar
-    T = temperatures(P, T0, alpha)
+    T = layer_temperatures(atm, T0, alpha)
     dP = layer_dP_bar(P)
     NL = P.size
     tau = np.zeros((nm, NL, nu.size))
@@ -517,8 +526,9 @@ def flux_tangents(wl, theta, per_layer=False):
     T = c.T
     NL = P.size
     dT_dth = np.zeros((2, NL))
-    dT_dth[0] = T / theta[0]
-    dT_dth[1] = T * np.log(P)
+    if getattr(atm, "T_layers", None) is None:   # a layer-by-layer profile ignores (T0, alpha)
+        dT_dth[0] = T / theta[0]
+        dT_dth[1] = T * np.log(P)
     tau = c.dtau_mol.sum(axis=0) + c.dtau_cia
     dtau_dTn = c.ddtau_mol_dT.sum(axis=0) + c.ddtau_cia_dT
     Tn = transmission(tau)
@@ -563,6 +573,17 @@ def flux_tangents(wl, theta, per_layer=False):
     if per_layer:
         out["dF_dTn"] = response_linear(dF0_layers, wl.nu, resp)
     return out
+
+
+def flux_jvp(wl, theta, dtheta, dT_layers=None):
+    """J dtheta: the directional derivative of F along dtheta (and along the
+    per-layer temperature tangent dT_layers, if given), assembled from the
+    forward-mode tangents of flux_tangents."""
+    t = flux_tangents(wl, theta, per_layer=dT_layers is not None)
+    out = np.tensordot(np.asarray(dtheta, float), t["dF"], axes=1)
+    if dT_layers is not None:
+        out = out + np.asarray(dT_layers, float) @ t["dF_dTn"]
+    return t["F"], out
 
 
 def gaussian_loss(F, data, sigma):

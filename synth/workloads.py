@@ -45,7 +45,8 @@ class LineList:
 
 @dataclass
 class Atmosphere:
-    """Layer model: pressures ascending (top -> bottom), power-law T-P profile."""
+    """Layer model: pressures ascending (top -> bottom); power-law T-P profile
+    unless T_layers gives every layer's temperature."""
     P_bar: np.ndarray
     T0: float
     alpha: float
@@ -58,6 +59,7 @@ class Atmosphere:
     cia_nu_c: float = 4360.0
     vmr_h2: float = 0.75 * 2.33 / 2.016
     bottom: int = 0             # 0: F_B = pi B(T_bottom) ; 1: F_B = 0
+    T_layers: Optional[np.ndarray] = None   # layer-by-layer T [K]; replaces the power law
 
 
 @dataclass

@@ -331,6 +331,70 @@ def test_flux_tangents_by_central_differences():
     np.testing.assert_allclose(t["dF_dTn"].T @ (T / th[0]), t["dF"][0], rtol=1e-10)
 
 
+def test_layer_temperatures_reproduce_power_law():
+    """A layer-by-layer profile equal to the power law gives the same spectrum,
+    and its per-layer tangents are those of the power-law model."""
+    from dataclasses import replace
+    wl = synth.make_config(4, "tiny")
+    th = wl.theta
+    T = O.temperatures(wl.atmos.P_bar, th[0], th[1])
+    wl_l = replace(wl, atmos=replace(wl.atmos, T_layers=T))
+    np.testing.assert_array_equal(O.emission_flux(wl_l, th), O.emission_flux(wl, th))
+    a = O.flux_tangents(wl, th, per_layer=True)
+    b = O.flux_tangents(wl_l, th, per_layer=True)
+    np.testing.assert_array_equal(a["dF_dTn"], b["dF_dTn"])
+    # (T0, alpha) no longer act on the layer-by-layer model; the other tangents are unchanged
+    assert np.all(b["dF"][:2] == 0.0)
+    np.testing.assert_array_equal(a["dF"][2:], b["dF"][2:])
+
+
+def test_per_layer_tangents_by_central_differences():
+    """dF/dT_n of a layer-by-layer profile (a non-monotonic one) against central
+    differences of the oracle in T_n."""
+    from dataclasses import replace
+    wl = synth.make_config(4, "tiny")
+    th = wl.theta
+    NL = wl.atmos.P_bar.size
+    rng = np.random.default_rng(3)
+    T = O.temperatures(wl.atmos.P_bar, th[0], th[1]) * (1 + 0.1 * rng.uniform(-1, 1, NL))
+    wl_l = replace(wl, atmos=replace(wl.atmos, T_layers=T))
+    t = O.flux_tangents(wl_l, th, per_layer=True)
+    sens = np.abs(t["dF_dTn"]).max(axis=1)
+    layers = np.argsort(sens)[-3:]          # the three layers the spectrum depends on most
+    assert sens[layers].min() > 1e-3 * sens.max()
+    for n in layers:
+        h = 1e-5 * T[n]
+        Tp, Tm = T.copy(), T.copy()
+        Tp[n] += h
+        Tm[n] -= h
+        fd = (O.emission_flux(replace(wl, atmos=replace(wl.atmos, T_layers=Tp)), th)
+              - O.emission_flux(replace(wl, atmos=replace(wl.atmos, T_layers=Tm)), th)) / (2 * h)
+        np.testing.assert_allclose(t["dF_dTn"][n], fd, rtol=1e-5, atol=1e-6 * np.abs(fd).max(),
+                                   err_msg=f"layer {n}")
+
+
+def test_flux_jvp_is_the_tangent_combination():
+    """J dtheta from flux_jvp equals the central difference along dtheta."""
+    from dataclasses import replace
+    wl = synth.make_config(4, "tiny")
+    th = wl.theta
+    NL = wl.atmos.P_bar.size
+    rng = np.random.default_rng(8)
+    dth = rng.normal(size=6) * np.array([5.0, 1e-3, 1e-2, 1e-2, 0.1, 0.1])
+    F, jv = O.flux_jvp(wl, th, dth)
+    h = 1e-4
+    fd = (O.emission_flux(wl, th + h * dth) - O.emission_flux(wl, th - h * dth)) / (2 * h)
+    np.testing.assert_allclose(jv, fd, rtol=1e-5, atol=1e-6 * np.abs(fd).max())
+    # per-layer direction on a layer-by-layer profile
+    T = O.temperatures(wl.atmos.P_bar, th[0], th[1])
+    wl_l = replace(wl, atmos=replace(wl.atmos, T_layers=T))
+    dT = rng.normal(size=NL) * 3.0
+    F, jv = O.flux_jvp(wl_l, th, np.zeros(6), dT)
+    fd = (O.emission_flux(replace(wl, atmos=replace(wl.atmos, T_layers=T + h * dT)), th)
+          - O.emission_flux(replace(wl, atmos=replace(wl.atmos, T_layers=T - h * dT)), th)) / (2 * h)
+    np.testing.assert_allclose(jv, fd, rtol=1e-5, atol=1e-6 * np.abs(fd).max())
+
+
 def test_loss_gradient_by_central_differences():
     wl = synth.make_config(4, "tiny")
     F_star = O.emission_flux(wl, wl.theta_star)
