@@ -357,6 +357,18 @@ def main():
     t32 = time_fwd("fp32", max(3, args.steps))
     t64 = time_fwd("fp64", args.fp64_reps)
 
+    # forward-mode derivative along a parameter tangent plus a per-layer
+    # temperature tangent (spectrum and J dtheta in one call)
+    dth = np.array([5.0, 1e-3, 1e-2, -1e-2, 0.1, 0.1])
+    dT = np.random.default_rng(6).normal(size=atm.P_bar.size)
+    ctx.flux_jvp(atm, resp, dth, dT)
+    torch.cuda.synchronize()
+    tj0 = time.perf_counter()
+    for _ in range(max(3, args.steps // 2)):
+        ctx.flux_jvp(atm, resp, dth, dT)
+    torch.cuda.synchronize()
+    tjvp = (time.perf_counter() - tj0) / max(3, args.steps // 2)
+
     avg_launch_ms = kms / max(nl, 1)
     flops_per_launch = (FLOPS_PER_EVAL_NEAR * knear + FLOPS_PER_EVAL_FAR * (kevals - knear)) / max(nl, 1)
     achieved = flops_per_launch / (avg_launch_ms * 1e-3) / 1e12
@@ -383,6 +395,7 @@ def main():
         "forward_fp32": {"spectra_per_s": 1.0 / t32, "evals_per_s": evals / t32},
         "forward_fp64_plain": {"spectra_per_s": 1.0 / t64, "evals_per_s": evals / t64},
         "fp32_over_fp64_spectra": t64 / t32,
+        "flux_jvp": {"ms_per_call": tjvp * 1e3, "evals_per_s": evals / tjvp},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS, "traffic": recorded_traffic(),
                      "kernel": "k_voigt_f32<tangent>", "avg_launch_ms": avg_launch_ms,

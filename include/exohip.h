@@ -137,7 +137,7 @@ int exo_cross_section(exo_ctx* ctx, int s, double T_K, double P_bar, int precisi
  *   alpha_CIA(T, nu) = cia_alpha0 (T/1000)^cia_Tpow exp(cia_slope (nu - cia_nu_c)/40)
  * [cm^5] and H2 volume mixing ratio vmr_h2. */
 typedef struct {
-  int32_t n_layers;          /* >= 2 */
+  int32_t n_layers;          /* 2..4096 */
   const double* P_bar;       /* host [n_layers], strictly ascending, > 0 */
   double T0_K, alpha;
   int32_t n_species;         /* 1..EXO_MAX_SPECIES */
@@ -149,6 +149,9 @@ typedef struct {
   int32_t bottom;            /* exo_bottom */
   int64_t grid_begin;        /* model grid = context grid [grid_begin, grid_begin+grid_len) */
   int64_t grid_len;          /* 0 = the whole context grid */
+  const double* T_layers;    /* host [n_layers] K (each > 1, finite) or NULL: the
+                                layer-by-layer temperature model of Sec. 6.1; when
+                                given, T0_K and alpha are not used */
 } exo_atmos;
 
 /* Response of Sec. 4 on the (log-uniform) model grid: rotation with
@@ -180,7 +183,9 @@ int exo_emission_flux(exo_ctx* ctx, const exo_atmos* atm, const exo_response* re
  *             dL/dF, float (EXO_FP32_KAHAN) or double (EXO_FP64)
  *   grad_host host [2 + n_species + 2] doubles, written on return:
  *             {dL/dT0, dL/dalpha, dL/dlog10X_1..S, dL/dRV, dL/dvsini}
- *             (RV, vsini entries are 0 when resp == NULL)
+ *             (RV, vsini entries are 0 when resp == NULL; T0, alpha
+ *             entries are 0 with atm->T_layers, whose gradient is
+ *             dL_dT_layers)
  *   dL_dT_layers host [n_layers] or NULL: dL/dT_n of every layer
  *   flux_dev  device or NULL: if given, the forward spectrum F is written
  *             there as by exo_emission_flux (one pass gives F and gradient)
@@ -189,6 +194,26 @@ int exo_emission_flux(exo_ctx* ctx, const exo_atmos* atm, const exo_response* re
 int exo_flux_vjp(exo_ctx* ctx, const exo_atmos* atm, const exo_response* resp,
                  int precision, const void* cot_dev, double* grad_host,
                  double* dL_dT_layers, void* flux_dev, void* stream);
+
+/* Jacobian-vector product of the emission spectrum (forward mode, App. D):
+ * dF = J dtheta along the parameter tangent
+ *   dtheta_host   host [2 + n_species + 2] doubles
+ *                 {dT0, dalpha, dlog10X_1..S, dRV, dvsini}; dT0 and dalpha
+ *                 are not used with atm->T_layers, dRV and dvsini not when
+ *                 resp == NULL
+ *   dT_layers_host host [n_layers] or NULL: a per-layer temperature tangent
+ *                 dT_n, added to the one (dT0, dalpha) induce
+ *   flux_dev      device [out_len] float or NULL: the spectrum F, as
+ *                 exo_emission_flux writes it
+ *   dflux_dev     device [out_len] float: J dtheta
+ * (out_len: resp->out_len, or the model grid length when resp == NULL.)
+ * EXO_FP32_KAHAN only (the tangents are those of the FP32 Voigt sum; the
+ * transfer and the response run in FP64).  Host arrays are copied before
+ * the call returns; the work is asynchronous on `stream`.
+ * Errors: EXO_ENOTSET, EXO_EINVAL, EXO_ENOMEM, EXO_EDEVICE. */
+int exo_flux_jvp(exo_ctx* ctx, const exo_atmos* atm, const exo_response* resp,
+                 int precision, const double* dtheta_host, const double* dT_layers_host,
+                 void* flux_dev, void* dflux_dev, void* stream);
 
 /* Response alone (Sec. 4) applied to a caller spectrum F0 on the model grid
  * [grid_begin, grid_begin + grid_len) of the context grid (grid_len 0 = all):

@@ -11,7 +11,8 @@ from ._lib import (  # noqa: F401
 
 def __getattr__(name):
     # the torch-dependent front end is imported lazily
-    if name in ("Context", "Atmos", "Response", "EmissionFlux", "hjert_f32", "hjert_f64", "trans2e3"):
+    if name in ("Context", "Atmos", "Response", "EmissionFlux", "LayerEmissionFlux", "hjert_f32", "hjert_f64",
+                "trans2e3"):
         from . import api
         return getattr(api, name)
     if name in ("Server", "ServeRequest"):

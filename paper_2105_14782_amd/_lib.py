@@ -41,6 +41,7 @@ class ExoAtmos(ctypes.Structure):
         ("bottom", ctypes.c_int32),
         ("grid_begin", ctypes.c_int64),
         ("grid_len", ctypes.c_int64),
+        ("T_layers", _c_dp),
     ]
 
 
@@ -91,6 +92,7 @@ def load_library(path: str = LIB_PATH):
         "exo_profile_enable": ([V, I], I),
         "exo_profile_read": ([V, ctypes.POINTER(I64), ctypes.POINTER(D), ctypes.POINTER(D)], I),
         "exo_profile_read_near": ([V, ctypes.POINTER(D)], I),
+        "exo_flux_jvp": ([V, ctypes.POINTER(ExoAtmos), ctypes.POINTER(ExoResponse), I, _c_dp, _c_dp, V, V, V], I),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)

@@ -51,11 +51,13 @@ class Atmos:
     bottom: int = L.EXO_FB_PLANCK_BOTTOM
     grid_begin: int = 0
     grid_len: int = 0
+    T_layers: Optional[np.ndarray] = None   # layer-by-layer T [K]; replaces (T0, alpha)
 
     def to_c(self):
         P = _f64(self.P_bar)
         sp = np.ascontiguousarray(np.asarray(self.species, dtype=np.int32))
         lx = _f64(self.log10_mmr)
+        Tl = None if self.T_layers is None else _f64(self.T_layers)
         a = L.ExoAtmos(
             n_layers=P.size, P_bar=L.dptr(P), T0_K=float(self.T0), alpha=float(self.alpha),
             n_species=sp.size, species=sp.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
@@ -63,8 +65,9 @@ class Atmos:
             cia_alpha0=float(self.cia_alpha0), cia_Tpow=float(self.cia_Tpow),
             cia_slope=float(self.cia_slope), cia_nu_c=float(self.cia_nu_c),
             vmr_h2=float(self.vmr_h2), bottom=int(self.bottom),
-            grid_begin=int(self.grid_begin), grid_len=int(self.grid_len))
-        return a, (P, sp, lx)   # keep the arrays alive for the call
+            grid_begin=int(self.grid_begin), grid_len=int(self.grid_len),
+            T_layers=L.dptr(Tl) if Tl is not None else None)
+        return a, (P, sp, lx, Tl)   # keep the arrays alive for the call
 
     @staticmethod
     def from_workload(atm, species, theta=None, grid_begin=0, grid_len=0) -> "Atmos":
@@ -74,7 +77,7 @@ class Atmos:
         lx = atm.log10_mmr if theta is None else np.asarray(theta[2:2 + nm], float)
         return Atmos(atm.P_bar, T0, al, list(species), list(lx), atm.g_cgs, atm.mmw,
                      atm.cia_alpha0, atm.cia_Tpow, atm.cia_slope, atm.cia_nu_c, atm.vmr_h2,
-                     atm.bottom, grid_begin, grid_len)
+                     atm.bottom, grid_begin, grid_len, getattr(atm, "T_layers", None))
 
 
 @dataclass
@@ -189,6 +192,28 @@ class Context:
             ctypes.c_void_p(flux.data_ptr()) if flux is not None else None, _stream(stream)))
         return grad, layers, flux
 
+    def flux_jvp(self, atmos: Atmos, response: Optional[Response], dtheta, dT_layers=None,
+                 want_flux: bool = True, stream=None):
+        """(F or None, J dtheta) on the device: the spectrum and its directional
+        derivative along dtheta = (dT0, dalpha, dlog10X..., dRV, dvsini) plus the
+        optional per-layer temperature tangent dT_layers."""
+        n = self._out_len(atmos, response)
+        m = len(atmos.species)
+        dth = _f64(dtheta)
+        assert dth.size == 4 + m
+        dTl = None if dT_layers is None else _f64(dT_layers)
+        assert dTl is None or dTl.size == len(atmos.P_bar)
+        dev = f"cuda:{self.device}"
+        flux = torch.empty(n, dtype=torch.float32, device=dev) if want_flux else None
+        dflux = torch.empty(n, dtype=torch.float32, device=dev)
+        a, keep = atmos.to_c()
+        r = response.to_c() if response is not None else None
+        L.check(self._lib.exo_flux_jvp(
+            self._h, ctypes.byref(a), ctypes.byref(r) if r is not None else None, L.EXO_FP32_KAHAN,
+            L.dptr(dth), L.dptr(dTl), ctypes.c_void_p(flux.data_ptr()) if flux is not None else None,
+            ctypes.c_void_p(dflux.data_ptr()), _stream(stream)))
+        return flux, dflux
+
     def broaden(self, F0: torch.Tensor, response: Response, grid_begin=0, grid_len=0, stream=None):
         assert F0.dtype == torch.float64 and F0.is_contiguous()
         out = torch.empty(int(response.out_len), dtype=torch.float64, device=F0.device)
@@ -272,3 +297,52 @@ class EmissionFlux(torch.autograd.Function):
         g, _, _ = ctx.exo.flux_vjp(ctx.atmos, ctx.response, gF.detach().to(torch.float32).contiguous())
         out = torch.as_tensor(g[:ctx.ntheta], dtype=ctx.theta_dtype)
         return out, None, None, None
+
+    @staticmethod
+    def jvp(ctx, gtheta, *unused):
+        """Forward mode (torch.autograd.forward_ad) through exo_flux_jvp."""
+        dth = np.zeros(4 + len(ctx.atmos.species))
+        g = gtheta.detach().cpu().numpy().astype(np.float64)
+        dth[:g.size] = g
+        _, dF = ctx.exo.flux_jvp(ctx.atmos, ctx.response, dth, want_flux=False)
+        return dF
+
+
+class LayerEmissionFlux(torch.autograd.Function):
+    """F(T_layers, phi), phi = (log10 X_1..X_M, RV, vsini): the layer-by-layer
+    temperature model (one free temperature per layer), with the HIP adjoint
+    as backward and exo_flux_jvp as forward-mode derivative.
+
+    T_layers: float64 CPU tensor [n_layers]; phi: float64 CPU tensor [M + 2].
+    Returns the FP32 spectrum on the device.
+    """
+
+    @staticmethod
+    def forward(ctx, T_layers: torch.Tensor, phi: torch.Tensor, exo: Context, atmos: Atmos,
+                response: Response):
+        T = T_layers.detach().cpu().numpy().astype(np.float64)
+        ph = phi.detach().cpu().numpy().astype(np.float64)
+        m = len(atmos.species)
+        a = Atmos(**{**atmos.__dict__, "T_layers": T, "log10_mmr": list(ph[:m])})
+        r = Response(**{**response.__dict__, "rv_kms": ph[m], "vsini_kms": ph[m + 1]})
+        ctx.exo, ctx.atmos, ctx.response = exo, a, r
+        ctx.dtypes = (T_layers.dtype, phi.dtype)
+        return exo.emission_flux(a, r, "fp32")
+
+    @staticmethod
+    def backward(ctx, gF):
+        g, gT, _ = ctx.exo.flux_vjp(ctx.atmos, ctx.response, gF.detach().to(torch.float32).contiguous(),
+                                    want_layers=True)
+        return (torch.as_tensor(gT, dtype=ctx.dtypes[0]), torch.as_tensor(g[2:], dtype=ctx.dtypes[1]),
+                None, None, None)
+
+    @staticmethod
+    def jvp(ctx, gT, gphi, *unused):
+        dth = np.zeros(4 + len(ctx.atmos.species))
+        dTl = None
+        if gphi is not None:
+            dth[2:] = gphi.detach().cpu().numpy().astype(np.float64)
+        if gT is not None:
+            dTl = gT.detach().cpu().numpy().astype(np.float64)
+        _, dF = ctx.exo.flux_jvp(ctx.atmos, ctx.response, dth, dTl, want_flux=False)
+        return dF

@@ -11,6 +11,10 @@
 
 namespace exo {
 
+// Layers per atmosphere (per-call parameter blocks are staged through a
+// fixed pinned buffer).
+constexpr int kMaxLayers = 4096;
+
 int set_err(int code, const char* fmt, ...);
 bool fail_alloc_hook();
 

@@ -51,6 +51,7 @@ struct VoigtArgs {
 struct AtmosDev {
   int nlay, nspec, bottom;
   const double* P;                 // [nlay] bar
+  const double* T_in;              // [nlay] K, or nullptr: T = T0 (P / 1 bar)^alpha
   double T0, alpha, g, mmw;
   double cia_alpha0, cia_Tpow, cia_slope, cia_nu_c, vmr_h2;
   double logx[kMaxSpecies];
@@ -74,6 +75,17 @@ struct RtArgs {
   double* Fup;           // scratch [nlay][ng]
   double* taubar;        // [nlay][ng]
   double* partT;         // [nblocks][nlay]
+};
+
+// Forward-mode tangent of the transfer: per-layer dT_n =
+// [powerlaw] T_n (dT0/T0 + dalpha ln P_n) + dTl[n], per-species dlog10 X_m.
+struct JvpArgs {
+  const double* lnP;     // [nlay]
+  const double* dTl;     // [nlay] or nullptr
+  const double* dlogx;   // [nspec]
+  double dT0_rel, dalpha;
+  int powerlaw;
+  double* dF0;           // [ng] output
 };
 
 // Response (rotation + IP) on the model grid.
@@ -112,6 +124,10 @@ hipError_t launch_cast_copy(const double* src, void* dst, bool dst64, int64_t n,
 hipError_t launch_to_double(const void* src, bool src64, double* dst, int64_t n, hipStream_t st);
 hipError_t launch_grad_final(const double* partT, int64_t nbT, const double* partX, int64_t nbX,
                              const double* partR, int64_t nbR, const double* T, const double* lnP,
-                             int nlay, int nspec, double T0, double* out, hipStream_t st);
+                             int nlay, int nspec, double T0, int powerlaw, double* out, hipStream_t st);
+hipError_t launch_rt_jvp(const RtArgs& R, const JvpArgs& J, hipStream_t st);
+// dF = IP * (rot * dF0 + (drot/dRV dRV + drot/dvsini dvsini) * F0), float output
+hipError_t launch_response_jvp(const RespDev& R, const double* F0, const double* dF0, double d_rv,
+                               double d_vsini, double* dmid, float* dout, hipStream_t st);
 
 }  // namespace exo

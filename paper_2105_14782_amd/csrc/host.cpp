@@ -550,13 +550,19 @@ extern "C" int exo_cross_section(exo_ctx* c, int s, double T, double P, int prec
 int exo::validate_atmos(const exo_ctx* c, const exo_atmos* a, int64_t* gb, int64_t* gl) {
   if (!a) return set_err(EXO_EINVAL, "atmos is NULL");
   if (c->n_nu < 2) return set_err(EXO_ENOTSET, "grid not set");
-  if (a->n_layers < 2 || a->n_layers > 100000 || !a->P_bar) return set_err(EXO_EINVAL, "need >= 2 layers");
+  if (a->n_layers < 2 || a->n_layers > kMaxLayers || !a->P_bar)
+    return set_err(EXO_EINVAL, "need 2..%d layers", kMaxLayers);
   for (int i = 0; i < a->n_layers; ++i) {
     if (!(a->P_bar[i] > 0) || !std::isfinite(a->P_bar[i])) return set_err(EXO_EINVAL, "P must be > 0");
     if (i > 0 && !(a->P_bar[i] > a->P_bar[i - 1])) return set_err(EXO_EINVAL, "P must ascend (top -> bottom)");
   }
-  if (!(a->T0_K > 0) || !std::isfinite(a->T0_K) || !std::isfinite(a->alpha))
+  if (a->T_layers) {
+    for (int i = 0; i < a->n_layers; ++i)
+      if (!(a->T_layers[i] > 1.0) || !std::isfinite(a->T_layers[i]))
+        return set_err(EXO_EINVAL, "layer temperatures must be finite and exceed 1 K");
+  } else if (!(a->T0_K > 0) || !std::isfinite(a->T0_K) || !std::isfinite(a->alpha)) {
     return set_err(EXO_EINVAL, "bad T0/alpha");
+  }
   if (a->n_species < 1 || a->n_species > EXO_MAX_SPECIES || !a->species || !a->log10_mmr)
     return set_err(EXO_EINVAL, "bad species list");
   for (int m = 0; m < a->n_species; ++m) {
@@ -569,9 +575,11 @@ int exo::validate_atmos(const exo_ctx* c, const exo_atmos* a, int64_t* gb, int64
       !std::isfinite(a->cia_slope) || !std::isfinite(a->cia_nu_c) || !(a->vmr_h2 >= 0))
     return set_err(EXO_EINVAL, "bad CIA parameters");
   if (a->bottom != EXO_FB_PLANCK_BOTTOM && a->bottom != EXO_FB_ZERO) return set_err(EXO_EINVAL, "bad bottom");
-  const double Tmin = std::min(a->T0_K * std::pow(a->P_bar[0], a->alpha),
-                               a->T0_K * std::pow(a->P_bar[a->n_layers - 1], a->alpha));
-  if (!(Tmin > 1.0) || !std::isfinite(Tmin)) return set_err(EXO_EINVAL, "layer temperatures must exceed 1 K");
+  if (!a->T_layers) {
+    const double Tmin = std::min(a->T0_K * std::pow(a->P_bar[0], a->alpha),
+                                 a->T0_K * std::pow(a->P_bar[a->n_layers - 1], a->alpha));
+    if (!(Tmin > 1.0) || !std::isfinite(Tmin)) return set_err(EXO_EINVAL, "layer temperatures must exceed 1 K");
+  }
   int64_t b = a->grid_begin, l = a->grid_len;
   if (l == 0) {
     if (b != 0) return set_err(EXO_EINVAL, "grid_len 0 requires grid_begin 0");
@@ -619,9 +627,13 @@ int exo::forward_core(exo_ctx* c, Workspace& ws, const exo_atmos* a, int64_t gb,
                       bool fp64, bool tangent, hipStream_t st) {
   const int NL = a->n_layers, M = a->n_species;
   int rc;
-  // parameter block: P
-  if ((rc = ws.reserve(ws.params, (size_t)NL * sizeof(double)))) return rc;
-  if ((rc = ws.stage_params(a->P_bar, NL, (double*)ws.params.p, st))) return rc;
+  // parameter block: P, then the layer temperatures when the atmosphere gives them
+  if ((rc = ws.reserve(ws.params, (size_t)2 * NL * sizeof(double)))) return rc;
+  {
+    std::vector<double> blk(a->P_bar, a->P_bar + NL);
+    if (a->T_layers) blk.insert(blk.end(), a->T_layers, a->T_layers + NL);
+    if ((rc = ws.stage_params(blk.data(), blk.size(), (double*)ws.params.p, st))) return rc;
+  }
   if ((rc = ws.reserve(ws.layer, (size_t)6 * NL * sizeof(double)))) return rc;
   if ((rc = ws.reserve(ws.col, (size_t)M * NL * sizeof(double)))) return rc;
   double* lay = (double*)ws.layer.p;
@@ -630,6 +642,7 @@ int exo::forward_core(exo_ctx* c, Workspace& ws, const exo_atmos* a, int64_t gb,
   A.nspec = M;
   A.bottom = a->bottom;
   A.P = (const double*)ws.params.p;
+  A.T_in = a->T_layers ? (const double*)ws.params.p + NL : nullptr;
   A.T0 = a->T0_K;
   A.alpha = a->alpha;
   A.g = a->g_cgs;
@@ -709,7 +722,7 @@ size_t exo::estimate_workspace(const exo_ctx* c, const exo_atmos* a, const exo_r
   auto R = [](size_t b) { return (b + 255) & ~size_t(255); };
   const size_t NL = a->n_layers, M = a->n_species;
   const size_t esz = fp64 ? sizeof(double) : sizeof(float);
-  size_t t = R(NL * 8) + R(6 * NL * 8) + R(M * NL * 8) + R(M * NL * gl * esz) + R(gl * 8);
+  size_t t = R(2 * NL * 8) + R(6 * NL * 8) + R(M * NL * 8) + R(M * NL * gl * esz) + R(gl * 8);
   if (vjp) t += R(M * NL * gl * sizeof(float));
   const OpacityPlan P = plan_opacity_all(c, a, gl, fp64, vjp);
   for (size_t b : {P.rec, P.core, P.rect, P.rec64, P.part, P.part_t}) t += b ? R(b) : 0;
@@ -798,7 +811,8 @@ int exo::vjp_impl(exo_ctx* c, Workspace& ws, const exo_atmos* a, const exo_respo
   HIP_TRY(launch_grad_x(Rt.taubar, ws.tau.p, false, M, NL, gl, (double*)ws.partX.p, nbg, st));
   const double* lay = (const double*)ws.layer.p;
   HIP_TRY(launch_grad_final(Rt.partT, nbg, (const double*)ws.partX.p, nbg, (const double*)ws.partR.p,
-                            nbR, lay, lay + 2 * NL, NL, M, a->T0_K, (double*)ws.gout.p, st));
+                            nbR, lay, lay + 2 * NL, NL, M, a->T0_K, a->T_layers ? 0 : 1,
+                            (double*)ws.gout.p, st));
   std::vector<double> h(4 + M + NL);
   HIP_TRY(hipMemcpyAsync(h.data(), ws.gout.p, h.size() * sizeof(double), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
@@ -815,6 +829,66 @@ extern "C" int exo_flux_vjp(exo_ctx* c, const exo_atmos* a, const exo_response* 
   std::lock_guard<std::mutex> g(c->mu);
   hipStream_t st = (hipStream_t)stream;
   return with_ws(c->ws, st, [&] { return vjp_impl(c, c->ws, a, r, precision, cot, grad, dLdT, flux, st); });
+}
+
+static int jvp_impl(exo_ctx* c, Workspace& ws, const exo_atmos* a, const exo_response* r,
+                    int precision, const double* dth, const double* dTl, void* flux, void* dflux,
+                    hipStream_t st) {
+  int64_t gb, gl;
+  int rc;
+  if ((rc = validate_atmos(c, a, &gb, &gl))) return rc;
+  if (precision != EXO_FP32_KAHAN)
+    return set_err(EXO_EINVAL, "flux_jvp is provided for EXO_FP32_KAHAN");
+  if (!dth || !dflux) return set_err(EXO_EINVAL, "dtheta_host / dflux_dev is NULL");
+  const int NL = a->n_layers, M = a->n_species;
+  for (int k = 0; k < 2 + M + 2; ++k)
+    if (!std::isfinite(dth[k])) return set_err(EXO_EINVAL, "non-finite dtheta");
+  if (dTl)
+    for (int n = 0; n < NL; ++n)
+      if (!std::isfinite(dTl[n])) return set_err(EXO_EINVAL, "non-finite dT_layers");
+  RespDev R{};
+  if (r && (rc = prepare_response(c, r, gl, &R))) return rc;
+  if ((rc = forward_core(c, ws, a, gb, gl, false, true, st))) return rc;
+  // tangent parameter block: dlog10 X, then the per-layer dT
+  if ((rc = ws.reserve(ws.gout, (size_t)(M + NL) * sizeof(double)))) return rc;
+  {
+    std::vector<double> blk(dth + 2, dth + 2 + M);
+    if (dTl) blk.insert(blk.end(), dTl, dTl + NL);
+    if ((rc = ws.stage_params(blk.data(), blk.size(), (double*)ws.gout.p, st))) return rc;
+  }
+  if ((rc = ws.reserve(ws.F0bar, (size_t)gl * sizeof(double)))) return rc;
+  const double* lay = (const double*)ws.layer.p;
+  JvpArgs J{};
+  J.lnP = lay + 2 * NL;
+  J.dlogx = (const double*)ws.gout.p;
+  J.dTl = dTl ? (const double*)ws.gout.p + M : nullptr;
+  J.powerlaw = a->T_layers ? 0 : 1;
+  J.dT0_rel = a->T_layers ? 0.0 : dth[0] / a->T0_K;
+  J.dalpha = a->T_layers ? 0.0 : dth[1];
+  J.dF0 = (double*)ws.F0bar.p;
+  HIP_TRY(launch_rt_jvp(ws.last_rt, J, st));
+  const double* F0 = (const double*)ws.F0.p;
+  if (r) {
+    // taps (and the spectrum when asked for), then the tangent of both stages
+    if ((rc = apply_response(ws, R, F0, flux, false, st))) return rc;
+    if ((rc = ws.reserve(ws.midbar, (size_t)(R.ol + 2 * R.K) * sizeof(double)))) return rc;
+    HIP_TRY(launch_response_jvp(R, F0, J.dF0, dth[2 + M], dth[2 + M + 1], (double*)ws.midbar.p,
+                                (float*)dflux, st));
+  } else {
+    if (flux) HIP_TRY(launch_cast_copy(F0, flux, false, gl, st));
+    HIP_TRY(launch_cast_copy(J.dF0, dflux, false, gl, st));
+  }
+  return EXO_OK;
+}
+
+extern "C" int exo_flux_jvp(exo_ctx* c, const exo_atmos* a, const exo_response* r, int precision,
+                            const double* dth, const double* dTl, void* flux, void* dflux,
+                            void* stream) {
+  if (!c) return set_err(EXO_EINVAL, "ctx is NULL");
+  HIP_TRY(hipSetDevice(c->device));
+  std::lock_guard<std::mutex> g(c->mu);
+  hipStream_t st = (hipStream_t)stream;
+  return with_ws(c->ws, st, [&] { return jvp_impl(c, c->ws, a, r, precision, dth, dTl, flux, dflux, st); });
 }
 
 extern "C" int exo_broaden(exo_ctx* c, int64_t gb, int64_t gl, const exo_response* r,

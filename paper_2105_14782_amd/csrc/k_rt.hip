@@ -18,7 +18,7 @@ __global__ __launch_bounds__(256) void k_atmos(AtmosDev A) {
   const double Pprev = n > 0 ? A.P[n - 1] : A.P[0] * A.P[0] / A.P[1];
   const double dP = P - Pprev;
   const double lnP = log(P);
-  const double T = A.T0 * exp(A.alpha * lnP);
+  const double T = A.T_in ? A.T_in[n] : A.T0 * exp(A.alpha * lnP);
   A.T[n] = T;
   A.dP[n] = dP;
   A.lnP[n] = lnP;
@@ -116,6 +116,70 @@ __global__ __launch_bounds__(256) void k_rt_adjoint(RtArgs R) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Forward-mode transfer (App. D): with dT_n the layer temperature tangent and
+// dtau_n = sum_m (dtau^m_n/dT_n dT_n + ln10 tau^m_n dlog10 X_m)
+//          + dtau^CIA_n/dT_n dT_n,
+// the tangent of F0 = sum_n Phi_n (1 - T_n) S_n + Phi_N F_B, top to bottom:
+//   dPhi_{n+1} = dPhi_n T_n + Phi_n dT_n,  dT_n = -2 E2(tau_n) dtau_n,
+//   dS_n = pi dB/dT(T_n) dT_n,  dF_B = pi dB/dT(T_{N-1}) dT_{N-1}.
+// ---------------------------------------------------------------------------
+template <typename TT>
+__global__ __launch_bounds__(256) void k_rt_jvp(RtArgs R, JvpArgs J) {
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (j >= R.ng) return;
+  const double nu = R.nu[j];
+  const double ciaf = exp(R.cia_slope * (nu - R.cia_nu_c) / 40.0);
+  const TT* tau = (const TT*)R.tau;
+  const TT* taut = (const TT*)R.taut;
+  double Phi = 1.0, dPhi = 0.0, dF0 = 0.0, dTlast = 0.0;
+  for (int n = 0; n < R.nlay; ++n) {
+    const double dT = (J.powerlaw ? R.T[n] * (J.dT0_rel + J.dalpha * J.lnP[n]) : 0.0) +
+                      (J.dTl ? J.dTl[n] : 0.0);
+    double t = R.cia[n] * ciaf, dt = R.dcia[n] * ciaf * dT;
+    for (int m = 0; m < R.nspec; ++m) {
+      const int64_t o = ((int64_t)m * R.nlay + n) * R.ng + j;
+      const double tm = (double)tau[o];
+      t += tm;
+      dt += (double)taut[o] * dT + kLn10 * J.dlogx[m] * tm;
+    }
+    double Tr, dTr;
+    trans2e3(t, &Tr, &dTr);
+    double dB;
+    const double S = planck_pi(R.T[n], nu, &dB);
+    const double dTrn = dTr * dt;
+    dF0 += dPhi * (1.0 - Tr) * S - Phi * dTrn * S + Phi * (1.0 - Tr) * dB * dT;
+    dPhi = dPhi * Tr + Phi * dTrn;
+    Phi *= Tr;
+    dTlast = dT;
+  }
+  if (R.bottom == 0) {
+    double dB;
+    const double FB = planck_pi(R.T[R.nlay - 1], nu, &dB);
+    dF0 += dPhi * FB + Phi * dB * dTlast;
+  }
+  J.dF0[j] = dF0;
+}
+
+// Tangent of the rotation stage: dmid[p] = sum_k rot_k dF0_{i - dlo - k}
+//   + (drot_rv_k dRV + drot_vs_k dvsini) F0_{i - dlo - k}
+__global__ __launch_bounds__(256) void k_conv_rot_jvp(RespDev R, const double* __restrict__ F0,
+                                                      const double* __restrict__ dF0, double d_rv,
+                                                      double d_vs, double* __restrict__ dmid,
+                                                      int64_t nmid) {
+  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (p >= nmid) return;
+  const int64_t i = R.ob - R.K + p;
+  const double* __restrict__ src = F0 + (i - R.dlo);
+  const double* __restrict__ dsrc = dF0 + (i - R.dlo);
+  double acc = 0.0;
+  for (int64_t k = 0; k < R.nrot; ++k) {
+    acc = fma(R.rot[k], dsrc[-k], acc);
+    acc = fma(fma(R.drot_rv[k], d_rv, R.drot_vs[k] * d_vs), src[-k], acc);
+  }
+  dmid[p] = acc;
+}
+
 // sum_{n,j} taubar_nj tau^m_nj per block (fixed order), for every species m.
 template <typename TT>
 __global__ __launch_bounds__(256) void k_grad_x(const double* __restrict__ taubar,
@@ -133,14 +197,14 @@ __global__ __launch_bounds__(256) void k_grad_x(const double* __restrict__ tauba
   }
 }
 
-// Final fixed-order reductions and the chain rule to (T0, alpha):
-//   dT_n/dT0 = T_n/T0,  dT_n/dalpha = T_n ln(P_n / 1 bar).
+// Final fixed-order reductions and the chain rule to (T0, alpha) of the
+// power-law profile:  dT_n/dT0 = T_n/T0,  dT_n/dalpha = T_n ln(P_n / 1 bar).
 // out = {dT0, dalpha, dlog10X_1..M, dRV, dvsini, dT_0..dT_{N-1}}
 __global__ void k_grad_final(const double* __restrict__ partT, int64_t nbT,
                              const double* __restrict__ partX, int64_t nbX,
                              const double* __restrict__ partR, int64_t nbR,
                              const double* __restrict__ T, const double* __restrict__ lnP, int nlay,
-                             int nspec, double T0, double* __restrict__ out) {
+                             int nspec, double T0, int powerlaw, double* __restrict__ out) {
   const int t = threadIdx.x;
   double* gT = out + 2 + nspec + 2;
   for (int n = t; n < nlay; n += blockDim.x) {
@@ -156,8 +220,9 @@ __global__ void k_grad_final(const double* __restrict__ partT, int64_t nbT,
       g0 += gT[n] * T[n] / T0;
       ga += gT[n] * T[n] * lnP[n];
     }
-    out[0] = g0;
-    out[1] = ga;
+    // a layer-by-layer profile does not depend on (T0, alpha)
+    out[0] = powerlaw ? g0 : 0.0;
+    out[1] = powerlaw ? ga : 0.0;
     for (int m = 0; m < nspec; ++m) {
       double s = 0.0;
       for (int64_t b = 0; b < nbX; ++b) s += partX[b * nspec + m];
@@ -373,9 +438,23 @@ hipError_t launch_grad_x(const double* taubar, const void* tau, bool tau64, int 
 
 hipError_t launch_grad_final(const double* partT, int64_t nbT, const double* partX, int64_t nbX,
                              const double* partR, int64_t nbR, const double* T, const double* lnP,
-                             int nlay, int nspec, double T0, double* out, hipStream_t st) {
+                             int nlay, int nspec, double T0, int powerlaw, double* out, hipStream_t st) {
   hipLaunchKernelGGL(k_grad_final, dim3(1), dim3(256), 0, st, partT, nbT, partX, nbX, partR, nbR,
-                     T, lnP, nlay, nspec, T0, out);
+                     T, lnP, nlay, nspec, T0, powerlaw, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_rt_jvp(const RtArgs& R, const JvpArgs& J, hipStream_t st) {
+  hipLaunchKernelGGL(k_rt_jvp<float>, dim3(nb(R.ng)), dim3(256), 0, st, R, J);
+  return hipGetLastError();
+}
+
+hipError_t launch_response_jvp(const RespDev& R, const double* F0, const double* dF0, double d_rv,
+                               double d_vsini, double* dmid, float* dout, hipStream_t st) {
+  const int64_t nmid = R.ol + 2 * R.K;
+  hipLaunchKernelGGL(k_conv_rot_jvp, dim3(nb(nmid)), dim3(256), 0, st, R, F0, dF0, d_rv, d_vsini,
+                     dmid, nmid);
+  hipLaunchKernelGGL(k_conv_ip<float>, dim3(nb(R.ol)), dim3(256), 0, st, R, dmid, dout);
   return hipGetLastError();
 }
 

@@ -22,7 +22,7 @@ namespace {
 
 struct Request {
   int64_t id = 0;
-  std::vector<double> P, logx;
+  std::vector<double> P, logx, T;
   std::vector<int32_t> species;
   exo_atmos atm{};
   exo_response resp{};
@@ -286,6 +286,10 @@ extern "C" int exo_server_submit(exo_server* s, const exo_atmos* a, const exo_re
   q->atm.P_bar = q->P.data();
   q->atm.log10_mmr = q->logx.data();
   q->atm.species = q->species.data();
+  if (a->T_layers) {
+    q->T.assign(a->T_layers, a->T_layers + a->n_layers);
+    q->atm.T_layers = q->T.data();
+  }
   if (r) {
     q->resp = *r;
     q->has_resp = true;

@@ -1,0 +1,224 @@
+"""Forward-mode derivatives (exo_flux_jvp) and the layer-by-layer temperature
+model (Sec. 6.1) through the C ABI, against the FP64 oracle.
+
+Tolerances: J dtheta per output point relative to max |J dtheta| (1e-3, the
+gradient tolerance); gradients per component as in the VJP parity tests; the
+dot-product identity <cot, J dtheta> = <J^T cot, dtheta> between the GPU's own
+JVP and VJP to 1e-5 (both use the same FP32 Voigt tangents).
+"""
+import sys
+from dataclasses import replace
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+RTOL_GRAD = 1e-3
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def exo():
+    import paper_2105_14782_amd as pkg
+    pkg.load_library()
+    from paper_2105_14782_amd import api
+    return api
+
+
+def _ctx(exo, wl):
+    c = exo.Context(0)
+    for s, ll in enumerate(wl.lines):
+        c.set_lines(s, ll)
+    c.set_grid(wl.nu)
+    return c
+
+
+def _inputs(exo, wl, th):
+    atm = exo.Atmos.from_workload(wl.atmos, list(range(len(wl.lines))), th)
+    resp = exo.Response.from_workload(wl.response, th) if wl.response is not None else None
+    return atm, resp
+
+
+def _rel(a, ref):
+    a, ref = np.asarray(a, float), np.asarray(ref, float)
+    return float(np.max(np.abs(a - ref)) / np.max(np.abs(ref)))
+
+
+def _dtheta(rng):
+    return rng.normal(size=6) * np.array([5.0, 1e-3, 1e-2, 1e-2, 0.1, 0.1])
+
+
+def _layer_profile(wl, th, seed):
+    rng = np.random.default_rng(seed)
+    T = O.temperatures(wl.atmos.P_bar, th[0], th[1])
+    return T * (1 + 0.08 * rng.uniform(-1, 1, T.size))
+
+
+def test_jvp_against_oracle(exo):
+    _say("flux_jvp small vs oracle")
+    wl = synth.make_config(4, "small")
+    th = wl.theta
+    c = _ctx(exo, wl)
+    atm, resp = _inputs(exo, wl, th)
+    dth = _dtheta(np.random.default_rng(1))
+    F, dF = c.flux_jvp(atm, resp, dth)
+    assert torch.equal(F.cpu(), c.emission_flux(atm, resp, "fp32").cpu())
+    _, ref = O.flux_jvp(wl, th, dth)
+    err = _rel(dF.cpu().double().numpy(), ref)
+    _say(f"  J dtheta max rel err {err:.2e}")
+    assert err < RTOL_GRAD
+
+
+def test_jvp_single_directions_without_response(exo):
+    """Each parameter direction alone on F0 (no response), against the oracle."""
+    wl = replace(synth.make_config(4, "small"), response=None)
+    th = wl.theta
+    c = _ctx(exo, wl)
+    atm, _ = _inputs(exo, wl, th)
+    t = O.flux_tangents(wl, th)
+    for k in range(4):
+        e = np.zeros(6)
+        e[k] = 1.0
+        F, dF = c.flux_jvp(atm, None, e)
+        err = _rel(dF.cpu().double().numpy(), t["dF"][k])
+        _say(f"  direction {k}: max rel err {err:.2e}")
+        assert err < RTOL_GRAD, k
+
+
+def test_jvp_vjp_dot_product(exo):
+    wl = synth.make_config(4, "small")
+    th = wl.theta
+    c = _ctx(exo, wl)
+    atm, resp = _inputs(exo, wl, th)
+    rng = np.random.default_rng(2)
+    dth = _dtheta(rng)
+    dT = rng.normal(size=wl.atmos.P_bar.size) * 2.0
+    cot = torch.tensor(rng.normal(size=resp.out_len), dtype=torch.float32, device="cuda")
+    _, dF = c.flux_jvp(atm, resp, dth, dT, want_flux=False)
+    g, gl, _ = c.flux_vjp(atm, resp, cot, want_layers=True)
+    lhs = float(torch.dot(cot.double(), dF.double()))
+    rhs = float(np.dot(g, dth) + np.dot(gl, dT))
+    _say(f"  <cot, J dth> = {lhs:.10e}, <J^T cot, dth> = {rhs:.10e}")
+    assert abs(lhs - rhs) <= 1e-5 * max(abs(lhs), abs(rhs))
+
+
+def test_layer_profile_equal_to_power_law(exo):
+    wl = synth.make_config(4, "small")
+    th = wl.theta
+    c = _ctx(exo, wl)
+    atm, resp = _inputs(exo, wl, th)
+    T = O.temperatures(wl.atmos.P_bar, th[0], th[1])
+    F_pl = c.emission_flux(atm, resp, "fp32").cpu().double().numpy()
+    F_l = c.emission_flux(replace(atm, T_layers=T), resp, "fp32").cpu().double().numpy()
+    assert _rel(F_l, F_pl) < 1e-6
+
+
+def test_layer_profile_gradients_against_oracle(exo):
+    """VJP (per-layer gradient) and JVP (per-layer direction) of a
+    non-monotonic layer-by-layer profile."""
+    _say("layer-by-layer profile: VJP and JVP vs oracle")
+    wl = synth.make_config(4, "small")
+    th = wl.theta
+    T = _layer_profile(wl, th, 5)
+    wl_l = replace(wl, atmos=replace(wl.atmos, T_layers=T))
+    c = _ctx(exo, wl_l)
+    atm, resp = _inputs(exo, wl_l, th)
+    assert atm.T_layers is not None
+    F_star = O.emission_flux(wl_l, th)
+    rng = np.random.default_rng(6)
+    data = F_star * (1 + 0.01 * rng.normal(size=F_star.size))
+    sigma = 0.01 * F_star
+    F = c.emission_flux(atm, resp, "fp32").double()
+    cot = (-(torch.tensor(data, device="cuda") - F) / torch.tensor(sigma, device="cuda") ** 2).float()
+    g, gl, _ = c.flux_vjp(atm, resp, cot.contiguous(), want_layers=True)
+    _, g_ref, gl_ref = O.loss_gradient(wl_l, th, data, sigma, per_layer=True)
+    assert g[0] == 0.0 and g[1] == 0.0
+    scale = np.maximum(np.abs(g_ref[2:]), 1e-6 * np.abs(g_ref[2:]).max())
+    assert np.all(np.abs(g[2:] - g_ref[2:]) / scale < RTOL_GRAD), (g, g_ref)
+    errl = np.abs(gl - gl_ref) / np.maximum(np.abs(gl_ref), 1e-6 * np.abs(gl_ref).max())
+    _say(f"  per-layer gradient max rel err {errl.max():.2e}")
+    assert np.max(errl) < 5e-3
+    dT = rng.normal(size=T.size) * 3.0
+    dth = _dtheta(rng)
+    _, dF = c.flux_jvp(atm, resp, dth, dT, want_flux=False)
+    _, ref = O.flux_jvp(wl_l, th, dth, dT)
+    err = _rel(dF.cpu().double().numpy(), ref)
+    _say(f"  J (dtheta, dT) max rel err {err:.2e}")
+    assert err < RTOL_GRAD
+
+
+def test_forward_mode_autograd(exo):
+    import torch.autograd.forward_ad as fwAD
+    wl = synth.make_config(4, "tiny")
+    th = wl.theta
+    c = _ctx(exo, wl)
+    atm, resp = _inputs(exo, wl, None)
+    dth = _dtheta(np.random.default_rng(7))
+    with fwAD.dual_level():
+        theta = fwAD.make_dual(torch.tensor(th, dtype=torch.float64), torch.tensor(dth))
+        F = exo.EmissionFlux.apply(theta, c, atm, resp)
+        dF = fwAD.unpack_dual(F).tangent
+    _, ref = O.flux_jvp(wl, th, dth)
+    assert _rel(dF.cpu().double().numpy(), ref) < RTOL_GRAD
+
+
+def test_layer_autograd_function(exo):
+    """LayerEmissionFlux: backward gives dL/dT_n and dL/dphi, forward mode J (dT, dphi)."""
+    import torch.autograd.forward_ad as fwAD
+    wl = synth.make_config(4, "tiny")
+    th = wl.theta
+    T = _layer_profile(wl, th, 9)
+    wl_l = replace(wl, atmos=replace(wl.atmos, T_layers=T))
+    c = _ctx(exo, wl_l)
+    atm, resp = _inputs(exo, wl_l, None)
+    F_star = O.emission_flux(wl_l, th)
+    rng = np.random.default_rng(10)
+    data = F_star * (1 + 0.01 * rng.normal(size=F_star.size))
+    sigma = 0.01 * F_star
+    Tt = torch.tensor(T, dtype=torch.float64, requires_grad=True)
+    phi = torch.tensor(th[2:], dtype=torch.float64, requires_grad=True)
+    F = exo.LayerEmissionFlux.apply(Tt, phi, c, atm, resp)
+    d = torch.tensor(data, device="cuda", dtype=torch.float32)
+    s = torch.tensor(sigma, device="cuda", dtype=torch.float32)
+    (0.5 * torch.sum(((d - F) / s) ** 2)).backward()
+    _, g_ref, gl_ref = O.loss_gradient(wl_l, th, data, sigma, per_layer=True)
+    errl = np.abs(Tt.grad.numpy() - gl_ref) / np.maximum(np.abs(gl_ref), 1e-6 * np.abs(gl_ref).max())
+    assert errl.max() < 5e-3
+    errp = np.abs(phi.grad.numpy() - g_ref[2:]) / np.maximum(np.abs(g_ref[2:]), 1e-6 * np.abs(g_ref[2:]).max())
+    assert errp.max() < 5e-3
+    dT = rng.normal(size=T.size) * 3.0
+    dphi = np.array([1e-2, -1e-2, 0.1, 0.1])
+    with fwAD.dual_level():
+        Td = fwAD.make_dual(torch.tensor(T), torch.tensor(dT))
+        pd = fwAD.make_dual(torch.tensor(th[2:]), torch.tensor(dphi))
+        dF = fwAD.unpack_dual(exo.LayerEmissionFlux.apply(Td, pd, c, atm, resp)).tangent
+    _, ref = O.flux_jvp(wl_l, th, np.concatenate([[0.0, 0.0], dphi]), dT)
+    assert _rel(dF.cpu().double().numpy(), ref) < RTOL_GRAD
+
+
+def test_jvp_and_layer_profile_errors(exo):
+    import paper_2105_14782_amd as pkg
+    wl = synth.make_config(4, "tiny")
+    th = wl.theta
+    c = _ctx(exo, wl)
+    atm, resp = _inputs(exo, wl, th)
+    with pytest.raises(pkg.ExoError) as e:
+        c.emission_flux(replace(atm, T_layers=np.full(wl.atmos.P_bar.size, 0.5)), resp)
+    assert e.value.code == pkg.EXO_EINVAL
+    bad = np.zeros(6)
+    bad[3] = np.nan
+    with pytest.raises(pkg.ExoError) as e:
+        c.flux_jvp(atm, resp, bad)
+    assert e.value.code == pkg.EXO_EINVAL
+    with pytest.raises(pkg.ExoError) as e:
+        c.flux_jvp(replace(atm, P_bar=np.logspace(-8, 2, 5000)), resp, np.zeros(6))
+    assert e.value.code == pkg.EXO_EINVAL
