@@ -45,6 +45,8 @@ def parse():
     ap.add_argument("--size", default="full", choices=["small", "medium", "full"])
     ap.add_argument("--fp64-reps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-modit", action="store_true", help="skip the MODIT-vs-direct cross-section runs")
+    ap.add_argument("--modit-only", action="store_true", help="only the MODIT-vs-direct runs (for profiling)")
     ap.add_argument("--cpu-points", type=int, default=192)
     ap.add_argument("--serve-requests", type=int, default=48,
                     help="requests of the Poisson serving run (0: skip)")
@@ -54,6 +56,8 @@ def parse():
                     help="write the VALU-issue summary from a --pmc run of --counters and exit")
     ap.add_argument("--summarize-stats", metavar="STATS_CSV",
                     help="write the kernel-time summary from a rocprofv3 --stats run and exit")
+    ap.add_argument("--summarize-modit-stats", metavar="STATS_CSV",
+                    help="write the MODIT kernel-time summary from a rocprofv3 --stats run of --modit-only")
     ap.add_argument("--counters", action="store_true",
                     help="one step plus a 512 MiB device copy (calibration), for rocprofv3 --pmc runs")
     return ap.parse_args()
@@ -77,7 +81,7 @@ def cpu_baseline(wl, theta, n_points):
 
 
 VOIGT_SOURCES = ["paper_2105_14782_amd/csrc/k_voigt.hip", "paper_2105_14782_amd/csrc/exo_device.h",
-                 "paper_2105_14782_amd/csrc/exo_launch.h"]
+                 "paper_2105_14782_amd/csrc/exo_launch.h", "paper_2105_14782_amd/csrc/exo_lines.h"]
 TRAFFIC_PROFILE = "profiles/voigt_tangent_config2_traffic.md"
 
 
@@ -157,6 +161,7 @@ def summarize_counters(fetch_csv, write_csv, out_path):
 
 VALU_PROFILE = "profiles/voigt_tangent_config2_valu.md"
 STATS_PROFILE = "profiles/voigt_config2_kernel_stats.md"
+MODIT_PROFILE = "profiles/modit_config3_kernel_stats.md"
 VALU_COUNTERS = "SQ_INSTS_VALU SQ_INSTS_VALU_TRANS_F32 SQ_ACTIVE_INST_VALU SQ_BUSY_CYCLES GRBM_GUI_ACTIVE"
 
 
@@ -202,27 +207,83 @@ def summarize_valu(csv_path, out_path):
     print("\n".join(lines))
 
 
-def summarize_stats(csv_path, out_path):
+def summarize_stats(csv_path, out_path, modit=False):
     """Markdown table of a rocprofv3 --kernel-trace --stats run of the bench."""
     import csv
     rows = list(csv.DictReader(open(csv_path)))
-    lines = [
-        "# Kernel trace summary: config-2 emission bench (rocprofv3 --kernel-trace --stats)", "",
-        "Command (repository root, one MI355X):", "", "```",
-        "rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/prof_bench -o bench -- \\",
-        "    python3 bench.py --steps 3 --warmup 1 --no-cpu-baseline --fp64-reps 1 --serve-requests 0",
-        "python3 bench.py --summarize-stats gpurun_out/prof_bench/bench_kernel_stats.csv", "```", "",
-        "Workload: 2 species x 1e5 lines, 20,000-point log-uniform grid, 100 layers.",
-        "The run does 1 warm-up + 3 timed flux_vjp steps (two tangent-mode Voigt sums each),",
-        "then 4 FP32 forward spectra and 2 plain-FP64 forward spectra (two Voigt sums each).", "",
-        "| kernel | calls | avg ms | total ms | % |", "|---|---:|---:|---:|---:|",
-    ]
+    if modit:
+        head = [
+            "# Kernel trace summary: MODIT vs direct cross-section, config-3 grid (rocprofv3 --kernel-trace --stats)", "",
+            "Command (repository root, one MI355X):", "", "```",
+            "rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/prof_modit -o modit -- \\",
+            "    python3 bench.py --modit-only",
+            "python3 bench.py --summarize-modit-stats gpurun_out/prof_modit/modit_kernel_stats.csv", "```", "",
+            "Workload: one layer (1300 K, 1 bar) of the config-3 line list, 100,000-point grid at R0 = 1e6,",
+            "at 1e5, 1e6 and 1e7 lines: each size runs 6 MODIT cross-sections in FP32 and 6 in FP64",
+            "(transform length 262,144: 9 radix-4 Stockham passes forward over the width rows, 9 inverse),",
+            "and 4, 4 and 2 direct FP32 cross-sections (`k_voigt_f32<false, 4>`).", "",
+        ]
+    else:
+        head = [
+            "# Kernel trace summary: config-2 emission bench (rocprofv3 --kernel-trace --stats)", "",
+            "Command (repository root, one MI355X):", "", "```",
+            "rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/prof_bench -o bench -- \\",
+            "    python3 bench.py --steps 3 --warmup 1 --no-cpu-baseline --fp64-reps 1 --serve-requests 0 --no-modit",
+            "python3 bench.py --summarize-stats gpurun_out/prof_bench/bench_kernel_stats.csv", "```", "",
+            "Workload: 2 species x 1e5 lines, 20,000-point log-uniform grid, 100 layers.",
+            "The run does 1 warm-up + 3 timed flux_vjp steps (two tangent-mode Voigt sums each),",
+            "then 4 FP32 forward spectra and 2 plain-FP64 forward spectra (two Voigt sums each),",
+            "then the flux_jvp timing calls (tangent-mode Voigt sums as well).", "",
+        ]
+    lines = head + ["| kernel | calls | avg ms | total ms | % |", "|---|---:|---:|---:|---:|"]
     for r in rows:
         name = r["Name"] if len(r["Name"]) <= 70 else r["Name"][:67] + "..."
         lines.append(f"| `{name}` | {r['Calls']} | {float(r['AverageNs']) / 1e6:.3f} | "
                      f"{float(r['TotalDurationNs']) / 1e6:.2f} | {float(r['Percentage']):.2f} |")
     open(out_path, "w").write("\n".join(lines) + "\n")
     print("\n".join(lines))
+
+
+def modit_bench(reps=5):
+    """MODIT (Sec. 2.1.2) against the direct sum on the throughput workload
+    (config 3: lines U(4340, 4796.44) cm^-1, 100,000-point grid at R0 = 1e6),
+    one layer at T = 1300 K, P = 1 bar, as the paper benchmarks opacity time
+    against the number of lines: 1e5, 1e6 and 1e7 lines (every 100th, every
+    10th, all)."""
+    import torch
+    import synth
+    from dataclasses import replace
+    from paper_2105_14782_amd import api
+    wl = synth.make_config(3, "full")
+    full = wl.lines[0]
+    ctx = api.Context(0)
+    ctx.set_grid(wl.nu)
+    T, P = 1300.0, 1.0
+    out = {"workload": "config-3 single layer (T = 1300 K, P = 1 bar), 100,000-point grid at R0 = 1e6",
+           "runs": []}
+
+    def timed(fn, n):
+        fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(n):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) / n
+
+    for stride in (100, 10, 1):
+        sub = full if stride == 1 else replace(
+            full, nu_c=full.nu_c[::stride], S0=full.S0[::stride], E_low=full.E_low[::stride],
+            alpha_ref=full.alpha_ref[::stride], n_texp=full.n_texp[::stride])
+        ctx.set_lines(0, sub)
+        run = {"lines": int(sub.n)}
+        for prec in ("fp32", "fp64"):
+            run[f"modit_{prec}_ms"] = 1e3 * timed(lambda: ctx.cross_section_modit(0, T, P, prec), reps)
+        run["direct_fp32_ms"] = 1e3 * timed(lambda: ctx.cross_section(0, T, P, "fp32"), 1 if stride == 1 else 3)
+        run["direct_over_modit_fp32"] = run["direct_fp32_ms"] / run["modit_fp32_ms"]
+        out["runs"].append(run)
+    ctx.close()
+    return out
 
 
 SERVE_MARGIN = 260   # output margin (points) at R0 = 1e6: rotation + RV + 6-sigma IP reach < 200
@@ -287,10 +348,16 @@ def main():
     if args.summarize_stats:
         summarize_stats(args.summarize_stats, os.path.join(ROOT, STATS_PROFILE))
         return
+    if args.summarize_modit_stats:
+        summarize_stats(args.summarize_modit_stats, os.path.join(ROOT, MODIT_PROFILE), modit=True)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
                           "n_gpus": args.gpus}))
         sys.exit(2)
+    if args.modit_only:
+        print(json.dumps({"modit": modit_bench()}), flush=True)
+        return
     import torch
     import synth
     from paper_2105_14782_amd import api
@@ -407,6 +474,8 @@ def main():
     ctx.close()
     if args.serve_requests > 0:
         out["serving"] = serving_bench(args.serve_requests)
+    if not args.no_modit:
+        out["modit"] = modit_bench()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, theta, args.cpu_points)
     print(json.dumps(out), flush=True)

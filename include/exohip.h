@@ -129,6 +129,22 @@ int exo_set_grid(exo_ctx* ctx, int64_t n_nu, const double* nu);
 int exo_cross_section(exo_ctx* ctx, int s, double T_K, double P_bar, int precision,
                       void* sigma_dev, void* stream);
 
+/* The same cross-section by MODIT (Sec. 2.1.2), the paper's method for many
+ * lines: a lineshape density on the log-uniform grid (q = R0 ln nu, every
+ * line split over the neighbouring grid points and log-spaced Lorentz-width
+ * bins with linear weights) convolved with the Voigt profile through its
+ * Fourier transform exp(-2 pi^2 beta~^2 f^2 - 2 pi gamma~ |f|), with the
+ * common Doppler width beta~ = sqrt(k_B T/(M m_u)) R0/c in grid steps.
+ *   dln_gamma  step of the width bins in ln(gamma R0/nu) (>= 1e-3; the bins
+ *              widen when more than 32 would be needed)
+ * Needs a log-uniform grid.  Only lines with nu_0 <= nu_l <= nu_{N-1} enter
+ * the density; the transform length is the smallest power of two >= 2N (the
+ * aliasing correction the paper mentions is unpublished and not applied).
+ * sigma_dev as exo_cross_section.  Errors: EXO_EINVAL, EXO_ENOTSET,
+ * EXO_ENOMEM, EXO_EDEVICE. */
+int exo_cross_section_modit(exo_ctx* ctx, int species, double T_K, double P_bar, int precision,
+                            double dln_gamma, void* sigma_dev, void* stream);
+
 /* Atmosphere of Sec. 3 with the power-law T-P profile of Sec. 5.2:
  * T_n = T0 (P_n / 1 bar)^alpha, layer 0 at the top (lowest pressure).
  * dP_n = P_n - P_{n-1} with P_{-1} = P_0^2/P_1.  Molecular optical depth of

@@ -92,6 +92,7 @@ def load_library(path: str = LIB_PATH):
         "exo_profile_enable": ([V, I], I),
         "exo_profile_read": ([V, ctypes.POINTER(I64), ctypes.POINTER(D), ctypes.POINTER(D)], I),
         "exo_profile_read_near": ([V, ctypes.POINTER(D)], I),
+        "exo_cross_section_modit": ([V, I, D, D, I, D, V, V], I),
         "exo_flux_jvp": ([V, ctypes.POINTER(ExoAtmos), ctypes.POINTER(ExoResponse), I, _c_dp, _c_dp, V, V, V], I),
     }
     for name, (args, res) in sig.items():

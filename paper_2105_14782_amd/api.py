@@ -156,6 +156,19 @@ class Context:
                                             ctypes.c_void_p(out.data_ptr()), _stream(stream)))
         return out
 
+    def cross_section_modit(self, slot: int, T: float, P_bar: float, precision="fp32", dln_gamma=0.1,
+                            out=None, stream=None):
+        """MODIT cross-section (Sec. 2.1.2) on the context's log-uniform grid."""
+        p = _prec(precision)
+        dt = torch.float64 if p == L.EXO_FP64 else torch.float32
+        if out is None:
+            out = torch.empty(self.n_nu, dtype=dt, device=f"cuda:{self.device}")
+        assert out.dtype == dt and out.is_contiguous() and out.numel() == self.n_nu
+        L.check(self._lib.exo_cross_section_modit(self._h, int(slot), float(T), float(P_bar), p,
+                                                  float(dln_gamma), ctypes.c_void_p(out.data_ptr()),
+                                                  _stream(stream)))
+        return out
+
     def _out_len(self, atmos: Atmos, response: Optional[Response]):
         if response is not None:
             return int(response.out_len)

@@ -32,7 +32,7 @@ struct DevBuf {
 struct Workspace {
   static constexpr size_t kStageDoubles = 1 << 14;
   DevBuf rec, rect, core, rec64, tau, taut, part, part_t, F0, F0bar, mid, midbar, Fup, taubar, layer,
-      col, taps, partT, partX, partR, gout, params;
+      col, taps, partT, partX, partR, gout, params, mlines, mpart, mrows0, mrows1;
   double* h_stage = nullptr;     // pinned staging for per-call parameters
   hipEvent_t stage_ev = nullptr; // guards h_stage reuse
   RtArgs last_rt{};
@@ -44,7 +44,8 @@ struct Workspace {
   void bind_arena(char* base, size_t cap);
   std::vector<DevBuf*> bufs() {
     return {&rec, &rect, &core, &rec64, &tau, &taut, &part, &part_t, &F0, &F0bar, &mid, &midbar,
-            &Fup, &taubar, &layer, &col, &taps, &partT, &partX, &partR, &gout, &params};
+            &Fup, &taubar, &layer, &col, &taps, &partT, &partX, &partR, &gout, &params,
+            &mlines, &mpart, &mrows0, &mrows1};
   }
   hipEvent_t done_ev = nullptr;  // end of the last evaluation using this workspace
   hipStream_t last_st = nullptr;
@@ -72,6 +73,7 @@ struct Species {
   double mass = 0;
   int qr_kind = 0, n_qr = 0;
   double nu_lo = 0, nu_hi = 0;
+  std::vector<double> h_nu_c;   // sorted centres (host copy: window ranges without a device round trip)
   void release();
 };
 

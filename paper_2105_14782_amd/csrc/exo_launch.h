@@ -88,6 +88,29 @@ struct JvpArgs {
   double* dF0;           // [ng] output
 };
 
+// MODIT (Sec. 2.1.2) of one species at one (T, P).
+constexpr int kModitMaxBins = 32;   // width bins of the lineshape density
+struct ModitBins {
+  double lng0, d;   // ln gamma~_k = lng0 + k d
+  int K;
+  int pad;
+};
+struct ModitArgs {
+  LinesDev L;
+  double T, P, R0, beta_t, amp_scale, dlng;
+  const double* nu;        // grid [ng] (log-uniform)
+  int64_t ng, n_fft;
+  const double* nu_c;      // sorted centres (= L.nu_c)
+  int64_t l0, n_in;        // lines inside the grid: [l0, l0 + n_in)
+  double *x, *lng, *S;     // per-line scratch [n_in]
+  double* part;            // [2 n_part] min/max partials
+  int64_t n_part;
+  ModitBins* bins;         // device
+  void *rows0, *rows1;     // [kModitMaxBins][n_fft] complex (float2 or double2)
+  void* out;               // [ng] float or double
+  bool out64;
+};
+
 // Response (rotation + IP) on the model grid.
 struct RespDev {
   int64_t dlo, nrot;     // rotation taps for d = dlo .. dlo + nrot - 1, d = i - j
@@ -102,6 +125,7 @@ hipError_t launch_line_records(const LinesDev& L, const double* T_lay, const dou
                                LineRec* rec, LineRecT* rect, LineCore* core, LineRec64* rec64,
                                hipStream_t st);
 hipError_t launch_voigt(const VoigtArgs& A, bool fp64, bool tangent, hipStream_t st);
+hipError_t launch_modit(const ModitArgs& M, bool fp64, hipStream_t st);
 hipError_t launch_hjert_f32(int64_t n, const float* x, const float* a, float* H, float* L,
                             hipStream_t st);
 hipError_t launch_hjert_f64(int64_t n, const double* x, const double* a, double* H, hipStream_t st);

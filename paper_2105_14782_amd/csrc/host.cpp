@@ -201,6 +201,8 @@ extern "C" int exo_destroy(exo_ctx* c) {
 
 void Species::release() {
   for (DevBuf* b : {&nu_c, &S0, &E_low, &alpha_ref, &n_texp, &gamma_nat, &qr}) b->release();
+  h_nu_c.clear();
+  h_nu_c.shrink_to_fit();
   set = false;
   n = 0;
 }
@@ -278,6 +280,8 @@ extern "C" int exo_set_lines(exo_ctx* c, int s, int64_t n, const double* nu_c, c
   sp.mass = mass_amu;
   sp.qr_kind = qr_kind;
   sp.n_qr = n_qr;
+  sp.h_nu_c.resize(n);
+  for (int64_t i = 0; i < n; ++i) sp.h_nu_c[i] = nu_c[idx[i]];
   sp.nu_lo = tmp.empty() ? 0 : nu_c[idx.front()];
   sp.nu_hi = nu_c[idx.back()];
   sp.set = true;
@@ -513,6 +517,64 @@ int exo::species_opacity(exo_ctx* c, Workspace& ws, const Species& sp, const dou
     if ((rc = voigt_launch_profiled(c, A, fp64, tangent, st))) return rc;
   }
   return EXO_OK;
+}
+
+extern "C" int exo_cross_section_modit(exo_ctx* c, int s, double T, double P, int precision,
+                                       double dln_gamma, void* sigma, void* stream) {
+  if (!c) return set_err(EXO_EINVAL, "ctx is NULL");
+  if (s < 0 || s >= EXO_MAX_SPECIES) return set_err(EXO_EINVAL, "species slot %d out of range", s);
+  if (!c->sp[s].set) return set_err(EXO_ENOTSET, "species slot %d not set", s);
+  if (c->n_nu < 2) return set_err(EXO_ENOTSET, "grid not set");
+  if (!c->eslog) return set_err(EXO_EINVAL, "MODIT needs a log-uniform grid");
+  if (!(T > 0) || !(P >= 0) || !std::isfinite(T) || !std::isfinite(P))
+    return set_err(EXO_EINVAL, "need T > 0 and P >= 0");
+  if (precision != EXO_FP32_KAHAN && precision != EXO_FP64) return set_err(EXO_EINVAL, "bad precision");
+  if (!(dln_gamma >= 1e-3) || !std::isfinite(dln_gamma)) return set_err(EXO_EINVAL, "dln_gamma must be >= 1e-3");
+  if (!sigma) return set_err(EXO_EINVAL, "sigma_dev is NULL");
+  HIP_TRY(hipSetDevice(c->device));
+  std::lock_guard<std::mutex> g(c->mu);
+  hipStream_t st = (hipStream_t)stream;
+  const Species& sp = c->sp[s];
+  const bool fp64 = precision == EXO_FP64;
+  const int64_t ng = c->n_nu;
+  ModitArgs M{};
+  M.L = lines_dev(sp);
+  M.T = T;
+  M.P = P;
+  M.R0 = kCkms / c->dv_kms;   // 1 / mean ln spacing
+  M.beta_t = std::sqrt(kKB * T / (sp.mass * kMU)) * M.R0 / kC;
+  // FP32: the same exact power-of-two scale as the direct cross-section
+  M.amp_scale = fp64 ? 1.0 : 18446744073709551616.0;
+  M.dlng = dln_gamma;
+  M.nu = (const double*)c->d_nu.p;
+  M.ng = ng;
+  M.n_fft = 1;
+  while (M.n_fft < 2 * ng) M.n_fft *= 2;
+  M.nu_c = (const double*)sp.nu_c.p;
+  const auto& h = sp.h_nu_c;
+  M.l0 = std::lower_bound(h.begin(), h.end(), c->h_nu.front()) - h.begin();
+  M.n_in = (std::upper_bound(h.begin(), h.end(), c->h_nu.back()) - h.begin()) - M.l0;
+  M.n_part = 1024;
+  M.out = sigma;
+  M.out64 = fp64;
+  return with_ws(c->ws, st, [&]() -> int {
+    Workspace& ws = c->ws;
+    int rc;
+    const size_t csz = fp64 ? 2 * sizeof(double) : 2 * sizeof(float);
+    if ((rc = ws.reserve(ws.mlines, (size_t)3 * std::max<int64_t>(M.n_in, 1) * sizeof(double)))) return rc;
+    if ((rc = ws.reserve(ws.mpart, (size_t)2 * M.n_part * sizeof(double) + 256))) return rc;
+    if ((rc = ws.reserve(ws.mrows0, (size_t)kModitMaxBins * M.n_fft * csz))) return rc;
+    if ((rc = ws.reserve(ws.mrows1, (size_t)kModitMaxBins * M.n_fft * csz))) return rc;
+    M.x = (double*)ws.mlines.p;
+    M.lng = M.x + M.n_in;
+    M.S = M.lng + M.n_in;
+    M.part = (double*)ws.mpart.p;
+    M.bins = (ModitBins*)((char*)ws.mpart.p + 2 * M.n_part * sizeof(double));
+    M.rows0 = ws.mrows0.p;
+    M.rows1 = ws.mrows1.p;
+    HIP_TRY(launch_modit(M, fp64, st));
+    return EXO_OK;
+  });
 }
 
 extern "C" int exo_cross_section(exo_ctx* c, int s, double T, double P, int precision, void* sigma,

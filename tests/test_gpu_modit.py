@@ -1,0 +1,151 @@
+"""MODIT (Sec. 2.1.2) on the GPU, through the C ABI, against the MODIT oracle.
+
+Tolerances, relative to the largest cross-section value (a discrete
+convolution by DFT carries its rounding at the level of the largest terms):
+1e-10 in FP64, 1e-5 in FP32.  Pointwise relative errors are also checked in
+FP32 where the cross-section exceeds 1e-2 of its maximum; App. B notes that
+FP32 MODIT loses the bottoms of a wide dynamic range, so the floor of the
+comparison is not lower.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import oracle as O
+from oracle import modit as M
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def exo():
+    import paper_2105_14782_amd as pkg
+    pkg.load_library()
+    from paper_2105_14782_amd import api
+    return api
+
+
+def _lines(rng, centres, alpha=(0.01, 0.1), mass=18.0, gnat=None):
+    n = centres.size
+    return synth.LineList(np.sort(centres), 10 ** rng.uniform(-23, -20, n), rng.exponential(1000, n),
+                          10 ** rng.uniform(math.log10(alpha[0]), math.log10(alpha[1]), n),
+                          rng.uniform(0.5, 0.8, n), mass, 0, np.array([1.5]), gamma_nat=gnat)
+
+
+def _grid(n, R0=1e6, nu0=4340.0):
+    return nu0 * np.exp(np.arange(n) / R0)
+
+
+def _run(exo, ll, nu, T, P, prec, dlng=0.1):
+    c = exo.Context(0)
+    c.set_lines(2, ll)
+    c.set_grid(nu)
+    got = c.cross_section_modit(2, T, P, prec, dlng).cpu().double().numpy()
+    return c, got
+
+
+def _err(got, ref):
+    return float(np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
+
+
+CASES = [
+    # (n_nu, n_lines, T, P, extra)
+    (2, 1, 1000.0, 1.0, "on_node"),
+    (3, 2, 1000.0, 1.0, ""),
+    (1000, 1, 1500.0, 0.1, ""),
+    (1000, 400, 800.0, 3.0, "ends"),
+    (4097, 2000, 2000.0, 0.05, "outside"),
+    (3000, 1500, 1200.0, 0.0, ""),
+    (5000, 3000, 1300.0, 10.0, "wide_alpha"),
+]
+
+
+def _case(n_nu, n_lines, extra, seed):
+    rng = np.random.default_rng(seed)
+    nu = _grid(n_nu)
+    if extra == "on_node":
+        centres = np.array([nu[0]])
+    else:
+        centres = rng.uniform(nu[0], nu[-1], n_lines)
+    if extra == "ends":
+        centres[:3] = [nu[0], nu[-1], nu[n_nu // 2]]
+    if extra == "outside":
+        centres = np.concatenate([centres, nu[0] - rng.uniform(0.01, 5, 50), nu[-1] + rng.uniform(0.01, 5, 50)])
+    alpha = (1e-5, 10.0) if extra == "wide_alpha" else (0.01, 0.1)
+    return nu, _lines(rng, centres, alpha)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("n_nu,n_lines,T,P,extra", CASES)
+def test_modit_against_oracle(exo, prec, n_nu, n_lines, T, P, extra):
+    nu, ll = _case(n_nu, n_lines, extra, n_nu + n_lines)
+    ref, parts = M.modit_cross_section(ll, T, P, nu, want_parts=True)
+    c, got = _run(exo, ll, nu, T, P, prec)
+    err = _err(got, ref)
+    _say(f"  MODIT {prec} n_nu={n_nu} lines={n_lines} {extra}: K={parts['K']} max err / max {err:.2e}")
+    assert err < (1e-10 if prec == "fp64" else 1e-5)
+    if prec == "fp32":
+        keep = ref > 1e-2 * ref.max()
+        assert np.max(np.abs(got[keep] - ref[keep]) / ref[keep]) < 1e-3
+
+
+def test_modit_no_lines_in_window(exo):
+    rng = np.random.default_rng(3)
+    nu = _grid(500)
+    ll = _lines(rng, np.concatenate([nu[0] - rng.uniform(0.1, 1, 5), nu[-1] + rng.uniform(0.1, 1, 5)]))
+    for prec in ("fp32", "fp64"):
+        c, got = _run(exo, ll, nu, 1000.0, 1.0, prec)
+        assert np.all(got == 0.0)
+
+
+def test_modit_close_to_direct_sum(exo):
+    """MODIT against the GPU's own direct LPF on resolved, pressure-broadened
+    lines (the paper's comparison, App. B): within 1 % above 1e-2 of the peak."""
+    rng = np.random.default_rng(4)
+    nu = _grid(4000)
+    ll = _lines(rng, rng.uniform(nu[200], nu[-200], 300))
+    c, got = _run(exo, ll, nu, 1000.0, 1.0, "fp64")
+    direct = c.cross_section(2, 1000.0, 1.0, "fp64").cpu().double().numpy()
+    keep = direct > 1e-2 * direct.max()
+    assert np.max(np.abs(got[keep] - direct[keep]) / direct[keep]) < 1e-2
+
+
+def test_modit_is_deterministic(exo):
+    rng = np.random.default_rng(5)
+    nu = _grid(3000)
+    ll = _lines(rng, rng.uniform(nu[0], nu[-1], 5000))
+    c = exo.Context(0)
+    c.set_lines(0, ll)
+    c.set_grid(nu)
+    for prec in ("fp32", "fp64"):
+        a = c.cross_section_modit(0, 1100.0, 0.5, prec).cpu()
+        b = c.cross_section_modit(0, 1100.0, 0.5, prec).cpu()
+        assert torch.equal(a, b)
+
+
+def test_modit_errors(exo):
+    import paper_2105_14782_amd as pkg
+    rng = np.random.default_rng(6)
+    c = exo.Context(0)
+    ll = _lines(rng, rng.uniform(4340, 4341, 10))
+    c.set_lines(0, ll)
+    c.set_grid(np.linspace(4340, 4341, 100))      # not log-uniform
+    with pytest.raises(pkg.ExoError) as e:
+        c.cross_section_modit(0, 1000.0, 1.0)
+    assert e.value.code == pkg.EXO_EINVAL
+    c.set_grid(_grid(100))
+    with pytest.raises(pkg.ExoError) as e:
+        c.cross_section_modit(0, 1000.0, 1.0, dln_gamma=1e-4)
+    assert e.value.code == pkg.EXO_EINVAL
+    with pytest.raises(pkg.ExoError) as e:
+        c.cross_section_modit(1, 1000.0, 1.0)
+    assert e.value.code == pkg.EXO_ENOTSET
