@@ -2,9 +2,9 @@
  * exohip serving engine: continuous batching of emission-spectrum requests
  * on one GPU.  C ABI; builds on include/exohip.h.
  *
- * The workload is the one the paper's sampler generates (Sec. 5.3): a stream
+ * The workload is the one the paper's sampler generates (Sec. 5.2): a stream
  * of spectrum evaluations at nearby parameters, against line lists that stay
- * resident in GPU memory between evaluations (Sec. 2.5 keeps them on the
+ * resident in GPU memory between evaluations (Sec. 2.6 keeps them on the
  * device across calls for the same reason).
  *
  * Model of operation:
