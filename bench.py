@@ -259,7 +259,10 @@ def modit_bench(reps=5):
     ctx = api.Context(0)
     ctx.set_grid(wl.nu)
     T, P = 1300.0, 1.0
-    out = {"workload": "config-3 single layer (T = 1300 K, P = 1 bar), 100,000-point grid at R0 = 1e6",
+    atm = api.Atmos.from_workload(wl.atmos, [0])
+    T_scan = np.arange(500.0, 1701.0, 100.0)
+    out = {"workload": "config-3 single layer (T = 1300 K, P = 1 bar), 100,000-point grid at R0 = 1e6; "
+                       "line selection on the config-3 100-layer pressure grid",
            "runs": []}
 
     def timed(fn, n):
@@ -281,6 +284,11 @@ def modit_bench(reps=5):
             run[f"modit_{prec}_ms"] = 1e3 * timed(lambda: ctx.cross_section_modit(0, T, P, prec), reps)
         run["direct_fp32_ms"] = 1e3 * timed(lambda: ctx.cross_section(0, T, P, "fp32"), 1 if stride == 1 else 3)
         run["direct_over_modit_fp32"] = run["direct_fp32_ms"] / run["modit_fp32_ms"]
+        # weak-line pre-selection (App. G) of the same list on the config-3 atmosphere:
+        # isothermal 1700 K, strengths scanned over 500-1700 K, margin 2 layers
+        run["select_ms"] = 1e3 * timed(lambda: ctx.select_lines(0, math.log10(0.0023), atm, 1700.0, T_scan, 2),
+                                       reps)
+        run["select_kept"] = ctx.select_lines(0, math.log10(0.0023), atm, 1700.0, T_scan, 2)[1]
         out["runs"].append(run)
     ctx.close()
     return out

@@ -231,6 +231,25 @@ int exo_flux_jvp(exo_ctx* ctx, const exo_atmos* atm, const exo_response* resp,
                  int precision, const double* dtheta_host, const double* dT_layers_host,
                  void* flux_dev, void* dflux_dev, void* stream);
 
+/* Weak-line pre-selection (App. G): which lines of species `species` can
+ * shape the emission spectrum.  In an isothermal atmosphere at T_atm_K on
+ * the pressure grid of `atm` (its n_layers, P_bar, g_cgs, mmw and CIA fields
+ * are used; T0/alpha/T_layers, species and grid fields are not), every line
+ * gets its largest strength over T_strength_host[n_T] (n_T = 0: T_atm alone),
+ * its line-centre optical depth per layer
+ * dP_n/(m_u g) 10^log10_mmr/M S/(sqrt(2 pi) beta) erfcx(gamma_n/(sqrt2 beta))
+ * and the contribution function e^{-tau_n} dtau_n P_n/dP_n (tau_n including
+ * layer n).  The line is kept iff the layer where that peaks (the first
+ * maximum) is at most `margin_layers` deeper than where the H2-H2
+ * continuum's peaks at the line centre (the paper uses 2).
+ *   keep_dev     device [n_lines] uint8, in the caller's order of exo_set_lines:
+ *                1 = kept, 0 = shielded by the continuum
+ *   n_kept_host  NULL, or the number kept (then the call blocks until done)
+ * FP64 throughout.  Errors: EXO_EINVAL, EXO_ENOTSET, EXO_ENOMEM, EXO_EDEVICE. */
+int exo_select_lines(exo_ctx* ctx, int species, double log10_mmr, const exo_atmos* atm,
+                     double T_atm_K, const double* T_strength_host, int n_T, int margin_layers,
+                     uint8_t* keep_dev, int64_t* n_kept_host, void* stream);
+
 /* Response alone (Sec. 4) applied to a caller spectrum F0 on the model grid
  * [grid_begin, grid_begin + grid_len) of the context grid (grid_len 0 = all):
  * F0_dev device [grid_len] double, out_dev device [resp->out_len] double.

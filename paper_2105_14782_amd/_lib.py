@@ -73,6 +73,10 @@ def load_library(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is missing: build it with `python -m paper_2105_14782_amd.build`")
+    # PyTorch ships its own HIP runtime.  When this library (linked against the
+    # system one) is loaded first and PyTorch then initialises the device, this
+    # library's runtime no longer finds it; loading PyTorch first avoids that.
+    import torch  # noqa: F401
     lib = ctypes.CDLL(path)
     V, I, I64, D = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_double
     sig = {
@@ -93,6 +97,8 @@ def load_library(path: str = LIB_PATH):
         "exo_profile_read": ([V, ctypes.POINTER(I64), ctypes.POINTER(D), ctypes.POINTER(D)], I),
         "exo_profile_read_near": ([V, ctypes.POINTER(D)], I),
         "exo_cross_section_modit": ([V, I, D, D, I, D, V, V], I),
+        "exo_select_lines": ([V, I, D, ctypes.POINTER(ExoAtmos), D, _c_dp, I, I, V,
+                              ctypes.POINTER(I64), V], I),
         "exo_flux_jvp": ([V, ctypes.POINTER(ExoAtmos), ctypes.POINTER(ExoResponse), I, _c_dp, _c_dp, V, V, V], I),
     }
     for name, (args, res) in sig.items():

@@ -169,6 +169,20 @@ class Context:
                                                   _stream(stream)))
         return out
 
+    def select_lines(self, slot: int, log10_mmr: float, atmos: Atmos, T_atm: float, T_strength=None,
+                     margin: int = 2, stream=None):
+        """Weak-line pre-selection (App. G): (keep mask on the device, uint8 in
+        the order the lines were given to set_lines; number kept)."""
+        n = self._nlines.get(int(slot), 0)
+        keep = torch.empty(n, dtype=torch.uint8, device=f"cuda:{self.device}")
+        Ts = None if T_strength is None else _f64(T_strength)
+        a, keep_alive = atmos.to_c()
+        nk = ctypes.c_int64()
+        L.check(self._lib.exo_select_lines(self._h, int(slot), float(log10_mmr), ctypes.byref(a), float(T_atm),
+                                           L.dptr(Ts), 0 if Ts is None else int(Ts.size), int(margin),
+                                           ctypes.c_void_p(keep.data_ptr()), ctypes.byref(nk), _stream(stream)))
+        return keep, nk.value
+
     def _out_len(self, atmos: Atmos, response: Optional[Response]):
         if response is not None:
             return int(response.out_len)

@@ -19,7 +19,7 @@ INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 OUT = os.path.join(HERE, "libexohip.so")
 BUILD = os.path.join(HERE, "_build")
 
-SOURCES = ["k_voigt.hip", "k_rt.hip", "k_modit.hip", "host.cpp", "serve.cpp"]
+SOURCES = ["k_voigt.hip", "k_rt.hip", "k_modit.hip", "k_select.hip", "host.cpp", "serve.cpp"]
 ARCH = os.environ.get("EXO_OFFLOAD_ARCH", "gfx950")
 
 COMMON = [

@@ -68,7 +68,7 @@ struct Workspace {
 struct Species {
   bool set = false;
   int64_t n = 0;
-  DevBuf nu_c, S0, E_low, alpha_ref, n_texp, gamma_nat, qr;
+  DevBuf nu_c, S0, E_low, alpha_ref, n_texp, gamma_nat, qr, perm;   // perm: caller index of sorted line i
   bool has_gnat = false;
   double mass = 0;
   int qr_kind = 0, n_qr = 0;

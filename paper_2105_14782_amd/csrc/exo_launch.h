@@ -111,6 +111,20 @@ struct ModitArgs {
   bool out64;
 };
 
+// Weak-line pre-selection (App. G) of one species in an isothermal atmosphere.
+struct SelectArgs {
+  LinesDev L;
+  const int64_t* perm;       // caller index of sorted line i
+  const double* T_strength;  // [n_T] temperatures scanned for the largest strength
+  int n_T;
+  double T_atm;
+  int nlay, margin;
+  const double *P, *dP, *col, *cia;   // per layer (col, cia at T_atm)
+  double cia_slope, cia_nu_c;
+  unsigned char* keep;       // [n] by caller index
+  unsigned long long* n_kept;
+};
+
 // Response (rotation + IP) on the model grid.
 struct RespDev {
   int64_t dlo, nrot;     // rotation taps for d = dlo .. dlo + nrot - 1, d = i - j
@@ -126,6 +140,7 @@ hipError_t launch_line_records(const LinesDev& L, const double* T_lay, const dou
                                hipStream_t st);
 hipError_t launch_voigt(const VoigtArgs& A, bool fp64, bool tangent, hipStream_t st);
 hipError_t launch_modit(const ModitArgs& M, bool fp64, hipStream_t st);
+hipError_t launch_select_lines(const SelectArgs& A, hipStream_t st);
 hipError_t launch_hjert_f32(int64_t n, const float* x, const float* a, float* H, float* L,
                             hipStream_t st);
 hipError_t launch_hjert_f64(int64_t n, const double* x, const double* a, double* H, hipStream_t st);

@@ -200,7 +200,7 @@ extern "C" int exo_destroy(exo_ctx* c) {
 }
 
 void Species::release() {
-  for (DevBuf* b : {&nu_c, &S0, &E_low, &alpha_ref, &n_texp, &gamma_nat, &qr}) b->release();
+  for (DevBuf* b : {&nu_c, &S0, &E_low, &alpha_ref, &n_texp, &gamma_nat, &qr, &perm}) b->release();
   h_nu_c.clear();
   h_nu_c.shrink_to_fit();
   set = false;
@@ -270,6 +270,11 @@ extern "C" int exo_set_lines(exo_ctx* c, int s, int64_t n, const double* nu_c, c
     sp.release();
     return rc;
   }
+  if ((rc = sp.perm.reserve(n * sizeof(int64_t)))) {
+    sp.release();
+    return rc;
+  }
+  HIP_TRY(hipMemcpy(sp.perm.p, idx.data(), n * sizeof(int64_t), hipMemcpyHostToDevice));
   if ((rc = sp.qr.reserve(n_qr * sizeof(double)))) {
     sp.release();
     return rc;
@@ -517,6 +522,96 @@ int exo::species_opacity(exo_ctx* c, Workspace& ws, const Species& sp, const dou
     if ((rc = voigt_launch_profiled(c, A, fp64, tangent, st))) return rc;
   }
   return EXO_OK;
+}
+
+extern "C" int exo_select_lines(exo_ctx* c, int s, double log10_mmr, const exo_atmos* a, double T_atm,
+                                const double* T_strength, int n_T, int margin, uint8_t* keep,
+                                int64_t* n_kept, void* stream) {
+  if (!c) return set_err(EXO_EINVAL, "ctx is NULL");
+  if (s < 0 || s >= EXO_MAX_SPECIES) return set_err(EXO_EINVAL, "species slot %d out of range", s);
+  if (!c->sp[s].set) return set_err(EXO_ENOTSET, "species slot %d not set", s);
+  if (!a || !keep) return set_err(EXO_EINVAL, "atmos / keep_dev is NULL");
+  if (a->n_layers < 2 || a->n_layers > kMaxLayers || !a->P_bar)
+    return set_err(EXO_EINVAL, "need 2..%d layers", kMaxLayers);
+  for (int i = 0; i < a->n_layers; ++i) {
+    if (!(a->P_bar[i] > 0) || !std::isfinite(a->P_bar[i])) return set_err(EXO_EINVAL, "P must be > 0");
+    if (i > 0 && !(a->P_bar[i] > a->P_bar[i - 1])) return set_err(EXO_EINVAL, "P must ascend (top -> bottom)");
+  }
+  if (!(a->g_cgs > 0) || !(a->mmw > 0)) return set_err(EXO_EINVAL, "need g > 0 and mmw > 0");
+  if (!std::isfinite(a->cia_alpha0) || a->cia_alpha0 < 0 || !std::isfinite(a->cia_Tpow) ||
+      !std::isfinite(a->cia_slope) || !std::isfinite(a->cia_nu_c) || !(a->vmr_h2 >= 0))
+    return set_err(EXO_EINVAL, "bad CIA parameters");
+  if (!std::isfinite(log10_mmr) || log10_mmr > 0) return set_err(EXO_EINVAL, "log10_mmr must be finite and <= 0");
+  if (!(T_atm > 1.0) || !std::isfinite(T_atm)) return set_err(EXO_EINVAL, "T_atm must exceed 1 K");
+  if (n_T < 0 || n_T > 256 || (n_T > 0 && !T_strength)) return set_err(EXO_EINVAL, "bad temperature list");
+  for (int t = 0; t < n_T; ++t)
+    if (!(T_strength[t] > 1.0) || !std::isfinite(T_strength[t])) return set_err(EXO_EINVAL, "bad temperature list");
+  if (margin < 0 || margin > kMaxLayers) return set_err(EXO_EINVAL, "margin must be in [0, %d]", kMaxLayers);
+  HIP_TRY(hipSetDevice(c->device));
+  std::lock_guard<std::mutex> g(c->mu);
+  hipStream_t st = (hipStream_t)stream;
+  const Species& sp = c->sp[s];
+  const int NL = a->n_layers;
+  return with_ws(c->ws, st, [&]() -> int {
+    Workspace& ws = c->ws;
+    int rc;
+    // parameter block: P, the isothermal T, the strength temperatures
+    std::vector<double> blk(a->P_bar, a->P_bar + NL);
+    blk.insert(blk.end(), NL, T_atm);
+    if (n_T > 0) blk.insert(blk.end(), T_strength, T_strength + n_T);
+    else blk.push_back(T_atm);
+    if ((rc = ws.reserve(ws.params, blk.size() * sizeof(double)))) return rc;
+    if ((rc = ws.stage_params(blk.data(), blk.size(), (double*)ws.params.p, st))) return rc;
+    if ((rc = ws.reserve(ws.layer, (size_t)6 * NL * sizeof(double)))) return rc;
+    if ((rc = ws.reserve(ws.col, (size_t)NL * sizeof(double)))) return rc;
+    if ((rc = ws.reserve(ws.gout, 256))) return rc;
+    double* lay = (double*)ws.layer.p;
+    AtmosDev A{};
+    A.nlay = NL;
+    A.nspec = 1;
+    A.P = (const double*)ws.params.p;
+    A.T_in = (const double*)ws.params.p + NL;
+    A.g = a->g_cgs;
+    A.mmw = a->mmw;
+    A.cia_alpha0 = a->cia_alpha0;
+    A.cia_Tpow = a->cia_Tpow;
+    A.cia_slope = a->cia_slope;
+    A.cia_nu_c = a->cia_nu_c;
+    A.vmr_h2 = a->vmr_h2;
+    A.logx[0] = log10_mmr;
+    A.mass[0] = sp.mass;
+    A.T = lay;
+    A.dP = lay + NL;
+    A.lnP = lay + 2 * NL;
+    A.cia = lay + 3 * NL;
+    A.dcia = lay + 4 * NL;
+    A.col = (double*)ws.col.p;
+    HIP_TRY(launch_atmos(A, st));
+    SelectArgs S{};
+    S.L = lines_dev(sp);
+    S.perm = (const int64_t*)sp.perm.p;
+    S.T_strength = (const double*)ws.params.p + 2 * NL;
+    S.n_T = n_T > 0 ? n_T : 1;
+    S.T_atm = T_atm;
+    S.nlay = NL;
+    S.margin = margin;
+    S.P = A.P;
+    S.dP = A.dP;
+    S.col = A.col;
+    S.cia = A.cia;
+    S.cia_slope = a->cia_slope;
+    S.cia_nu_c = a->cia_nu_c;
+    S.keep = keep;
+    S.n_kept = (unsigned long long*)ws.gout.p;
+    HIP_TRY(launch_select_lines(S, st));
+    if (n_kept) {
+      unsigned long long h = 0;
+      HIP_TRY(hipMemcpyAsync(&h, ws.gout.p, sizeof(h), hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipStreamSynchronize(st));
+      *n_kept = (int64_t)h;
+    }
+    return EXO_OK;
+  });
 }
 
 extern "C" int exo_cross_section_modit(exo_ctx* c, int s, double T, double P, int precision,
