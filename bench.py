@@ -432,6 +432,18 @@ def main():
     t32 = time_fwd("fp32", max(3, args.steps))
     t64 = time_fwd("fp64", args.fp64_reps)
 
+    # one leapfrog step of the sampler: Gaussian likelihood and its gradient in one pass
+    Fd = ctx.emission_flux(atm, resp, "fp32")
+    dat = (Fd * (1.0 + 0.01 * torch.randn(Fd.numel(), device="cuda", generator=None))).contiguous()
+    sig = (0.01 * Fd).contiguous()
+    ctx.loss_grad(atm, resp, dat, sig)
+    torch.cuda.synchronize()
+    tl0 = time.perf_counter()
+    for _ in range(max(3, args.steps // 2)):
+        ctx.loss_grad(atm, resp, dat, sig)
+    torch.cuda.synchronize()
+    tloss = (time.perf_counter() - tl0) / max(3, args.steps // 2)
+
     # forward-mode derivative along a parameter tangent plus a per-layer
     # temperature tangent (spectrum and J dtheta in one call)
     dth = np.array([5.0, 1e-3, 1e-2, -1e-2, 0.1, 0.1])
@@ -471,6 +483,7 @@ def main():
         "forward_fp64_plain": {"spectra_per_s": 1.0 / t64, "evals_per_s": evals / t64},
         "fp32_over_fp64_spectra": t64 / t32,
         "flux_jvp": {"ms_per_call": tjvp * 1e3, "evals_per_s": evals / tjvp},
+        "leapfrog_loss_grad": {"ms_per_call": tloss * 1e3, "evals_per_s": evals / tloss},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS, "traffic": recorded_traffic(),
                      "kernel": "k_voigt_f32<tangent>", "avg_launch_ms": avg_launch_ms,

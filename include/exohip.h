@@ -211,6 +211,20 @@ int exo_flux_vjp(exo_ctx* ctx, const exo_atmos* atm, const exo_response* resp,
                  int precision, const void* cot_dev, double* grad_host,
                  double* dL_dT_layers, void* flux_dev, void* stream);
 
+/* Gaussian log-likelihood and its gradient in one pass (what a Hamiltonian
+ * sampler needs at every leapfrog step, Sec. 5.2):
+ *   loss = 1/2 sum_j ((data_j - F_j) / sigma_j)^2
+ * with F the spectrum of (atm, resp) as exo_emission_flux computes it.
+ *   data_dev, sigma_dev  device [out_len] float (sigma > 0)
+ *   loss_host            host double, written on return
+ *   grad_host, dL_dT_layers, flux_dev as exo_flux_vjp (the gradient of loss)
+ * One forward pass: the cotangent (F - data)/sigma^2 is formed on the device
+ * from this pass's F.  EXO_FP32_KAHAN only.  Blocks until loss and gradient
+ * are on the host.  Errors as exo_flux_vjp. */
+int exo_loss_grad(exo_ctx* ctx, const exo_atmos* atm, const exo_response* resp, int precision,
+                  const void* data_dev, const void* sigma_dev, double* loss_host, double* grad_host,
+                  double* dL_dT_layers, void* flux_dev, void* stream);
+
 /* Jacobian-vector product of the emission spectrum (forward mode, App. D):
  * dF = J dtheta along the parameter tangent
  *   dtheta_host   host [2 + n_species + 2] doubles

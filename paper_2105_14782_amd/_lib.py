@@ -100,6 +100,8 @@ def load_library(path: str = LIB_PATH):
         "exo_select_lines": ([V, I, D, ctypes.POINTER(ExoAtmos), D, _c_dp, I, I, V,
                               ctypes.POINTER(I64), V], I),
         "exo_flux_jvp": ([V, ctypes.POINTER(ExoAtmos), ctypes.POINTER(ExoResponse), I, _c_dp, _c_dp, V, V, V], I),
+        "exo_loss_grad": ([V, ctypes.POINTER(ExoAtmos), ctypes.POINTER(ExoResponse), I, V, V,
+                           ctypes.POINTER(D), _c_dp, _c_dp, V, V], I),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)

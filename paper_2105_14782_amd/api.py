@@ -219,6 +219,27 @@ class Context:
             ctypes.c_void_p(flux.data_ptr()) if flux is not None else None, _stream(stream)))
         return grad, layers, flux
 
+    def loss_grad(self, atmos: Atmos, response: Optional[Response], data: torch.Tensor, sigma: torch.Tensor,
+                  want_layers: bool = False, want_flux: bool = False, stream=None):
+        """(loss, grad[2 + M + 2], dloss/dT_n or None, F or None) for the Gaussian
+        likelihood loss = 1/2 sum ((data - F)/sigma)^2, in one forward pass."""
+        n = self._out_len(atmos, response)
+        for t in (data, sigma):
+            assert t.dtype == torch.float32 and t.is_contiguous() and t.numel() == n
+        m = len(atmos.species)
+        grad = np.zeros(4 + m)
+        layers = np.zeros(len(atmos.P_bar)) if want_layers else None
+        flux = torch.empty(n, dtype=torch.float32, device=data.device) if want_flux else None
+        loss = ctypes.c_double()
+        a, keep = atmos.to_c()
+        r = response.to_c() if response is not None else None
+        L.check(self._lib.exo_loss_grad(
+            self._h, ctypes.byref(a), ctypes.byref(r) if r is not None else None, L.EXO_FP32_KAHAN,
+            ctypes.c_void_p(data.data_ptr()), ctypes.c_void_p(sigma.data_ptr()), ctypes.byref(loss),
+            L.dptr(grad), L.dptr(layers), ctypes.c_void_p(flux.data_ptr()) if flux is not None else None,
+            _stream(stream)))
+        return loss.value, grad, layers, flux
+
     def flux_jvp(self, atmos: Atmos, response: Optional[Response], dtheta, dT_layers=None,
                  want_flux: bool = True, stream=None):
         """(F or None, J dtheta) on the device: the spectrum and its directional

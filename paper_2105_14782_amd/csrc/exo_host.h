@@ -32,7 +32,7 @@ struct DevBuf {
 struct Workspace {
   static constexpr size_t kStageDoubles = 1 << 14;
   DevBuf rec, rect, core, rec64, tau, taut, part, part_t, F0, F0bar, mid, midbar, Fup, taubar, layer,
-      col, taps, partT, partX, partR, gout, params, mlines, mpart, mrows0, mrows1;
+      col, taps, partT, partX, partR, gout, params, mlines, mpart, mrows0, mrows1, lossF, lossC, lossP;
   double* h_stage = nullptr;     // pinned staging for per-call parameters
   hipEvent_t stage_ev = nullptr; // guards h_stage reuse
   RtArgs last_rt{};
@@ -45,7 +45,7 @@ struct Workspace {
   std::vector<DevBuf*> bufs() {
     return {&rec, &rect, &core, &rec64, &tau, &taut, &part, &part_t, &F0, &F0bar, &mid, &midbar,
             &Fup, &taubar, &layer, &col, &taps, &partT, &partX, &partR, &gout, &params,
-            &mlines, &mpart, &mrows0, &mrows1};
+            &mlines, &mpart, &mrows0, &mrows1, &lossF, &lossC, &lossP};
   }
   hipEvent_t done_ev = nullptr;  // end of the last evaluation using this workspace
   hipStream_t last_st = nullptr;
@@ -124,6 +124,10 @@ int forward_core(exo_ctx* c, Workspace& ws, const exo_atmos* a, int64_t gb, int6
 int apply_response(Workspace& ws, RespDev& R, const double* F0, void* out, bool out64, hipStream_t st);
 int emission_impl(exo_ctx* c, Workspace& ws, const exo_atmos* a, const exo_response* r,
                   int precision, void* flux, hipStream_t st);
+// With data != nullptr the cotangent is that of the Gaussian likelihood
+// 1/2 sum ((data - F)/sigma)^2, formed on the device from this pass's F;
+// its value goes to *loss.
 int vjp_impl(exo_ctx* c, Workspace& ws, const exo_atmos* a, const exo_response* r, int precision,
-             const void* cot, double* grad, double* dLdT, void* flux, hipStream_t st);
+             const void* cot, double* grad, double* dLdT, void* flux, hipStream_t st,
+             const float* data = nullptr, const float* sigma = nullptr, double* loss = nullptr);
 }  // namespace exo

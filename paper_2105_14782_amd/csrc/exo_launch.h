@@ -160,6 +160,9 @@ hipError_t launch_response_vjp(const RespDev& R, const double* F0, const void* c
                                double* midbar, double* F0bar, int64_t ng, double* partR,
                                int64_t nblocks_mid, hipStream_t st);
 hipError_t launch_cast_copy(const double* src, void* dst, bool dst64, int64_t n, hipStream_t st);
+// cot = (F - d)/s^2 and ceil(n/256) block partials of 1/2 sum ((d - F)/s)^2
+hipError_t launch_gauss_cot(const float* F, const float* d, const float* sg, int64_t n, float* cot,
+                            double* part, hipStream_t st);
 hipError_t launch_to_double(const void* src, bool src64, double* dst, int64_t n, hipStream_t st);
 hipError_t launch_grad_final(const double* partT, int64_t nbT, const double* partX, int64_t nbX,
                              const double* partR, int64_t nbR, const double* T, const double* lnP,

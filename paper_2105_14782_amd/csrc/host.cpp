@@ -926,13 +926,15 @@ extern "C" int exo_emission_flux(exo_ctx* c, const exo_atmos* a, const exo_respo
 
 int exo::vjp_impl(exo_ctx* c, Workspace& ws, const exo_atmos* a, const exo_response* r,
                   int precision, const void* cot, double* grad, double* dLdT, void* flux,
-                  hipStream_t st) {
+                  hipStream_t st, const float* data, const float* sigma, double* loss) {
   int64_t gb, gl;
   int rc;
   if ((rc = validate_atmos(c, a, &gb, &gl))) return rc;
   if (precision != EXO_FP32_KAHAN)
-    return set_err(EXO_EINVAL, "flux_vjp is provided for EXO_FP32_KAHAN");
-  if (!cot || !grad) return set_err(EXO_EINVAL, "cot_dev / grad_host is NULL");
+    return set_err(EXO_EINVAL, "the gradient is provided for EXO_FP32_KAHAN");
+  const bool fused = data != nullptr;
+  if (fused ? (!sigma || !loss || !grad) : (!cot || !grad))
+    return set_err(EXO_EINVAL, fused ? "sigma_dev / loss_host / grad_host is NULL" : "cot_dev / grad_host is NULL");
   RespDev R{};
   if (r && (rc = prepare_response(c, r, gl, &R))) return rc;
   const int NL = a->n_layers, M = a->n_species;
@@ -941,9 +943,22 @@ int exo::vjp_impl(exo_ctx* c, Workspace& ws, const exo_atmos* a, const exo_respo
   const int64_t nbg = (gl + 255) / 256;
   if ((rc = ws.reserve(ws.F0bar, (size_t)gl * sizeof(double)))) return rc;
   double* F0bar = (double*)ws.F0bar.p;
+  // Gaussian likelihood: the spectrum (into flux_dev or scratch), then its cotangent
+  const int64_t nout = r ? R.ol : gl, nbL = (nout + 255) / 256;
+  float* Fout = (float*)flux;
+  if (fused) {
+    if (!Fout) {
+      if ((rc = ws.reserve(ws.lossF, (size_t)nout * sizeof(float)))) return rc;
+      Fout = (float*)ws.lossF.p;
+    }
+    if ((rc = ws.reserve(ws.lossC, (size_t)nout * sizeof(float)))) return rc;
+    if ((rc = ws.reserve(ws.lossP, (size_t)nbL * sizeof(double)))) return rc;
+    cot = ws.lossC.p;
+  }
   int64_t nbR = 0;
   if (r) {
-    if ((rc = apply_response(ws, R, F0, flux, false, st))) return rc;
+    if ((rc = apply_response(ws, R, F0, Fout, false, st))) return rc;
+    if (fused) HIP_TRY(launch_gauss_cot(Fout, data, sigma, nout, (float*)ws.lossC.p, (double*)ws.lossP.p, st));
     const int64_t nmid = R.ol + 2 * R.K;
     nbR = (nmid + 255) / 256;
     if ((rc = ws.reserve(ws.midbar, (size_t)nmid * sizeof(double)))) return rc;
@@ -951,7 +966,8 @@ int exo::vjp_impl(exo_ctx* c, Workspace& ws, const exo_atmos* a, const exo_respo
     HIP_TRY(launch_response_vjp(R, F0, cot, false, (double*)ws.midbar.p, F0bar, gl,
                                 (double*)ws.partR.p, nbR, st));
   } else {
-    if (flux) HIP_TRY(launch_cast_copy(F0, flux, false, gl, st));
+    if (Fout) HIP_TRY(launch_cast_copy(F0, Fout, false, gl, st));
+    if (fused) HIP_TRY(launch_gauss_cot(Fout, data, sigma, nout, (float*)ws.lossC.p, (double*)ws.lossP.p, st));
     HIP_TRY(launch_to_double(cot, false, F0bar, gl, st));
   }
   if ((rc = ws.reserve(ws.Fup, (size_t)NL * gl * sizeof(double)))) return rc;
@@ -970,9 +986,15 @@ int exo::vjp_impl(exo_ctx* c, Workspace& ws, const exo_atmos* a, const exo_respo
   HIP_TRY(launch_grad_final(Rt.partT, nbg, (const double*)ws.partX.p, nbg, (const double*)ws.partR.p,
                             nbR, lay, lay + 2 * NL, NL, M, a->T0_K, a->T_layers ? 0 : 1,
                             (double*)ws.gout.p, st));
-  std::vector<double> h(4 + M + NL);
+  std::vector<double> h(4 + M + NL), hl(fused ? nbL : 0);
   HIP_TRY(hipMemcpyAsync(h.data(), ws.gout.p, h.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+  if (fused) HIP_TRY(hipMemcpyAsync(hl.data(), ws.lossP.p, hl.size() * sizeof(double), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
+  if (fused) {
+    double sum = 0.0;
+    for (double v : hl) sum += v;   // fixed order
+    *loss = sum;
+  }
   for (int k = 0; k < 2 + M + 2; ++k) grad[k] = h[k];
   if (dLdT)
     for (int n = 0; n < NL; ++n) dLdT[n] = h[4 + M + n];
@@ -1046,6 +1068,20 @@ extern "C" int exo_flux_jvp(exo_ctx* c, const exo_atmos* a, const exo_response* 
   std::lock_guard<std::mutex> g(c->mu);
   hipStream_t st = (hipStream_t)stream;
   return with_ws(c->ws, st, [&] { return jvp_impl(c, c->ws, a, r, precision, dth, dTl, flux, dflux, st); });
+}
+
+extern "C" int exo_loss_grad(exo_ctx* c, const exo_atmos* a, const exo_response* r, int precision,
+                             const void* data, const void* sigma, double* loss, double* grad, double* dLdT,
+                             void* flux, void* stream) {
+  if (!c) return set_err(EXO_EINVAL, "ctx is NULL");
+  if (!data) return set_err(EXO_EINVAL, "data_dev is NULL");
+  HIP_TRY(hipSetDevice(c->device));
+  std::lock_guard<std::mutex> g(c->mu);
+  hipStream_t st = (hipStream_t)stream;
+  return with_ws(c->ws, st, [&] {
+    return vjp_impl(c, c->ws, a, r, precision, nullptr, grad, dLdT, flux, st, (const float*)data,
+                    (const float*)sigma, loss);
+  });
 }
 
 extern "C" int exo_broaden(exo_ctx* c, int64_t gb, int64_t gl, const exo_response* r,

@@ -383,6 +383,23 @@ __global__ __launch_bounds__(256) void k_rot_param_grad(RespDev R, const double*
   }
 }
 
+// Gaussian likelihood on the output spectrum: cot_j = dL/dF_j = (F_j - d_j)/s_j^2
+// and block partials of L = 1/2 sum_j ((d_j - F_j)/s_j)^2 (fixed order).
+__global__ __launch_bounds__(256) void k_gauss_cot(const float* __restrict__ F, const float* __restrict__ d,
+                                                   const float* __restrict__ sg, int64_t n,
+                                                   float* __restrict__ cot, double* __restrict__ part) {
+  __shared__ double sm[4];
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  double l = 0.0;
+  if (j < n) {
+    const double r = ((double)F[j] - (double)d[j]) / (double)sg[j];
+    cot[j] = (float)(r / (double)sg[j]);
+    l = 0.5 * r * r;
+  }
+  const double t = block_sum256(l, sm);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
 template <typename TO>
 __global__ __launch_bounds__(256) void k_cast(const double* __restrict__ s, TO* __restrict__ d, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -485,6 +502,12 @@ hipError_t launch_response_vjp(const RespDev& R, const double* F0, const void* c
   else hipLaunchKernelGGL(k_convT_ip<float>, dim3(nb(nmid)), dim3(256), 0, st, R, (const float*)cot, midbar, nmid);
   hipLaunchKernelGGL(k_convT_rot, dim3(nb(ng)), dim3(256), 0, st, R, midbar, nmid, F0bar, ng);
   hipLaunchKernelGGL(k_rot_param_grad, dim3((unsigned)nblocks_mid), dim3(256), 0, st, R, F0, midbar, nmid, partR);
+  return hipGetLastError();
+}
+
+hipError_t launch_gauss_cot(const float* F, const float* d, const float* sg, int64_t n, float* cot,
+                            double* part, hipStream_t st) {
+  hipLaunchKernelGGL(k_gauss_cot, dim3(nb(n)), dim3(256), 0, st, F, d, sg, n, cot, part);
   return hipGetLastError();
 }
 

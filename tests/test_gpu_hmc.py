@@ -1,0 +1,90 @@
+"""The Gaussian likelihood gradient in one pass (exo_loss_grad) against the
+oracle, and posterior recovery by the NUTS driver on synthetic data (the
+paper's Sec. 5.2 setting at the small configuration-4 size).
+
+Tolerances: loss 1e-4 relative (the residuals are 1 % noise, so F's own FP32
+and hjert errors of ~1e-7 move the loss by ~1e-5); gradient 1e-3 as in the
+VJP parity tests.  Recovery: every posterior mean within 5 posterior standard
+deviations of the true parameters.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def exo():
+    import paper_2105_14782_amd as pkg
+    pkg.load_library()
+    from paper_2105_14782_amd import api
+    return api
+
+
+@pytest.fixture(scope="module")
+def case():
+    wl = synth.make_config(4, "small")
+    F_star = O.emission_flux(wl, wl.theta_star)
+    rng = np.random.default_rng(404)
+    data = F_star * (1 + 0.01 * rng.normal(size=F_star.size))
+    return wl, data, 0.01 * F_star
+
+
+def _ctx(exo, wl):
+    c = exo.Context(0)
+    for s, ll in enumerate(wl.lines):
+        c.set_lines(s, ll)
+    c.set_grid(wl.nu)
+    return c
+
+
+def test_loss_grad_against_oracle(exo, case):
+    wl, data, sigma = case
+    th = wl.theta
+    c = _ctx(exo, wl)
+    atm = exo.Atmos.from_workload(wl.atmos, [0, 1], th)
+    resp = exo.Response.from_workload(wl.response, th)
+    d = torch.tensor(data, dtype=torch.float32, device="cuda")
+    s = torch.tensor(sigma, dtype=torch.float32, device="cuda")
+    loss, g, gl, F = c.loss_grad(atm, resp, d, s, want_layers=True, want_flux=True)
+    assert torch.equal(F.cpu(), c.emission_flux(atm, resp, "fp32").cpu())
+    L_ref, g_ref, gl_ref = O.loss_gradient(wl, th, data, sigma, per_layer=True)
+    _say(f"  loss {loss:.8e} oracle {L_ref:.8e}")
+    assert abs(loss - L_ref) <= 1e-4 * L_ref
+    scale = np.maximum(np.abs(g_ref), 1e-6 * np.abs(g_ref).max())
+    assert np.all(np.abs(g - g_ref) / scale < 1e-3), (g, g_ref)
+    errl = np.abs(gl - gl_ref) / np.maximum(np.abs(gl_ref), 1e-6 * np.abs(gl_ref).max())
+    assert errl.max() < 5e-3
+    # the same gradient as flux_vjp with the cotangent formed from the same F
+    cot = ((F.double() - d.double()) / s.double() ** 2).float().contiguous()
+    g2, _, _ = c.flux_vjp(atm, resp, cot)
+    np.testing.assert_allclose(g, g2, rtol=1e-6, atol=1e-9 * np.abs(g2).max())
+
+
+def test_nuts_recovers_parameters(exo, case):
+    from paper_2105_14782_amd import hmc
+    _say("NUTS posterior recovery, config-4 small")
+    wl, data, sigma = case
+    c = _ctx(exo, wl)
+    atm = exo.Atmos.from_workload(wl.atmos, [0, 1])
+    resp = exo.Response.from_workload(wl.response)
+    lo = np.array([1000.0, 0.05, -4.0, -4.0, 20.0, 10.0])
+    hi = np.array([1600.0, 0.15, -1.0, -1.0, 35.0, 25.0])
+    post = hmc.SpectrumPosterior(c, atm, resp, data, sigma, lo, hi)
+    res = hmc.nuts(post, post.z_of(wl.theta), 80, 80, np.random.default_rng(12), max_depth=6)
+    m, sd = res.samples.mean(axis=0), res.samples.std(axis=0)
+    _say(f"  mean {m}\n  sd   {sd}\n  true {wl.theta_star}\n  step {res.step_size:.3g}, accept "
+         f"{res.accept.mean():.2f}, evaluations {res.n_eval}, divergences {res.divergences}")
+    assert np.all(np.abs(m - wl.theta_star) < 5 * sd + 1e-12), (m, sd)
+    assert res.accept.mean() > 0.5
