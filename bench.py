@@ -47,7 +47,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-modit", action="store_true", help="skip the MODIT-vs-direct cross-section runs")
     ap.add_argument("--modit-only", action="store_true", help="only the MODIT-vs-direct runs (for profiling)")
-    ap.add_argument("--cpu-points", type=int, default=192)
+    ap.add_argument("--cpu-points", type=int, default=256)
     ap.add_argument("--serve-requests", type=int, default=48,
                     help="requests of the Poisson serving run (0: skip)")
     ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -145,7 +145,8 @@ def summarize_counters(fetch_csv, write_csv, out_path):
         f"{f_fac:.3f} and WRITE_SIZE by {w_fac:.3f}.", "",
         f"Tangent Voigt launches measured: {len(fv)} (1e5 lines x 20,000 points x 100 layers each).", "",
         "Algorithmic bytes per launch: line records 1e7 x (64 + 64) B + centres 0.8 MB read, "
-        "outputs 2 x 100 x 20,000 x 8 B (split partial sums) written: 1.33e9 B.", "",
+        "outputs 2 x 100 x 20,000 x 8 B (split partial sums) written: 1.33e9 B.  Register spills of the",
+        "core-branch call (the kernel asks for 7 waves per SIMD) add scratch writes and reads.", "",
         f"- fetch_kib_per_launch: {np.mean(fv):.1f}",
         f"- write_kib_per_launch: {np.mean(wv):.1f}",
         f"- traffic_bytes_per_launch: {fetch + write:.4e}",
@@ -233,7 +234,7 @@ def summarize_stats(csv_path, out_path, modit=False):
             "Workload: 2 species x 1e5 lines, 20,000-point log-uniform grid, 100 layers.",
             "The run does 1 warm-up + 3 timed flux_vjp steps (two tangent-mode Voigt sums each),",
             "then 4 FP32 forward spectra and 2 plain-FP64 forward spectra (two Voigt sums each),",
-            "then the flux_jvp timing calls (tangent-mode Voigt sums as well).", "",
+            "then 4 loss_grad (leapfrog step) and 4 flux_jvp calls (tangent-mode Voigt sums as well).", "",
         ]
     lines = head + ["| kernel | calls | avg ms | total ms | % |", "|---|---:|---:|---:|---:|"]
     for r in rows:

@@ -293,7 +293,7 @@ __device__ __forceinline__ void near_lines(int sb, int se, const LineRec* __rest
 // One (tile, layer, split): far prefix, near lines, far suffix, each summed
 // in blocks of kChunk lines into the compensated accumulator.
 template <bool TAN, int G>
-__global__ __launch_bounds__(256) void k_voigt_f32(VoigtArgs A) {
+__device__ __forceinline__ void voigt_body(const VoigtArgs& A) {
   const int y = blockIdx.y;
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -338,6 +338,22 @@ __global__ __launch_bounds__(256) void k_voigt_f32(VoigtArgs A) {
       if (TAN) A.part_t[p] = make_float2(ts[g], tc[g]);
     }
   }
+}
+
+// The kernels.  The tangent-mode loop needs 96 registers per lane, which
+// allows 5 waves per SIMD; asking for 7 keeps both line loops free of spills
+// (the spills land in the rarely taken core branch) and measured 9 % faster.
+// The forward kernel fits 8 waves without the hint.
+template <bool TAN, int G>
+__global__ void k_voigt_f32(VoigtArgs A);
+template <>
+__global__ __launch_bounds__(256) void k_voigt_f32<false, kVoigtG>(VoigtArgs A) {
+  voigt_body<false, kVoigtG>(A);
+}
+template <>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 8))) void k_voigt_f32<true, kVoigtG>(
+    VoigtArgs A) {
+  voigt_body<true, kVoigtG>(A);
 }
 
 // Fixed-order combine of split-K partials.
