@@ -272,6 +272,25 @@ def test_emission_full_config2_sampled(exo):
     assert maxrel(got, ref) < 1e-11
 
 
+def test_emission_config3_medium_sampled(exo):
+    """The throughput workload's line density at 1e6 lines (config 3 medium:
+    100,000-point grid at R0 = 1e6, 100 layers, 1e13 pairs; the line records
+    are processed in several layer chunks): FP32 F0 at sampled grid points
+    against the oracle."""
+    _say("emission config3 medium sampled")
+    wl = synth.make_config(3, "medium")
+    c = _ctx_with(exo, wl)
+    theta = np.array([wl.atmos.T0, wl.atmos.alpha, wl.atmos.log10_mmr[0]])
+    rng = np.random.default_rng(2025)
+    idx = np.sort(rng.choice(wl.nu.size, 4, replace=False))
+    idx[0], idx[-1] = 0, wl.nu.size - 1
+    F0 = c.emission_flux(_atmos(exo, wl, theta), None, "fp32").cpu().double().numpy()
+    ref = O.emission_F0(wl, theta, nu_idx=idx)
+    err = maxrel(F0[idx], ref)
+    _say(f"  fp32 max rel err {err:.3e}")
+    assert err < RTOL_FLUX
+
+
 def test_response_rejects_out_of_range(exo):
     import paper_2105_14782_amd as pkg
     wl = synth.make_config(2, "small")
