@@ -466,9 +466,18 @@ def optical_depths(wl, theta, nu_idx=None, want_dT=False) -> Columns:
     NL = P.size
     tau = np.zeros((nm, NL, nu.size))
     dtau = np.zeros((nm, NL, nu.size)) if want_dT else None
+    modit = getattr(atm, "opacity", "lpf") == "modit"
+    if modit and (want_dT or nu_idx is not None):
+        raise ValueError("the MODIT opacity is evaluated on the whole grid, without tangents")
     for m, ll in enumerate(wl.lines):
         col = column_factor(dP, 10.0 ** logx[m], ll.mass_amu, atm.g_cgs)
         for n in range(NL):
+            if modit:
+                from .modit import modit_cross_section
+                # the truncated transform rings slightly below zero next to
+                # narrow lines; an optical depth is not negative
+                tau[m, n] = col[n] * np.maximum(modit_cross_section(ll, T[n], P[n], nu, atm.modit_dln_gamma), 0.0)
+                continue
             r = cross_section(ll, T[n], P[n], nu, want_dT=want_dT)
             if want_dT:
                 tau[m, n] = col[n] * r[0]

@@ -60,6 +60,8 @@ class Atmosphere:
     vmr_h2: float = 0.75 * 2.33 / 2.016
     bottom: int = 0             # 0: F_B = pi B(T_bottom) ; 1: F_B = 0
     T_layers: Optional[np.ndarray] = None   # layer-by-layer T [K]; replaces the power law
+    opacity: str = "lpf"        # line opacity: "lpf" (direct sum) or "modit" (Sec. 2.1.2)
+    modit_dln_gamma: float = 0.1
 
 
 @dataclass

@@ -100,3 +100,49 @@ def test_modit_matches_direct_sum(R0, T, P, bound):
     keep = ref > 1e-2 * ref.max()
     err = np.max(np.abs(sig[keep] - ref[keep]) / ref[keep])
     assert err < bound, err
+
+
+def _emission_case(R0, n_nu, seed=7):
+    """A single-species atmosphere (config-3 small layers) whose lines sit
+    inside the window, with low lower-state energies so that the 100 bar
+    column is not opaque at every wavenumber (median line depth ~0.5)."""
+    from dataclasses import replace
+    wl = synth.make_config(3, "small")
+    nu = 4340.0 * np.exp(np.arange(n_nu) / R0)
+    rng = np.random.default_rng(seed)
+    n = 300
+    ll = replace(wl.lines[0], nu_c=np.sort(rng.uniform(nu[200], nu[-200], n)),
+                 S0=10 ** np.clip(rng.normal(-23.0, 1.67, n), -28, -18), E_low=rng.exponential(300.0, n),
+                 alpha_ref=rng.uniform(0.01, 0.1, n), n_texp=rng.uniform(0.5, 0.8, n))
+    wl = replace(wl, nu=nu, lines=[ll])
+    return wl, np.array([1300.0, 0.10, -3.0])
+
+
+def test_modit_emission_converges_to_direct():
+    """The emission spectrum with MODIT opacities (the paper's use of MODIT in
+    place of the direct LPF) approaches the direct-sum spectrum as the grid
+    resolves the coldest layer's Doppler width: beta~ = 1.0 grid step at
+    R0 = 1e6 (206 K top layer), 3.1 at R0 = 3e6, where the linear line-shape
+    density's smearing of a profile core falls to ~1 %."""
+    from dataclasses import replace
+    errs = []
+    for R0, n_nu in ((1e6, 2500), (3e6, 6000)):
+        wl, th = _emission_case(R0, n_nu)
+        F_lpf = O.emission_F0(wl, th)
+        F_modit = O.emission_F0(replace(wl, atmos=replace(wl.atmos, opacity="modit")), th)
+        rel = np.abs(F_modit - F_lpf) / F_lpf
+        errs.append((rel.max(), np.median(rel)))
+    (m1, med1), (m3, med3) = errs
+    assert m3 < 2e-2 and med3 < 2e-3, errs
+    assert m1 > 2 * m3, errs                     # coarser grid, larger error
+    assert m3 > 1e-6                             # the two paths really differ
+
+
+def test_modit_emission_rejects_tangents():
+    from dataclasses import replace
+    wl, th = _emission_case(1e6, 600)
+    wl = replace(wl, atmos=replace(wl.atmos, opacity="modit"))
+    with pytest.raises(ValueError):
+        O.optical_depths(wl, th, want_dT=True)
+    with pytest.raises(ValueError):
+        O.optical_depths(wl, th, nu_idx=[0, 1])
