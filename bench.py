@@ -47,6 +47,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-modit", action="store_true", help="skip the MODIT-vs-direct cross-section runs")
     ap.add_argument("--modit-only", action="store_true", help="only the MODIT-vs-direct runs (for profiling)")
+    ap.add_argument("--modit-emission-only", action="store_true",
+                    help="only the config-3 emission with MODIT opacities (for profiling)")
     ap.add_argument("--cpu-points", type=int, default=256)
     ap.add_argument("--serve-requests", type=int, default=48,
                     help="requests of the Poisson serving run (0: skip)")
@@ -58,6 +60,8 @@ def parse():
                     help="write the kernel-time summary from a rocprofv3 --stats run and exit")
     ap.add_argument("--summarize-modit-stats", metavar="STATS_CSV",
                     help="write the MODIT kernel-time summary from a rocprofv3 --stats run of --modit-only")
+    ap.add_argument("--summarize-modit-emission-stats", metavar="STATS_CSV",
+                    help="write the kernel-time summary from a rocprofv3 --stats run of --modit-emission-only")
     ap.add_argument("--counters", action="store_true",
                     help="one step plus a 512 MiB device copy (calibration), for rocprofv3 --pmc runs")
     return ap.parse_args()
@@ -162,6 +166,7 @@ def summarize_counters(fetch_csv, write_csv, out_path):
 
 VALU_PROFILE = "profiles/voigt_tangent_config2_valu.md"
 STATS_PROFILE = "profiles/voigt_config2_kernel_stats.md"
+MODIT_EMISSION_PROFILE = "profiles/modit_emission_config3_kernel_stats.md"
 MODIT_PROFILE = "profiles/modit_config3_kernel_stats.md"
 VALU_COUNTERS = "SQ_INSTS_VALU SQ_INSTS_VALU_TRANS_F32 SQ_ACTIVE_INST_VALU SQ_BUSY_CYCLES GRBM_GUI_ACTIVE"
 
@@ -212,7 +217,20 @@ def summarize_stats(csv_path, out_path, modit=False):
     """Markdown table of a rocprofv3 --kernel-trace --stats run of the bench."""
     import csv
     rows = list(csv.DictReader(open(csv_path)))
-    if modit:
+    if modit == "emission":
+        head = [
+            "# Kernel trace summary: config-3 emission with MODIT opacities (rocprofv3 --kernel-trace --stats)", "",
+            "Command (repository root, one MI355X):", "", "```",
+            "rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/prof_modit_em -o modit_em -- \\",
+            "    python3 bench.py --modit-emission-only",
+            "python3 bench.py --summarize-modit-emission-stats gpurun_out/prof_modit_em/modit_em_kernel_stats.csv",
+            "```", "",
+            "Workload: the config-3 line list (1e7 lines) on its 100,000-point grid at R0 = 1e6, 100 layers",
+            "(1e-8 .. 100 bar, T0 = 1300 K, alpha = 0.1), one species, no response: 6 spectra in FP32 and 6 in",
+            "FP64 (1 warm-up + 5 timed each).  The layers go 14 (FP32) or 10 (FP64) to a launch; each launch",
+            "has 9 radix-4 Stockham passes over 32 width rows per layer forward and 9 over one row inverse.", "",
+        ]
+    elif modit:
         head = [
             "# Kernel trace summary: MODIT vs direct cross-section, config-3 grid (rocprofv3 --kernel-trace --stats)", "",
             "Command (repository root, one MI355X):", "", "```",
@@ -292,7 +310,35 @@ def modit_bench(reps=5):
         run["select_kept"] = ctx.select_lines(0, math.log10(0.0023), atm, 1700.0, T_scan, 2)[1]
         out["runs"].append(run)
     ctx.close()
+    out["emission"] = modit_emission_bench(reps)
+    out["emission"]["direct_single_layer_fp32_ms"] = out["runs"][-1]["direct_fp32_ms"]
     return out
+
+
+def modit_emission_bench(reps=5):
+    """The whole config-3 emission spectrum (all 1e7 lines, 100 layers, no
+    response) with MODIT opacities, FP32 and FP64; the direct sum would take
+    100 single-layer sums of all lines."""
+    import torch
+    import synth
+    from dataclasses import replace
+    from paper_2105_14782_amd import api
+    wl = synth.make_config(3, "full")
+    ctx = api.Context(0)
+    ctx.set_lines(0, wl.lines[0])
+    ctx.set_grid(wl.nu)
+    atm = replace(api.Atmos.from_workload(wl.atmos, [0]), opacity="modit")
+    em = {"workload": "config-3 emission, 1e7 lines, 100 layers, 100,000-point grid, MODIT opacities"}
+    for prec in ("fp32", "fp64"):
+        ctx.emission_flux(atm, None, prec)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            ctx.emission_flux(atm, None, prec)
+        torch.cuda.synchronize()
+        em[f"modit_{prec}_ms"] = 1e3 * (time.perf_counter() - t) / reps
+    ctx.close()
+    return em
 
 
 SERVE_MARGIN = 260   # output margin (points) at R0 = 1e6: rotation + RV + 6-sigma IP reach < 200
@@ -360,12 +406,19 @@ def main():
     if args.summarize_modit_stats:
         summarize_stats(args.summarize_modit_stats, os.path.join(ROOT, MODIT_PROFILE), modit=True)
         return
+    if args.summarize_modit_emission_stats:
+        summarize_stats(args.summarize_modit_emission_stats, os.path.join(ROOT, MODIT_EMISSION_PROFILE),
+                        modit="emission")
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
                           "n_gpus": args.gpus}))
         sys.exit(2)
     if args.modit_only:
         print(json.dumps({"modit": modit_bench()}), flush=True)
+        return
+    if args.modit_emission_only:
+        print(json.dumps({"modit_emission": modit_emission_bench()}), flush=True)
         return
     import torch
     import synth

@@ -75,6 +75,16 @@ typedef enum {
   EXO_FB_ZERO = 1           /* F_B = 0                                      */
 } exo_bottom;
 
+/* Line optical depths of the emission model (exo_atmos.opacity). */
+typedef enum {
+  EXO_OPACITY_LPF = 0,      /* direct sum of the line profiles (Sec. 2.1.1)  */
+  EXO_OPACITY_MODIT = 1     /* MODIT (Sec. 2.1.2) on the model grid, which must be
+                               log-uniform: only the lines inside the model grid
+                               contribute; the cross-section is clamped at zero
+                               before it becomes an optical depth.  Forward only:
+                               the derivative entry points reject it. */
+} exo_opacity;
+
 #define EXO_MAX_SPECIES 64
 
 /* Message describing the calling thread's most recent failure ("" if none).
@@ -168,6 +178,8 @@ typedef struct {
   const double* T_layers;    /* host [n_layers] K (each > 1, finite) or NULL: the
                                 layer-by-layer temperature model of Sec. 6.1; when
                                 given, T0_K and alpha are not used */
+  int32_t opacity;           /* exo_opacity: how the line optical depths are formed */
+  double modit_dln_gamma;    /* EXO_OPACITY_MODIT: width-grid step in ln gamma~ (>= 1e-3) */
 } exo_atmos;
 
 /* Response of Sec. 4 on the (log-uniform) model grid: rotation with

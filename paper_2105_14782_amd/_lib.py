@@ -16,6 +16,7 @@ EXO_OK, EXO_EINVAL, EXO_ENOMEM, EXO_ENOTSET, EXO_EDEVICE = 0, -1, -2, -3, -4
 EXO_FP32_KAHAN, EXO_FP64 = 0, 1
 EXO_QR_POWER, EXO_QR_TABLE = 0, 1
 EXO_FB_PLANCK_BOTTOM, EXO_FB_ZERO = 0, 1
+EXO_OPACITY_LPF, EXO_OPACITY_MODIT = 0, 1
 EXO_MAX_SPECIES = 64
 
 _c_dp = ctypes.POINTER(ctypes.c_double)
@@ -42,6 +43,8 @@ class ExoAtmos(ctypes.Structure):
         ("grid_begin", ctypes.c_int64),
         ("grid_len", ctypes.c_int64),
         ("T_layers", _c_dp),
+        ("opacity", ctypes.c_int32),
+        ("modit_dln_gamma", ctypes.c_double),
     ]
 
 

@@ -33,6 +33,9 @@ def _f64(a) -> np.ndarray:
     return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
 
 
+_OPACITY = {"lpf": L.EXO_OPACITY_LPF, "modit": L.EXO_OPACITY_MODIT}
+
+
 @dataclass
 class Atmos:
     """Atmosphere / model-grid description passed to emission_flux and flux_vjp."""
@@ -52,6 +55,8 @@ class Atmos:
     grid_begin: int = 0
     grid_len: int = 0
     T_layers: Optional[np.ndarray] = None   # layer-by-layer T [K]; replaces (T0, alpha)
+    opacity: str = "lpf"        # line optical depths: "lpf" (direct sum) or "modit" (forward only)
+    modit_dln_gamma: float = 0.1
 
     def to_c(self):
         P = _f64(self.P_bar)
@@ -66,7 +71,8 @@ class Atmos:
             cia_slope=float(self.cia_slope), cia_nu_c=float(self.cia_nu_c),
             vmr_h2=float(self.vmr_h2), bottom=int(self.bottom),
             grid_begin=int(self.grid_begin), grid_len=int(self.grid_len),
-            T_layers=L.dptr(Tl) if Tl is not None else None)
+            T_layers=L.dptr(Tl) if Tl is not None else None,
+            opacity=_OPACITY[self.opacity], modit_dln_gamma=float(self.modit_dln_gamma))
         return a, (P, sp, lx, Tl)   # keep the arrays alive for the call
 
     @staticmethod
@@ -77,7 +83,8 @@ class Atmos:
         lx = atm.log10_mmr if theta is None else np.asarray(theta[2:2 + nm], float)
         return Atmos(atm.P_bar, T0, al, list(species), list(lx), atm.g_cgs, atm.mmw,
                      atm.cia_alpha0, atm.cia_Tpow, atm.cia_slope, atm.cia_nu_c, atm.vmr_h2,
-                     atm.bottom, grid_begin, grid_len, getattr(atm, "T_layers", None))
+                     atm.bottom, grid_begin, grid_len, getattr(atm, "T_layers", None),
+                     getattr(atm, "opacity", "lpf"), getattr(atm, "modit_dln_gamma", 0.1))
 
 
 @dataclass

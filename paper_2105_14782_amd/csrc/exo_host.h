@@ -117,6 +117,12 @@ int species_opacity(exo_ctx* c, Workspace& ws, const Species& sp, const double* 
                     const double* d_P, const double* d_col, int nlay, double amp_scale, bool fp64,
                     bool tangent, const double* d_nu, int64_t ng, void* out, float* out_t,
                     hipStream_t st);
+// MODIT cross-sections (d_col == NULL) or optical depths col_n sigma clamped
+// at zero, of nlay layers, from the lines with nu_lo <= nu_c <= nu_hi.
+int modit_opacity(exo_ctx* c, Workspace& ws, const Species& sp, const double* d_T, const double* d_P,
+                  const double* d_col, int nlay, double dlng, bool fp64, const double* d_nu, double nu_lo,
+                  double nu_hi, int64_t ng, void* out, hipStream_t st);
+size_t modit_workspace(const Species& sp, double nu_lo, double nu_hi, int64_t ng, int nlay, bool fp64);
 int validate_atmos(const exo_ctx* c, const exo_atmos* a, int64_t* gb, int64_t* gl);
 int prepare_response(const exo_ctx* c, const exo_response* r, int64_t gl, RespDev* R);
 int forward_core(exo_ctx* c, Workspace& ws, const exo_atmos* a, int64_t gb, int64_t gl, bool fp64,

@@ -88,28 +88,44 @@ struct JvpArgs {
   double* dF0;           // [ng] output
 };
 
-// MODIT (Sec. 2.1.2) of one species at one (T, P).
+// MODIT (Sec. 2.1.2) of one species on a batch of layers (blockIdx.y).
 constexpr int kModitMaxBins = 32;   // width bins of the lineshape density
 struct ModitBins {
   double lng0, d;   // ln gamma~_k = lng0 + k d
   int K;
   int pad;
 };
+// Per-layer constants of the MODIT line pass.
+struct ModitLayer {
+  double T, invT, lnTr, P, inv_qr, lng_floor;   // lnTr = ln(T / T_ref); floor = ln(1e-3 beta~)
+};
 struct ModitArgs {
   LinesDev L;
-  double T, P, R0, beta_t, amp_scale, dlng;
+  const double* T;         // device [nl] layer temperatures
+  const double* P;         // device [nl] layer pressures
+  const double* col;       // device [nl] column factors, or NULL: when given the output is
+                           // col[n] sigma clamped at zero (an optical depth)
+  double mass, R0, amp_scale, dlng;
   const double* nu;        // grid [ng] (log-uniform)
   int64_t ng, n_fft;
   const double* nu_c;      // sorted centres (= L.nu_c)
   int64_t l0, n_in;        // lines inside the grid: [l0, l0 + n_in)
-  double *x, *lng, *S;     // per-line scratch [n_in]
-  double* part;            // [2 n_part] min/max partials
+  int nl;                  // layers of this launch
+  bool want_pos;           // compute f and cell (they depend on the grid only)
+  void* f;                 // [n_in] R: position of the line in its cell, in [0, 1]
+  int64_t* cell;           // [ng + 1]: lines of cell j are [cell[j], cell[j + 1]) (window-relative)
+  ModitLayer* lay;         // [nl]
+  void* rec;               // [nl][n_in] {ln gamma~, S amp_scale} as R pairs
+  double* part;            // [nl][2 n_part] min/max partials of ln gamma~, one per line block
   int64_t n_part;
-  ModitBins* bins;         // device
-  void *rows0, *rows1;     // [kModitMaxBins][n_fft] complex (float2 or double2)
-  void* out;               // [ng] float or double
+  ModitBins* bins;         // device [nl]
+  void *rows0, *rows1;     // [nl][kModitMaxBins][n_fft] complex (float2 or double2)
+  void* out;               // [nl][ng] float or double
   bool out64;
 };
+// Largest batch of layers per MODIT launch (the forward DFT grid has
+// nl * kModitMaxBins rows in blockIdx.y).
+constexpr int kModitMaxLayersPerLaunch = 65535 / kModitMaxBins;
 
 // Weak-line pre-selection (App. G) of one species in an isothermal atmosphere.
 struct SelectArgs {

@@ -614,6 +614,108 @@ extern "C" int exo_select_lines(exo_ctx* c, int s, double log10_mmr, const exo_a
   });
 }
 
+// Per-layer device bytes of a MODIT launch; layers go in batches that fit
+// kModitBudget.
+static constexpr size_t kModitBudget = size_t(4) << 30;
+
+static int64_t modit_fft_len(int64_t ng) {
+  int64_t n = 1;
+  while (n < 2 * ng) n *= 2;
+  return n;
+}
+
+static size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+struct ModitPlan {
+  int nb;                 // layers per launch
+  int64_t n_fft, nbl;     // transform length, line blocks
+  size_t off_cell, off_lay, off_rec, lines_bytes;   // layout of ws.mlines
+  size_t part_bytes, rows_bytes;
+};
+
+static ModitPlan modit_plan(int64_t n_in, int64_t ng, int nlay, bool fp64) {
+  ModitPlan q{};
+  const size_t csz = fp64 ? 2 * sizeof(double) : 2 * sizeof(float);   // complex sample
+  const size_t psz = csz;                                             // {ln gamma~, S} pair
+  const int64_t ni = std::max<int64_t>(n_in, 1);
+  q.n_fft = modit_fft_len(ng);
+  q.nbl = (ni + 255) / 256;
+  const size_t per_layer = 2 * (size_t)kModitMaxBins * q.n_fft * csz + (size_t)ni * psz +
+                           2 * (size_t)q.nbl * sizeof(double) + sizeof(ModitBins) + sizeof(ModitLayer);
+  const size_t nb = std::max<size_t>(1, kModitBudget / per_layer);
+  q.nb = (int)std::min<size_t>({nb, (size_t)nlay, (size_t)kModitMaxLayersPerLaunch});
+  q.off_cell = align256((size_t)ni * sizeof(double));
+  q.off_lay = q.off_cell + align256((size_t)(ng + 1) * sizeof(int64_t));
+  q.off_rec = q.off_lay + align256((size_t)q.nb * sizeof(ModitLayer));
+  q.lines_bytes = q.off_rec + (size_t)q.nb * ni * psz;
+  q.part_bytes = align256((size_t)q.nb * 2 * q.nbl * sizeof(double)) + (size_t)q.nb * sizeof(ModitBins);
+  q.rows_bytes = (size_t)q.nb * kModitMaxBins * q.n_fft * csz;
+  return q;
+}
+
+// lines of sp with nu_lo <= nu_c <= nu_hi: [l0, l0 + n_in) of the sorted list
+static void modit_window(const Species& sp, double nu_lo, double nu_hi, int64_t* l0, int64_t* n_in) {
+  const auto& h = sp.h_nu_c;
+  *l0 = std::lower_bound(h.begin(), h.end(), nu_lo) - h.begin();
+  *n_in = (std::upper_bound(h.begin(), h.end(), nu_hi) - h.begin()) - *l0;
+}
+
+size_t exo::modit_workspace(const Species& sp, double nu_lo, double nu_hi, int64_t ng, int nlay,
+                            bool fp64) {
+  int64_t l0, n_in;
+  modit_window(sp, nu_lo, nu_hi, &l0, &n_in);
+  const ModitPlan q = modit_plan(n_in, ng, nlay, fp64);
+  return align256(q.lines_bytes) + align256(q.part_bytes) + 2 * align256(q.rows_bytes);
+}
+
+// MODIT cross-sections (col == NULL) or optical depths col_n sigma clamped
+// at zero, of nlay layers (device T, P, col [nlay]) on the log-uniform grid
+// d_nu [ng], into out [nlay][ng] (float, or double with fp64).
+int exo::modit_opacity(exo_ctx* c, Workspace& ws, const Species& sp, const double* d_T, const double* d_P,
+                       const double* d_col, int nlay, double dlng, bool fp64, const double* d_nu,
+                       double nu_lo, double nu_hi, int64_t ng, void* out, hipStream_t st) {
+  ModitArgs M{};
+  M.L = lines_dev(sp);
+  M.mass = sp.mass;
+  M.R0 = kCkms / c->dv_kms;   // 1 / mean ln spacing
+  // FP32: the same exact power-of-two scale as the direct cross-section
+  M.amp_scale = fp64 ? 1.0 : 18446744073709551616.0;
+  M.dlng = dlng;
+  M.nu = d_nu;
+  M.ng = ng;
+  M.nu_c = (const double*)sp.nu_c.p;
+  modit_window(sp, nu_lo, nu_hi, &M.l0, &M.n_in);
+  const ModitPlan q = modit_plan(M.n_in, ng, nlay, fp64);
+  M.n_fft = q.n_fft;
+  M.n_part = q.nbl;
+  M.out64 = fp64;
+  const size_t esz = fp64 ? sizeof(double) : sizeof(float);
+  int rc;
+  if ((rc = ws.reserve(ws.mlines, q.lines_bytes))) return rc;
+  if ((rc = ws.reserve(ws.mpart, q.part_bytes))) return rc;
+  if ((rc = ws.reserve(ws.mrows0, q.rows_bytes))) return rc;
+  if ((rc = ws.reserve(ws.mrows1, q.rows_bytes))) return rc;
+  char* base = (char*)ws.mlines.p;
+  M.f = base;
+  M.cell = (int64_t*)(base + q.off_cell);
+  M.lay = (ModitLayer*)(base + q.off_lay);
+  M.rec = base + q.off_rec;
+  M.part = (double*)ws.mpart.p;
+  M.bins = (ModitBins*)((char*)ws.mpart.p + align256((size_t)q.nb * 2 * q.nbl * sizeof(double)));
+  M.rows0 = ws.mrows0.p;
+  M.rows1 = ws.mrows1.p;
+  for (int n0 = 0; n0 < nlay; n0 += q.nb) {
+    M.nl = std::min(q.nb, nlay - n0);
+    M.want_pos = n0 == 0;
+    M.T = d_T + n0;
+    M.P = d_P + n0;
+    M.col = d_col ? d_col + n0 : nullptr;
+    M.out = (char*)out + (size_t)n0 * ng * esz;
+    HIP_TRY(launch_modit(M, fp64, st));
+  }
+  return EXO_OK;
+}
+
 extern "C" int exo_cross_section_modit(exo_ctx* c, int s, double T, double P, int precision,
                                        double dln_gamma, void* sigma, void* stream) {
   if (!c) return set_err(EXO_EINVAL, "ctx is NULL");
@@ -629,46 +731,15 @@ extern "C" int exo_cross_section_modit(exo_ctx* c, int s, double T, double P, in
   HIP_TRY(hipSetDevice(c->device));
   std::lock_guard<std::mutex> g(c->mu);
   hipStream_t st = (hipStream_t)stream;
-  const Species& sp = c->sp[s];
-  const bool fp64 = precision == EXO_FP64;
-  const int64_t ng = c->n_nu;
-  ModitArgs M{};
-  M.L = lines_dev(sp);
-  M.T = T;
-  M.P = P;
-  M.R0 = kCkms / c->dv_kms;   // 1 / mean ln spacing
-  M.beta_t = std::sqrt(kKB * T / (sp.mass * kMU)) * M.R0 / kC;
-  // FP32: the same exact power-of-two scale as the direct cross-section
-  M.amp_scale = fp64 ? 1.0 : 18446744073709551616.0;
-  M.dlng = dln_gamma;
-  M.nu = (const double*)c->d_nu.p;
-  M.ng = ng;
-  M.n_fft = 1;
-  while (M.n_fft < 2 * ng) M.n_fft *= 2;
-  M.nu_c = (const double*)sp.nu_c.p;
-  const auto& h = sp.h_nu_c;
-  M.l0 = std::lower_bound(h.begin(), h.end(), c->h_nu.front()) - h.begin();
-  M.n_in = (std::upper_bound(h.begin(), h.end(), c->h_nu.back()) - h.begin()) - M.l0;
-  M.n_part = 1024;
-  M.out = sigma;
-  M.out64 = fp64;
-  return with_ws(c->ws, st, [&]() -> int {
-    Workspace& ws = c->ws;
+  Workspace& ws = c->ws;
+  return with_ws(ws, st, [&]() -> int {
     int rc;
-    const size_t csz = fp64 ? 2 * sizeof(double) : 2 * sizeof(float);
-    if ((rc = ws.reserve(ws.mlines, (size_t)3 * std::max<int64_t>(M.n_in, 1) * sizeof(double)))) return rc;
-    if ((rc = ws.reserve(ws.mpart, (size_t)2 * M.n_part * sizeof(double) + 256))) return rc;
-    if ((rc = ws.reserve(ws.mrows0, (size_t)kModitMaxBins * M.n_fft * csz))) return rc;
-    if ((rc = ws.reserve(ws.mrows1, (size_t)kModitMaxBins * M.n_fft * csz))) return rc;
-    M.x = (double*)ws.mlines.p;
-    M.lng = M.x + M.n_in;
-    M.S = M.lng + M.n_in;
-    M.part = (double*)ws.mpart.p;
-    M.bins = (ModitBins*)((char*)ws.mpart.p + 2 * M.n_part * sizeof(double));
-    M.rows0 = ws.mrows0.p;
-    M.rows1 = ws.mrows1.p;
-    HIP_TRY(launch_modit(M, fp64, st));
-    return EXO_OK;
+    if ((rc = ws.reserve(ws.params, 16 * sizeof(double)))) return rc;
+    const double hp[2] = {T, P};
+    double* dp = (double*)ws.params.p;
+    if ((rc = ws.stage_params(hp, 2, dp, st))) return rc;
+    return modit_opacity(c, ws, c->sp[s], dp, dp + 1, nullptr, 1, dln_gamma, precision == EXO_FP64,
+                         (const double*)c->d_nu.p, c->h_nu.front(), c->h_nu.back(), c->n_nu, sigma, st);
   });
 }
 
@@ -732,6 +803,12 @@ int exo::validate_atmos(const exo_ctx* c, const exo_atmos* a, int64_t* gb, int64
       !std::isfinite(a->cia_slope) || !std::isfinite(a->cia_nu_c) || !(a->vmr_h2 >= 0))
     return set_err(EXO_EINVAL, "bad CIA parameters");
   if (a->bottom != EXO_FB_PLANCK_BOTTOM && a->bottom != EXO_FB_ZERO) return set_err(EXO_EINVAL, "bad bottom");
+  if (a->opacity != EXO_OPACITY_LPF && a->opacity != EXO_OPACITY_MODIT) return set_err(EXO_EINVAL, "bad opacity");
+  if (a->opacity == EXO_OPACITY_MODIT) {
+    if (!c->eslog) return set_err(EXO_EINVAL, "MODIT needs a log-uniform grid");
+    if (!(a->modit_dln_gamma >= 1e-3) || !std::isfinite(a->modit_dln_gamma))
+      return set_err(EXO_EINVAL, "modit_dln_gamma must be >= 1e-3");
+  }
   if (!a->T_layers) {
     const double Tmin = std::min(a->T0_K * std::pow(a->P_bar[0], a->alpha),
                                  a->T0_K * std::pow(a->P_bar[a->n_layers - 1], a->alpha));
@@ -824,16 +901,22 @@ int exo::forward_core(exo_ctx* c, Workspace& ws, const exo_atmos* a, int64_t gb,
   const size_t esz = fp64 ? sizeof(double) : sizeof(float);
   if ((rc = ws.reserve(ws.tau, (size_t)M * NL * gl * esz))) return rc;
   if (tangent && (rc = ws.reserve(ws.taut, (size_t)M * NL * gl * sizeof(float)))) return rc;
+  const bool modit = a->opacity == EXO_OPACITY_MODIT;
+  if (modit && tangent) return set_err(EXO_EINVAL, "the MODIT opacity has no tangents");
   // every species' buffers fit in the largest plan, reserved once up front
-  if ((rc = reserve_opacity(ws, plan_opacity_all(c, a, gl, fp64, tangent)))) return rc;
+  if (!modit && (rc = reserve_opacity(ws, plan_opacity_all(c, a, gl, fp64, tangent)))) return rc;
   const double* d_nu = (const double*)c->d_nu.p + gb;
   for (int m = 0; m < M; ++m) {
     const Species& sp = c->sp[a->species[m]];
     char* out = (char*)ws.tau.p + (size_t)m * NL * gl * esz;
     float* out_t = tangent ? (float*)ws.taut.p + (size_t)m * NL * gl : nullptr;
-    if ((rc = species_opacity(c, ws, sp, A.T, A.P, A.col + (size_t)m * NL, NL, 1.0, fp64, tangent,
-                              d_nu, gl, out, out_t, st)))
-      return rc;
+    if (modit)
+      rc = modit_opacity(c, ws, sp, A.T, A.P, A.col + (size_t)m * NL, NL, a->modit_dln_gamma, fp64, d_nu,
+                         c->h_nu[gb], c->h_nu[gb + gl - 1], gl, out, st);
+    else
+      rc = species_opacity(c, ws, sp, A.T, A.P, A.col + (size_t)m * NL, NL, 1.0, fp64, tangent, d_nu, gl,
+                           out, out_t, st);
+    if (rc) return rc;
   }
   if ((rc = ws.reserve(ws.F0, (size_t)gl * sizeof(double)))) return rc;
   RtArgs R{};
@@ -881,8 +964,16 @@ size_t exo::estimate_workspace(const exo_ctx* c, const exo_atmos* a, const exo_r
   const size_t esz = fp64 ? sizeof(double) : sizeof(float);
   size_t t = R(2 * NL * 8) + R(6 * NL * 8) + R(M * NL * 8) + R(M * NL * gl * esz) + R(gl * 8);
   if (vjp) t += R(M * NL * gl * sizeof(float));
-  const OpacityPlan P = plan_opacity_all(c, a, gl, fp64, vjp);
-  for (size_t b : {P.rec, P.core, P.rect, P.rec64, P.part, P.part_t}) t += b ? R(b) : 0;
+  if (a->opacity == EXO_OPACITY_MODIT) {
+    size_t mb = 0;
+    for (int m = 0; m < a->n_species; ++m)
+      mb = std::max(mb, modit_workspace(c->sp[a->species[m]], c->h_nu[gb], c->h_nu[gb + gl - 1], gl,
+                                        a->n_layers, fp64));
+    t += mb;
+  } else {
+    const OpacityPlan P = plan_opacity_all(c, a, gl, fp64, vjp);
+    for (size_t b : {P.rec, P.core, P.rect, P.rec64, P.part, P.part_t}) t += b ? R(b) : 0;
+  }
   int64_t nmid = 0;
   if (r) {
     RespDev RD{};
@@ -932,6 +1023,7 @@ int exo::vjp_impl(exo_ctx* c, Workspace& ws, const exo_atmos* a, const exo_respo
   if ((rc = validate_atmos(c, a, &gb, &gl))) return rc;
   if (precision != EXO_FP32_KAHAN)
     return set_err(EXO_EINVAL, "the gradient is provided for EXO_FP32_KAHAN");
+  if (a->opacity != EXO_OPACITY_LPF) return set_err(EXO_EINVAL, "the gradient is provided for the direct opacity");
   const bool fused = data != nullptr;
   if (fused ? (!sigma || !loss || !grad) : (!cot || !grad))
     return set_err(EXO_EINVAL, fused ? "sigma_dev / loss_host / grad_host is NULL" : "cot_dev / grad_host is NULL");
@@ -1018,6 +1110,7 @@ static int jvp_impl(exo_ctx* c, Workspace& ws, const exo_atmos* a, const exo_res
   if ((rc = validate_atmos(c, a, &gb, &gl))) return rc;
   if (precision != EXO_FP32_KAHAN)
     return set_err(EXO_EINVAL, "flux_jvp is provided for EXO_FP32_KAHAN");
+  if (a->opacity != EXO_OPACITY_LPF) return set_err(EXO_EINVAL, "flux_jvp is provided for the direct opacity");
   if (!dth || !dflux) return set_err(EXO_EINVAL, "dtheta_host / dflux_dev is NULL");
   const int NL = a->n_layers, M = a->n_species;
   for (int k = 0; k < 2 + M + 2; ++k)

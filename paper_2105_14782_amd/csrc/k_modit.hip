@@ -16,6 +16,10 @@
 //      over k, inverse DFT;
 //   5. sigma(nu_i) = sigma(q_i) R0 / nu_i.
 // The DFTs are radix-4 / radix-2 Stockham passes through global memory.
+// Every kernel takes a batch of layers in blockIdx.y (the line positions x
+// are common to all of them); used as an opacity, the output of layer n is
+// col_n sigma, clamped at zero where the Nyquist-truncated transform rings
+// below it next to lines whose Doppler width is about one grid step.
 #include <algorithm>
 #include <utility>
 
@@ -30,17 +34,59 @@ template <> struct Cplx<float> { using T = float2; };
 template <> struct Cplx<double> { using T = double2; };
 
 // -------------------------------------------------------------------------- 1
-__global__ __launch_bounds__(256) void k_modit_lines(LinesDev L, double T, double P, double R0,
-                                                     double beta_t, double amp_scale,
-                                                     const double* __restrict__ nu, int64_t ng,
-                                                     int64_t l0, int64_t n_in, double* __restrict__ x,
-                                                     double* __restrict__ lng, double* __restrict__ S) {
+template <typename R> struct Pair;
+template <> struct Pair<float> { using T = float2; };
+template <> struct Pair<double> { using T = double2; };
+
+__device__ inline double modit_beta_t(double T, double mass, double R0) {
+  return sqrt(kKB * T / (mass * kMU)) * R0 / kC;
+}
+
+// first index in [lo, hi) with a[i] >= v (STRICT: a[i] > v)
+template <bool STRICT>
+__device__ inline int64_t lower_index(const double* __restrict__ a, int64_t lo, int64_t hi, double v) {
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (STRICT ? a[mid] <= v : a[mid] < v) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// Per layer: 1/T, ln(T/T_ref), P, 1/q_r(T) and ln(1e-3 beta~).
+__global__ __launch_bounds__(256) void k_modit_layers(const double* __restrict__ T, const double* __restrict__ P,
+                                                      int nl, double mass, double R0, int qr_kind,
+                                                      const double* __restrict__ qr_params, int n_qr,
+                                                      ModitLayer* __restrict__ lay) {
+  const int n = blockIdx.x * 256 + threadIdx.x;
+  if (n >= nl) return;
+  const double Tn = T[n];
+  double qr, dlnqr;
+  qr_eval(qr_kind, qr_params, n_qr, Tn, &qr, &dlnqr);
+  ModitLayer c;
+  c.T = Tn;
+  c.invT = 1.0 / Tn;
+  c.lnTr = log(Tn / kTref);
+  c.P = P[n];
+  c.inv_qr = 1.0 / qr;
+  c.lng_floor = log(1e-3 * modit_beta_t(Tn, mass, R0));
+  lay[n] = c;
+}
+
+// Line position in its cell (grid only): for nu_j <= nu_l < nu_{j+1} the
+// line belongs to cell j with f = (ln nu_l - ln nu_j) / (ln nu_{j+1} - ln nu_j);
+// a line at nu_{ng-1} belongs to the last cell with f = 0.
+template <typename R>
+__global__ __launch_bounds__(256) void k_modit_pos(const double* __restrict__ nu_c, int64_t l0,
+                                                   int64_t n_in, const double* __restrict__ nu,
+                                                   int64_t ng, R* __restrict__ f) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i >= n_in) return;
-  const int64_t l = l0 + i;
-  const LineState st = line_state(L, l, T, P);
-  const double nl = L.nu_c[l];
-  // j: the largest grid index <= ng - 2 with nu_j <= nl  (nu_0 <= nl <= nu_{ng-1})
+  const double nl = nu_c[l0 + i];
+  if (nl >= nu[ng - 1]) {
+    f[i] = (R)0;
+    return;
+  }
   int64_t lo = 0, hi = ng - 1;
   while (hi - lo > 1) {
     const int64_t mid = (lo + hi) >> 1;
@@ -48,9 +94,16 @@ __global__ __launch_bounds__(256) void k_modit_lines(LinesDev L, double T, doubl
     else hi = mid;
   }
   const double lj = log(nu[lo]);
-  x[i] = (double)lo + (log(nl) - lj) / (log(nu[lo + 1]) - lj);
-  lng[i] = log(fmax(R0 * st.gam / nl, 1e-3 * beta_t));
-  S[i] = st.S * amp_scale;
+  f[i] = (R)((log(nl) - lj) / (log(nu[lo + 1]) - lj));
+}
+
+// cell[j] = first window line with nu_l >= nu_j (j < ng); cell[ng] = n_in
+__global__ __launch_bounds__(256) void k_modit_cells(const double* __restrict__ nu_c, int64_t l0,
+                                                     int64_t n_in, const double* __restrict__ nu,
+                                                     int64_t ng, int64_t* __restrict__ cell) {
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (j > ng) return;
+  cell[j] = (j < ng ? lower_index<false>(nu_c, l0, l0 + n_in, nu[j]) : l0 + n_in) - l0;
 }
 
 // -------------------------------------------------------------------------- 2
@@ -70,97 +123,134 @@ __device__ inline void block_minmax256(double& mn, double& mx, double* sm) {
   mx = fmax(fmax(sm[4], sm[5]), fmax(sm[6], sm[7]));
 }
 
-__global__ __launch_bounds__(256) void k_modit_minmax(const double* __restrict__ v, int64_t n,
-                                                      double* __restrict__ part) {
+// One thread per line, looping over the layers of the launch (the line's
+// parameters are read once): rec[n][i] = {ln gamma~, S(T_n) amp_scale} with
+// gamma~ = R0 gamma / nu_l floored at 1e-3 beta~, and per block the min/max
+// of ln gamma~ (as stored) into part[n][2 blockIdx.x ..].
+template <typename R>
+__global__ __launch_bounds__(256) void k_modit_lines(LinesDev L, const ModitLayer* __restrict__ lay, int nl,
+                                                     double R0, double amp_scale, int64_t l0, int64_t n_in,
+                                                     typename Pair<R>::T* __restrict__ rec,
+                                                     double* __restrict__ part, int64_t n_part) {
+  using P2 = typename Pair<R>::T;
   __shared__ double sm[8];
-  double mn = INFINITY, mx = -INFINITY;
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
-    mn = fmin(mn, v[i]);
-    mx = fmax(mx, v[i]);
-  }
-  block_minmax256(mn, mx, sm);
-  if (threadIdx.x == 0) {
-    part[2 * blockIdx.x] = mn;
-    part[2 * blockIdx.x + 1] = mx;
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const bool ok = i < n_in;
+  const int64_t l = l0 + (ok ? i : 0);
+  const double nu = L.nu_c[l], S0 = L.S0[l], E = L.E_low[l], alpha = L.alpha_ref[l], nt = L.n_texp[l];
+  const double gnat = L.gamma_nat ? L.gamma_nat[l] : 0.0;
+  const double eR = exp(-kC2 * nu / kTref);
+  const double sfac = S0 * amp_scale / (1.0 - eR);
+  const double ln_R0nu = log(R0 / nu);
+  for (int n = 0; n < nl; ++n) {
+    const ModitLayer c = lay[n];
+    const double eT = exp(-kC2 * nu * c.invT);
+    const double S = sfac * c.inv_qr * exp(-kC2 * E * (c.invT - 1.0 / kTref)) * (1.0 - eT);
+    const double g = alpha * exp(-nt * c.lnTr) * c.P + gnat;
+    const double lng = fmax(ln_R0nu + log(g), c.lng_floor);
+    P2 v;
+    v.x = (R)lng;
+    v.y = (R)S;
+    double mn = INFINITY, mx = -INFINITY;
+    if (ok) {
+      rec[(int64_t)n * n_in + i] = v;
+      mn = mx = (double)v.x;
+    }
+    block_minmax256(mn, mx, sm);
+    if (threadIdx.x == 0) {
+      part[(int64_t)n * 2 * n_part + 2 * blockIdx.x] = mn;
+      part[(int64_t)n * 2 * n_part + 2 * blockIdx.x + 1] = mx;
+    }
   }
 }
 
 // K = floor(range / d) + 2, at most kModitMaxBins (the step widens to range / (max - 2))
-__global__ __launch_bounds__(256) void k_modit_bins(const double* __restrict__ part, int nb, double dlng,
-                                                    ModitBins* __restrict__ bins) {
+__global__ __launch_bounds__(256) void k_modit_bins(const double* __restrict__ part, int64_t nb,
+                                                    double dlng, ModitBins* __restrict__ bins) {
   __shared__ double sm[8];
+  part += (int64_t)blockIdx.y * 2 * nb;
   double mn = INFINITY, mx = -INFINITY;
-  for (int b = threadIdx.x; b < nb; b += 256) {
+  for (int64_t b = threadIdx.x; b < nb; b += 256) {
     mn = fmin(mn, part[2 * b]);
     mx = fmax(mx, part[2 * b + 1]);
   }
   block_minmax256(mn, mx, sm);
   if (threadIdx.x == 0) {
+    // in doubles, so that a non-finite range still ends with 2 <= K <= max
     const double range = mx - mn;
     double d = dlng;
-    int K = (int)floor(range / d) + 2;
-    if (K > kModitMaxBins) {
+    double Kd = floor(range / d) + 2.0;
+    if (!(Kd <= (double)kModitMaxBins)) {
       d = range / (kModitMaxBins - 2);
-      K = min((int)floor(range / d) + 2, kModitMaxBins);
+      Kd = fmin(floor(range / d) + 2.0, (double)kModitMaxBins);
     }
-    bins->lng0 = mn;
-    bins->d = d;
-    bins->K = K;
+    bins[blockIdx.y].lng0 = mn;
+    bins[blockIdx.y].d = d;
+    bins[blockIdx.y].K = (int)fmax(2.0, fmin(Kd, (double)kModitMaxBins));
   }
 }
 
 // -------------------------------------------------------------------------- 3
-// first index in [lo, hi) with a[i] >= v (STRICT: a[i] > v)
-template <bool STRICT>
-__device__ inline int64_t lower_index(const double* __restrict__ a, int64_t lo, int64_t hi, double v) {
-  while (lo < hi) {
-    const int64_t mid = (lo + hi) >> 1;
-    if (STRICT ? a[mid] <= v : a[mid] < v) lo = mid + 1;
-    else hi = mid;
-  }
-  return lo;
+// Lineshape density of layer n = blockIdx.y into rows[(n K_max + k) n_fft + j].
+// Cell j gathers the lines of cell j - 1 (weight f) and of cell j (weight
+// 1 - f).  A group of G = 2^lgG lanes shares a cell: lane g takes the lines
+// g, g + G, ... of each range (consecutive lanes read consecutive lines, so
+// the loads coalesce), accumulates them in its own LDS column, and the group
+// then sums its G columns in lane order: a fixed summation order.  The first
+// ceil(ng G / 256) blocks do the cells; the rest write the zero padding
+// j = ng .. n_fft - 1.
+template <typename R>
+__device__ inline void lsd_add(R (*acc)[256], typename Pair<R>::T r, R w, R lng0, R dinv, int K) {
+  const R t = (r.x - lng0) * dinv;
+  const int k0 = min(max((int)floor(t), 0), K - 2);   // 0 <= t by construction; clamp all the same
+  const R fk = t - (R)k0;
+  const R sw = r.y * w;
+  acc[k0][threadIdx.x] += sw * ((R)1 - fk);
+  acc[k0 + 1][threadIdx.x] += sw * fk;
 }
 
-// One thread per DFT sample j of every width row: rows[k * n_fft + j].  For
-// j < ng the cell gathers the lines with nu_{j-1} <= nu_l < nu_j (weight
-// x - (j - 1)) and nu_j <= nu_l < nu_{j+1} (weight 1 - (x - j)); the last
-// cell's second range is the lines exactly at nu_{ng-1}.  Samples j >= ng are
-// the zero padding.
 template <typename R>
-__global__ __launch_bounds__(256) void k_modit_lsd(const double* __restrict__ nu_c, int64_t l0,
-                                                   int64_t n_in, const double* __restrict__ nu,
-                                                   int64_t ng, int64_t n_fft, const double* __restrict__ x,
-                                                   const double* __restrict__ lng,
-                                                   const double* __restrict__ S,
+__global__ __launch_bounds__(256) void k_modit_lsd(const int64_t* __restrict__ cell, int64_t ng, int64_t n_fft,
+                                                   int lgG, const R* __restrict__ f,
+                                                   const typename Pair<R>::T* __restrict__ rec, int64_t n_in,
                                                    const ModitBins* __restrict__ bins,
                                                    typename Cplx<R>::T* __restrict__ rows) {
   using C = typename Cplx<R>::T;
   __shared__ R acc[kModitMaxBins][256];
-  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  const int K = bins->K;
-  const double lng0 = bins->lng0, dinv = 1.0 / bins->d;
-  for (int k = 0; k < K; ++k) acc[k][threadIdx.x] = (R)0;
-  if (j < ng) {
-    const int64_t le = l0 + n_in;
-    const int64_t a0 = j > 0 ? lower_index<false>(nu_c, l0, le, nu[j - 1]) : l0;
-    const int64_t a1 = lower_index<false>(nu_c, a0, le, nu[j]);
-    const int64_t a2 = j + 1 < ng ? lower_index<false>(nu_c, a1, le, nu[j + 1])
-                                  : lower_index<true>(nu_c, a1, le, nu[ng - 1]);
-    for (int64_t l = (j > 0 ? a0 : a1); l < a2; ++l) {
-      const int64_t i = l - l0;
-      const double w = l < a1 ? x[i] - (double)(j - 1) : 1.0 - (x[i] - (double)j);
-      const double t = (lng[i] - lng0) * dinv;
-      const int k0 = min((int)floor(t), K - 2);
-      const double fk = t - (double)k0;
-      const double sw = S[i] * w;
-      acc[k0][threadIdx.x] += (R)(sw * (1.0 - fk));
-      acc[k0 + 1][threadIdx.x] += (R)(sw * fk);
+  const int n = blockIdx.y;
+  rec += (int64_t)n * n_in;
+  rows += (int64_t)n * kModitMaxBins * n_fft;
+  const ModitBins b = bins[n];
+  const int G = 1 << lgG;
+  const int64_t cell_blocks = ((ng << lgG) + 255) / 256;
+  if ((int64_t)blockIdx.x >= cell_blocks) {   // zero padding (whole block)
+    const int64_t j = ng + ((int64_t)blockIdx.x - cell_blocks) * 256 + threadIdx.x;
+    if (j < n_fft) {
+      C z;
+      z.x = (R)0;
+      z.y = (R)0;
+      for (int k = 0; k < b.K; ++k) rows[(int64_t)k * n_fft + j] = z;
     }
+    return;
   }
-  if (j < n_fft) {
-    for (int k = 0; k < K; ++k) {
+  const R lng0 = (R)b.lng0, dinv = (R)(1.0 / b.d);
+  const int g = threadIdx.x & (G - 1);
+  const int64_t j = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> lgG;
+  for (int k = 0; k < b.K; ++k) acc[k][threadIdx.x] = (R)0;
+  if (j < ng) {
+    const int64_t a1 = cell[j], a2 = cell[j + 1];
+    const int64_t a0 = j > 0 ? cell[j - 1] : a1;
+    for (int64_t l = a0 + g; l < a1; l += G) lsd_add<R>(acc, rec[l], f[l], lng0, dinv, b.K);
+    for (int64_t l = a1 + g; l < a2; l += G) lsd_add<R>(acc, rec[l], (R)1 - f[l], lng0, dinv, b.K);
+  }
+  __syncthreads();
+  if (j < ng) {
+    const int base = threadIdx.x & ~(G - 1);
+    for (int k = g; k < b.K; k += G) {
+      R sum = (R)0;
+      for (int q = 0; q < G; ++q) sum += acc[k][base + q];
       C v;
-      v.x = acc[k][threadIdx.x];
+      v.x = sum;
       v.y = (R)0;
       rows[(int64_t)k * n_fft + j] = v;
     }
@@ -185,14 +275,14 @@ __device__ inline C cmul(C a, decltype(a.x) c, decltype(a.x) s) {
 }
 
 // One Stockham pass of radix RADIX over rows of length n: the sub-transforms
-// of length L become transforms of length RADIX * L.  Rows >= bins->K (when
-// bins is given) are skipped.
+// of length L become transforms of length RADIX * L.  With bins, row
+// y = n K_max + k is width row k of layer n and is skipped when k >= K_n.
 template <typename R, int RADIX>
 __global__ __launch_bounds__(256) void k_fft_pass(const typename Cplx<R>::T* __restrict__ in,
                                                   typename Cplx<R>::T* __restrict__ out, int64_t n,
                                                   int64_t L, const ModitBins* __restrict__ bins) {
   using C = typename Cplx<R>::T;
-  if (bins && (int)blockIdx.y >= bins->K) return;
+  if (bins && (int)(blockIdx.y % kModitMaxBins) >= bins[blockIdx.y / kModitMaxBins].K) return;
   const int64_t q = n / RADIX;
   const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (j >= q) return;
@@ -241,43 +331,53 @@ __global__ __launch_bounds__(256) void k_fft_pass(const typename Cplx<R>::T* __r
 }
 
 // -------------------------------------------------------------------------- 4'
-// Y = conj( sum_k X_k exp(-2 pi^2 beta~^2 f^2 - 2 pi gamma~_k |f|) ), f the
-// signed DFT frequency in cycles per grid step.  (The inverse DFT is then a
-// forward DFT of Y, conjugated and divided by n.)
+// Layer n = blockIdx.y:
+// Y_n = conj( sum_k X_nk exp(-2 pi^2 beta~_n^2 f^2 - 2 pi gamma~_nk |f|) ), f
+// the signed DFT frequency in cycles per grid step.  (The inverse DFT is then
+// a forward DFT of Y, conjugated and divided by n_fft.)
 template <typename R>
 __global__ __launch_bounds__(256) void k_modit_product(const typename Cplx<R>::T* __restrict__ X,
-                                                       int64_t n, const ModitBins* __restrict__ bins,
-                                                       double beta_t, typename Cplx<R>::T* __restrict__ Y) {
+                                                       int64_t n_fft, const ModitBins* __restrict__ bins,
+                                                       const double* __restrict__ T, double mass,
+                                                       double R0, typename Cplx<R>::T* __restrict__ Y) {
   using C = typename Cplx<R>::T;
   const int64_t m = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (m >= n) return;
-  const double f = (double)(m <= n / 2 ? m : m - n) / (double)n;
+  if (m >= n_fft) return;
+  const int n = blockIdx.y;
+  X += (int64_t)n * kModitMaxBins * n_fft;
+  const double beta_t = modit_beta_t(T[n], mass, R0);
+  const double f = (double)(m <= n_fft / 2 ? m : m - n_fft) / (double)n_fft;
   const double g = -2.0 * kPi * kPi * beta_t * beta_t * f * f;
   const double h = -2.0 * kPi * fabs(f);
-  const int K = bins->K;
+  const ModitBins b = bins[n];
   double sx = 0.0, sy = 0.0;
-  for (int k = 0; k < K; ++k) {
-    const double gk = exp(bins->lng0 + bins->d * k);
+  for (int k = 0; k < b.K; ++k) {
+    const double gk = exp(b.lng0 + b.d * k);
     const R w = (R)exp(g + h * gk);
-    const C v = X[(int64_t)k * n + m];
+    const C v = X[(int64_t)k * n_fft + m];
     sx += (double)(v.x * w);
     sy += (double)(v.y * w);
   }
   C y;
   y.x = (R)sx;
   y.y = (R)-sy;
-  Y[m] = y;
+  Y[(int64_t)n * n_fft + m] = y;
 }
 
 // -------------------------------------------------------------------------- 5
+// out[n][i] = Re Z_n[i] / n_fft * R0 / nu_i * scale, times col[n] and clamped
+// at zero when col is given
 template <typename R, typename TO>
 __global__ __launch_bounds__(256) void k_modit_out(const typename Cplx<R>::T* __restrict__ Z,
                                                    int64_t ng, int64_t n_fft, double R0,
                                                    const double* __restrict__ nu, double scale,
-                                                   TO* __restrict__ out) {
+                                                   const double* __restrict__ col, TO* __restrict__ out) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i >= ng) return;
-  out[i] = (TO)((double)Z[i].x / (double)n_fft * R0 / nu[i] * scale);
+  const int n = blockIdx.y;
+  double v = (double)Z[(int64_t)n * n_fft + i].x / (double)n_fft * R0 / nu[i] * scale;
+  if (col) v = fmax(v * col[n], 0.0);
+  out[(int64_t)n * ng + i] = (TO)v;
 }
 
 template <typename TO>
@@ -310,32 +410,46 @@ static void* fft_rows(void* a, void* b, int64_t n, int rows, const ModitBins* bi
 template <typename R>
 static hipError_t modit_impl(const ModitArgs& M, hipStream_t st) {
   using C = typename Cplx<R>::T;
+  using P2 = typename Pair<R>::T;
+  const unsigned nl = (unsigned)M.nl;
   const int64_t nbl = nblk(M.n_in);
-  hipLaunchKernelGGL(k_modit_lines, dim3((unsigned)nbl), dim3(256), 0, st, M.L, M.T, M.P, M.R0,
-                     M.beta_t, M.amp_scale, M.nu, M.ng, M.l0, M.n_in, M.x, M.lng, M.S);
-  const int nb = (int)std::min<int64_t>(M.n_part, nbl);
-  hipLaunchKernelGGL(k_modit_minmax, dim3((unsigned)nb), dim3(256), 0, st, M.lng, M.n_in, M.part);
-  hipLaunchKernelGGL(k_modit_bins, dim3(1), dim3(256), 0, st, M.part, nb, M.dlng, M.bins);
-  hipLaunchKernelGGL(k_modit_lsd<R>, dim3(nblk(M.n_fft)), dim3(256), 0, st, M.nu_c, M.l0, M.n_in, M.nu,
-                     M.ng, M.n_fft, M.x, M.lng, M.S, M.bins, (C*)M.rows0);
-  void* X = fft_rows<R>(M.rows0, M.rows1, M.n_fft, kModitMaxBins, M.bins, st);
+  if (M.want_pos) {
+    hipLaunchKernelGGL(k_modit_pos<R>, dim3((unsigned)nbl), dim3(256), 0, st, M.nu_c, M.l0, M.n_in, M.nu, M.ng,
+                       (R*)M.f);
+    hipLaunchKernelGGL(k_modit_cells, dim3(nblk(M.ng + 1)), dim3(256), 0, st, M.nu_c, M.l0, M.n_in, M.nu, M.ng,
+                       M.cell);
+  }
+  hipLaunchKernelGGL(k_modit_layers, dim3(nblk(M.nl)), dim3(256), 0, st, M.T, M.P, M.nl, M.mass, M.R0,
+                     M.L.qr_kind, M.L.qr_params, M.L.n_qr, M.lay);
+  hipLaunchKernelGGL(k_modit_lines<R>, dim3((unsigned)nbl), dim3(256), 0, st, M.L, (const ModitLayer*)M.lay,
+                     M.nl, M.R0, M.amp_scale, M.l0, M.n_in, (P2*)M.rec, M.part, M.n_part);
+  hipLaunchKernelGGL(k_modit_bins, dim3(1, nl), dim3(256), 0, st, M.part, M.n_part, M.dlng, M.bins);
+  // lanes per cell: about a quarter of the mean lines per cell, a power of two in [1, 64]
+  int lgG = 0;
+  while (lgG < 6 && ((int64_t)4 << lgG) * 2 <= M.n_in / M.ng) ++lgG;
+  const int64_t lsd_blocks = ((M.ng << lgG) + 255) / 256 + nblk(M.n_fft - M.ng);
+  hipLaunchKernelGGL(k_modit_lsd<R>, dim3((unsigned)lsd_blocks, nl), dim3(256), 0, st, M.cell, M.ng, M.n_fft,
+                     lgG, (const R*)M.f, (const P2*)M.rec, M.n_in, M.bins, (C*)M.rows0);
+  void* X = fft_rows<R>(M.rows0, M.rows1, M.n_fft, M.nl * kModitMaxBins, M.bins, st);
   void* Y = X == M.rows0 ? M.rows1 : M.rows0;
-  hipLaunchKernelGGL(k_modit_product<R>, dim3(nblk(M.n_fft)), dim3(256), 0, st, (const C*)X, M.n_fft,
-                     M.bins, M.beta_t, (C*)Y);
-  void* Z = fft_rows<R>(Y, X, M.n_fft, 1, nullptr, st);
+  hipLaunchKernelGGL(k_modit_product<R>, dim3(nblk(M.n_fft), nl), dim3(256), 0, st, (const C*)X, M.n_fft,
+                     M.bins, M.T, M.mass, M.R0, (C*)Y);
+  void* Z = fft_rows<R>(Y, X, M.n_fft, M.nl, nullptr, st);
   if (M.out64)
-    hipLaunchKernelGGL((k_modit_out<R, double>), dim3(nblk(M.ng)), dim3(256), 0, st, (const C*)Z, M.ng,
-                       M.n_fft, M.R0, M.nu, 1.0 / M.amp_scale, (double*)M.out);
+    hipLaunchKernelGGL((k_modit_out<R, double>), dim3(nblk(M.ng), nl), dim3(256), 0, st, (const C*)Z, M.ng,
+                       M.n_fft, M.R0, M.nu, 1.0 / M.amp_scale, M.col, (double*)M.out);
   else
-    hipLaunchKernelGGL((k_modit_out<R, float>), dim3(nblk(M.ng)), dim3(256), 0, st, (const C*)Z, M.ng,
-                       M.n_fft, M.R0, M.nu, 1.0 / M.amp_scale, (float*)M.out);
+    hipLaunchKernelGGL((k_modit_out<R, float>), dim3(nblk(M.ng), nl), dim3(256), 0, st, (const C*)Z, M.ng,
+                       M.n_fft, M.R0, M.nu, 1.0 / M.amp_scale, M.col, (float*)M.out);
   return hipGetLastError();
 }
 
 hipError_t launch_modit(const ModitArgs& M, bool fp64, hipStream_t st) {
+  if (M.nl < 1 || M.nl > kModitMaxLayersPerLaunch) return hipErrorInvalidValue;
   if (M.n_in == 0) {
-    if (M.out64) hipLaunchKernelGGL(k_zero<double>, dim3(nblk(M.ng)), dim3(256), 0, st, (double*)M.out, M.ng);
-    else hipLaunchKernelGGL(k_zero<float>, dim3(nblk(M.ng)), dim3(256), 0, st, (float*)M.out, M.ng);
+    const int64_t n = (int64_t)M.nl * M.ng;
+    if (M.out64) hipLaunchKernelGGL(k_zero<double>, dim3(nblk(n)), dim3(256), 0, st, (double*)M.out, n);
+    else hipLaunchKernelGGL(k_zero<float>, dim3(nblk(n)), dim3(256), 0, st, (float*)M.out, n);
     return hipGetLastError();
   }
   return fp64 ? modit_impl<double>(M, st) : modit_impl<float>(M, st);

@@ -23,7 +23,14 @@ import numpy as np
 # --------------------------------------------------------------------------- posterior
 
 def _logistic(z):
-    return 1.0 / (1.0 + np.exp(-z))
+    # exp of a non-positive argument only: no overflow for large |z|
+    e = np.exp(-np.abs(z))
+    return np.where(z >= 0, 1.0 / (1.0 + e), e / (1.0 + e))
+
+
+def _log_logistic(z):
+    """log s(z) = -log(1 + e^{-z}), finite for every finite z."""
+    return -np.logaddexp(0.0, -z)
 
 
 class BoxPosterior:
@@ -52,7 +59,8 @@ class BoxPosterior:
         th = self.lo + w * s
         lp, g = self.f(th)
         self.n_eval += 1
-        jac = np.sum(np.log(w) + np.log(s) + np.log1p(-s))
+        # log((hi - lo) s (1 - s)), with log(1 - s) = log s(-z)
+        jac = np.sum(np.log(w) + _log_logistic(z) + _log_logistic(-z))
         return lp + jac, np.asarray(g, float) * w * s * (1.0 - s) + (1.0 - 2.0 * s)
 
 

@@ -66,6 +66,10 @@ CASES = [
     (4097, 2000, 2000.0, 0.05, "outside"),
     (3000, 1500, 1200.0, 0.0, ""),
     (5000, 3000, 1300.0, 10.0, "wide_alpha"),
+    # dense lines: 8, 16 and 64 lanes share a cell in the lineshape-density gather
+    (2000, 70_000, 1300.0, 1.0, ""),
+    (1000, 100_000, 900.0, 0.3, "ends"),
+    (501, 300_000, 1700.0, 3.0, ""),
 ]
 
 
