@@ -97,7 +97,7 @@ struct ModitBins {
 };
 // Per-layer constants of the MODIT line pass.
 struct ModitLayer {
-  double T, invT, lnTr, P, inv_qr, lng_floor;   // lnTr = ln(T / T_ref); floor = ln(1e-3 beta~)
+  double T, invT, lnTr, P, inv_qr, ln_inv_qr, lng_floor;   // lnTr = ln(T / T_ref); floor = ln(1e-3 beta~)
 };
 struct ModitArgs {
   LinesDev L;

@@ -69,6 +69,7 @@ __global__ __launch_bounds__(256) void k_modit_layers(const double* __restrict__
   c.lnTr = log(Tn / kTref);
   c.P = P[n];
   c.inv_qr = 1.0 / qr;
+  c.ln_inv_qr = -log(qr);
   c.lng_floor = log(1e-3 * modit_beta_t(Tn, mass, R0));
   lay[n] = c;
 }
@@ -123,6 +124,60 @@ __device__ inline void block_minmax256(double& mn, double& mx, double* sm) {
   mx = fmax(fmax(sm[4], sm[5]), fmax(sm[6], sm[7]));
 }
 
+// {ln gamma~, S amp_scale} of one line at one layer.  FP64: the formulas as
+// written.  FP32 records: ln S = a - c2 E / T - ln q_r + ln(1 - e^{-c2 nu / T})
+// with a = ln(S0 amp_scale / (1 - e^{-c2 nu / T_ref})) + c2 E / T_ref; the
+// argument a - c2 E / T (whose terms nearly cancel) in FP64, its exponential
+// as 2^m exp2(y - m) with the integer m exact and exp2 in FP32 (relative
+// error ~1e-7), the remaining factors and ln gamma~ in FP32.
+struct ModitLine {
+  double nu, S0, E, alpha, nt, gnat;
+  double sfac;      // FP64 form: S0 amp_scale / (1 - e^{-c2 nu / T_ref})
+  double a, c2E;    // FP32 form
+  float c2nu, R0nu;
+};
+
+__device__ inline ModitLine modit_line(const LinesDev& L, int64_t l, double R0, double amp_scale) {
+  ModitLine m;
+  m.nu = L.nu_c[l];
+  m.S0 = L.S0[l];
+  m.E = L.E_low[l];
+  m.alpha = L.alpha_ref[l];
+  m.nt = L.n_texp[l];
+  m.gnat = L.gamma_nat ? L.gamma_nat[l] : 0.0;
+  const double eR = exp(-kC2 * m.nu / kTref);
+  m.sfac = m.S0 * amp_scale / (1.0 - eR);
+  m.c2E = kC2 * m.E;
+  m.a = log(m.sfac) + m.c2E / kTref;
+  m.c2nu = (float)(kC2 * m.nu);
+  m.R0nu = (float)(R0 / m.nu);
+  return m;
+}
+
+template <typename R>
+__device__ inline typename Pair<R>::T modit_line_layer(const ModitLine& m, const ModitLayer& c, double R0);
+
+template <>
+__device__ inline double2 modit_line_layer<double>(const ModitLine& m, const ModitLayer& c, double R0) {
+  const double eT = exp(-kC2 * m.nu * c.invT);
+  const double S = m.sfac * c.inv_qr * exp(-m.c2E * (c.invT - 1.0 / kTref)) * (1.0 - eT);
+  const double g = m.alpha * exp(-m.nt * c.lnTr) * c.P + m.gnat;
+  return make_double2(fmax(log(R0 * g / m.nu), c.lng_floor), S);
+}
+
+template <>
+__device__ inline float2 modit_line_layer<float>(const ModitLine& m, const ModitLayer& c, double R0) {
+  // log2 of the core, clamped so that m stays a small integer (S0 = 0 gives
+  // y = -inf: the core is then 2^-200, zero in FP32)
+  const double y = fmin(fmax((fma(-m.c2E, c.invT, m.a) + c.ln_inv_qr) * 1.4426950408889634, -200.0), 200.0);
+  const double mi = rint(y);
+  const float core = ldexpf(exp2f((float)(y - mi)), (int)mi);
+  const float invT = (float)c.invT;
+  const float S = core * (1.0f - expf(-m.c2nu * invT));
+  const float g = (float)m.alpha * expf(-(float)m.nt * (float)c.lnTr) * (float)c.P + (float)m.gnat;
+  return make_float2(fmaxf(logf(m.R0nu * g), (float)c.lng_floor), S);
+}
+
 // One thread per line, looping over the layers of the launch (the line's
 // parameters are read once): rec[n][i] = {ln gamma~, S(T_n) amp_scale} with
 // gamma~ = R0 gamma / nu_l floored at 1e-3 beta~, and per block the min/max
@@ -136,21 +191,9 @@ __global__ __launch_bounds__(256) void k_modit_lines(LinesDev L, const ModitLaye
   __shared__ double sm[8];
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const bool ok = i < n_in;
-  const int64_t l = l0 + (ok ? i : 0);
-  const double nu = L.nu_c[l], S0 = L.S0[l], E = L.E_low[l], alpha = L.alpha_ref[l], nt = L.n_texp[l];
-  const double gnat = L.gamma_nat ? L.gamma_nat[l] : 0.0;
-  const double eR = exp(-kC2 * nu / kTref);
-  const double sfac = S0 * amp_scale / (1.0 - eR);
-  const double ln_R0nu = log(R0 / nu);
+  const ModitLine m = modit_line(L, l0 + (ok ? i : 0), R0, amp_scale);
   for (int n = 0; n < nl; ++n) {
-    const ModitLayer c = lay[n];
-    const double eT = exp(-kC2 * nu * c.invT);
-    const double S = sfac * c.inv_qr * exp(-kC2 * E * (c.invT - 1.0 / kTref)) * (1.0 - eT);
-    const double g = alpha * exp(-nt * c.lnTr) * c.P + gnat;
-    const double lng = fmax(ln_R0nu + log(g), c.lng_floor);
-    P2 v;
-    v.x = (R)lng;
-    v.y = (R)S;
+    const P2 v = modit_line_layer<R>(m, lay[n], R0);
     double mn = INFINITY, mx = -INFINITY;
     if (ok) {
       rec[(int64_t)n * n_in + i] = v;
@@ -330,6 +373,153 @@ __global__ __launch_bounds__(256) void k_fft_pass(const typename Cplx<R>::T* __r
   }
 }
 
+// -------------------------------------------------------------------------- 4 (LDS)
+// The same DFT in two passes through global memory (n = P Q, both powers of
+// two, 32 <= P, Q <= 512).  With S = n / P transforms of length P:
+//   pass A: B[t][k] = sum_i a[t + S i] W_P^{ik}, written to b[t P + k];
+//   pass B: X[k + P u] = sum_t W_n^{tk} B[t][k] W_Q^{tu}.
+// A block does C transforms side by side (C consecutive t in A, C consecutive
+// k in B, so every gather and scatter moves C contiguous samples = 128 bytes),
+// held in LDS as element (i, c) at i (C + 1) + c, and runs the radix-4/2
+// Stockham stages of the global pass above in LDS, its twiddles from a table
+// of W_N^e, e < N.
+constexpr int kFftMaxLds = 512;
+
+template <typename R> struct FftCols;
+template <> struct FftCols<float> { static constexpr int C = 16; };
+template <> struct FftCols<double> { static constexpr int C = 8; };
+
+template <typename R, int RADIX>
+__device__ __forceinline__ void lds_stage(typename Cplx<R>::T* lds, const typename Cplx<R>::T* tw, int N, int L) {
+  using Cx = typename Cplx<R>::T;
+  constexpr int C = FftCols<R>::C, Cp = C + 1;
+  constexpr int MAXB = C * kFftMaxLds / (RADIX * 256);
+  const int q = N / RADIX;
+  const int nb = C * q;
+  const int step = N / (RADIX * L);   // W_{RADIX L}^{e} = W_N^{e step}
+  Cx d[MAXB][RADIX];
+#pragma unroll
+  for (int b = 0; b < MAXB; ++b) {
+    const int w = threadIdx.x + 256 * b;
+    if (w < nb) {
+      const int c = w & (C - 1), j = w / C, k = j & (L - 1);
+#pragma unroll
+      for (int r = 0; r < RADIX; ++r) {
+        Cx v = lds[(j + r * q) * Cp + c];
+        if (r > 0) {
+          const Cx t = tw[r * k * step];   // W_N^{e} = (cos, -sin) stored as (c, s)
+          v = cmul(v, t.x, t.y);
+        }
+        d[b][r] = v;
+      }
+      if (RADIX == 2) {
+        const Cx a0 = d[b][0], a1 = d[b][1];
+        d[b][0].x = a0.x + a1.x; d[b][0].y = a0.y + a1.y;
+        d[b][1].x = a0.x - a1.x; d[b][1].y = a0.y - a1.y;
+      } else {
+        const R s02x = d[b][0].x + d[b][2].x, s02y = d[b][0].y + d[b][2].y;
+        const R d02x = d[b][0].x - d[b][2].x, d02y = d[b][0].y - d[b][2].y;
+        const R s13x = d[b][1].x + d[b][3].x, s13y = d[b][1].y + d[b][3].y;
+        const R d13x = d[b][1].x - d[b][3].x, d13y = d[b][1].y - d[b][3].y;
+        d[b][0].x = s02x + s13x; d[b][0].y = s02y + s13y;
+        d[b][1].x = d02x + d13y; d[b][1].y = d02y - d13x;
+        d[b][2].x = s02x - s13x; d[b][2].y = s02y - s13y;
+        d[b][3].x = d02x - d13y; d[b][3].y = d02y + d13x;
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int b = 0; b < MAXB; ++b) {
+    const int w = threadIdx.x + 256 * b;
+    if (w < nb) {
+      const int c = w & (C - 1), j = w / C, k = j & (L - 1);
+      const int o = (j - k) * RADIX + k;
+#pragma unroll
+      for (int r = 0; r < RADIX; ++r) lds[(o + r * L) * Cp + c] = d[b][r];
+    }
+  }
+  __syncthreads();
+}
+
+// twiddle table W_N^e = (cos, sin)(2 pi e / N), e < N, then the Stockham stages
+template <typename R>
+__device__ __forceinline__ void lds_fft(typename Cplx<R>::T* lds, typename Cplx<R>::T* tw, int N) {
+  for (int e = threadIdx.x; e < N; e += 256) {
+    R c, s;
+    twiddle((R)e, (R)N, &c, &s);
+    tw[e].x = c;
+    tw[e].y = s;
+  }
+  __syncthreads();
+  for (int L = 1; L < N;) {
+    if (N / L >= 4) {
+      lds_stage<R, 4>(lds, tw, N, L);
+      L *= 4;
+    } else {
+      lds_stage<R, 2>(lds, tw, N, L);
+      L *= 2;
+    }
+  }
+}
+
+// LDS holds two blocks per CU: ask for the registers of two waves per SIMD
+template <typename R>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_fft_lds_a(const typename Cplx<R>::T* __restrict__ in,
+                                                   typename Cplx<R>::T* __restrict__ out, int64_t n, int lgP,
+                                                   const ModitBins* __restrict__ bins) {
+  using Cx = typename Cplx<R>::T;
+  constexpr int C = FftCols<R>::C, Cp = C + 1;
+  __shared__ Cx lds[kFftMaxLds * Cp];
+  __shared__ Cx tw[kFftMaxLds];
+  if (bins && (int)(blockIdx.y % kModitMaxBins) >= bins[blockIdx.y / kModitMaxBins].K) return;
+  const int P = 1 << lgP;
+  const int64_t S = n >> lgP;
+  const int64_t t0 = (int64_t)blockIdx.x * C;
+  const Cx* __restrict__ a = in + (int64_t)blockIdx.y * n;
+  Cx* __restrict__ b = out + (int64_t)blockIdx.y * n;
+  for (int e = threadIdx.x; e < C * P; e += 256) {
+    const int c = e & (C - 1), i = e / C;
+    lds[i * Cp + c] = a[t0 + c + S * i];
+  }
+  __syncthreads();
+  lds_fft<R>(lds, tw, P);
+  for (int e = threadIdx.x; e < C * P; e += 256) {
+    const int k = e & (P - 1), c = e >> lgP;
+    b[(t0 + c) * P + k] = lds[k * Cp + c];
+  }
+}
+
+// LDS holds two blocks per CU: ask for the registers of two waves per SIMD
+template <typename R>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_fft_lds_b(const typename Cplx<R>::T* __restrict__ in,
+                                                   typename Cplx<R>::T* __restrict__ out, int64_t n, int lgP,
+                                                   const ModitBins* __restrict__ bins) {
+  using Cx = typename Cplx<R>::T;
+  constexpr int C = FftCols<R>::C, Cp = C + 1;
+  __shared__ Cx lds[kFftMaxLds * Cp];
+  __shared__ Cx tw[kFftMaxLds];
+  if (bins && (int)(blockIdx.y % kModitMaxBins) >= bins[blockIdx.y / kModitMaxBins].K) return;
+  const int64_t P = (int64_t)1 << lgP;
+  const int Q = (int)(n >> lgP);
+  const int64_t k0 = (int64_t)blockIdx.x * C;
+  const Cx* __restrict__ a = in + (int64_t)blockIdx.y * n;
+  Cx* __restrict__ b = out + (int64_t)blockIdx.y * n;
+  for (int e = threadIdx.x; e < C * Q; e += 256) {
+    const int c = e & (C - 1), t = e / C;
+    const int64_t kk = k0 + c;
+    R cs, sn;
+    twiddle((R)(((int64_t)t * kk) & (n - 1)), (R)n, &cs, &sn);
+    lds[t * Cp + c] = cmul(a[(int64_t)t * P + kk], cs, sn);
+  }
+  __syncthreads();
+  lds_fft<R>(lds, tw, Q);
+  for (int e = threadIdx.x; e < C * Q; e += 256) {
+    const int c = e & (C - 1), u = e / C;
+    b[k0 + c + P * u] = lds[u * Cp + c];
+  }
+}
+
 // -------------------------------------------------------------------------- 4'
 // Layer n = blockIdx.y:
 // Y_n = conj( sum_k X_nk exp(-2 pi^2 beta~_n^2 f^2 - 2 pi gamma~_nk |f|) ), f
@@ -394,6 +584,17 @@ static inline unsigned nblk(int64_t n) { return (unsigned)((n + 255) / 256); }
 template <typename R>
 static void* fft_rows(void* a, void* b, int64_t n, int rows, const ModitBins* bins, hipStream_t st) {
   using C = typename Cplx<R>::T;
+  int m = 0;
+  while (((int64_t)1 << m) < n) ++m;
+  if (m >= 10 && m <= 18) {
+    constexpr int NC = FftCols<R>::C;
+    const int lgP = m / 2;
+    hipLaunchKernelGGL(k_fft_lds_a<R>, dim3((unsigned)((n >> lgP) / NC), (unsigned)rows), dim3(256), 0, st,
+                       (const C*)a, (C*)b, n, lgP, bins);
+    hipLaunchKernelGGL(k_fft_lds_b<R>, dim3((unsigned)(((int64_t)1 << lgP) / NC), (unsigned)rows), dim3(256), 0,
+                       st, (const C*)b, (C*)a, n, lgP, bins);
+    return a;
+  }
   C* src = (C*)a;
   C* dst = (C*)b;
   for (int64_t L = 1; L < n;) {
