@@ -150,12 +150,23 @@ __device__ __forceinline__ void near_range(const VoigtArgs& A, const LineRec* __
 }
 
 // Far lines [sb, se): truncated wing polynomial, no core branch.
+// Offsets in FP32 from the wave's first point nu_w: d = (nu_j - nu_w) -
+// (nu_l - nu_w), each difference formed in FP64 and rounded once (the line's
+// once per wave, the points' once per chunk); for a far line (|d| >= the near
+// reach) this errs by ~1e-7 relative, like rounding the FP64 offset.  One
+// reciprocal serves two points: r0 = D1 / (D0 D1), r1 = D0 / (D0 D1) (D >= the
+// squared reach, so the product stays a normal FP32 number for any physical
+// width).
 template <bool TAN, int G>
 __device__ __forceinline__ void far_lines(int sb, int se, const LineRec* __restrict__ R,
                                           const LineRecT* __restrict__ RT,
-                                          const double* __restrict__ nuc, const double (&nuj)[G],
+                                          const double* __restrict__ nuc, const double (&nuj)[G], double nuw,
                                           float (&s)[G], float (&c)[G], float (&ts)[G],
                                           float (&tc)[G]) {
+  static_assert(G % 2 == 0, "points go in pairs");
+  float dj[G];
+#pragma unroll
+  for (int g = 0; g < G; ++g) dj[g] = (float)(nuj[g] - nuw);
   for (int l0 = sb; l0 < se; l0 += kChunk) {
     const int l1 = min(l0 + kChunk, se);
     float blk[G], tblk[G];
@@ -172,7 +183,7 @@ __device__ __forceinline__ void far_lines(int sb, int se, const LineRec* __restr
     for (int l = l0; l < l1; ++l) {
       const float4 e = en;
       const float g2 = g2n;
-      const double nul = nun;
+      const float dl = (float)(nun - nuw);
       float4 t;
       if (TAN) t = tn;
       const int ln = l + 1 < l1 ? l + 1 : l;
@@ -180,15 +191,25 @@ __device__ __forceinline__ void far_lines(int sb, int se, const LineRec* __restr
       g2n = R[ln].gam2;
       nun = nuc[ln];
       if (TAN) tn = *reinterpret_cast<const float4*>(RT[ln].t);
+      float D[G], r[G];
 #pragma unroll
       for (int g = 0; g < G; ++g) {
-        const float d = (float)(nuj[g] - nul);  // FP64 offset, rounded once
-        const float r = __builtin_amdgcn_rcpf(fmaf(d, d, g2));
-        const float h = fmaf(fmaf(e.z, r, e.y), r, e.x);
-        blk[g] = fmaf(h, r, blk[g]);
+        const float d = dj[g] - dl;
+        D[g] = fmaf(d, d, g2);
+      }
+#pragma unroll
+      for (int g = 0; g < G; g += 2) {
+        const float inv = __builtin_amdgcn_rcpf(D[g] * D[g + 1]);
+        r[g] = D[g + 1] * inv;
+        r[g + 1] = D[g] * inv;
+      }
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        const float h = fmaf(fmaf(e.z, r[g], e.y), r[g], e.x);
+        blk[g] = fmaf(h, r[g], blk[g]);
         if (TAN) {
-          const float ht = fmaf(fmaf(fmaf(t.w, r, t.z), r, t.y), r, t.x);
-          tblk[g] = fmaf(ht, r, tblk[g]);
+          const float ht = fmaf(fmaf(fmaf(t.w, r[g], t.z), r[g], t.y), r[g], t.x);
+          tblk[g] = fmaf(ht, r[g], tblk[g]);
         }
       }
     }
@@ -308,6 +329,9 @@ __device__ __forceinline__ void voigt_body(const VoigtArgs& A) {
   const LineCore* __restrict__ RC = A.core + (int64_t)y * A.n_lines;
   int i0, i1;
   near_range<G>(A, R, tile0, w, lb, le, i0, i1);
+  // base of the far tier's FP32 offsets: the wave's first point (uniform)
+  const int64_t jw = tile0 + (int64_t)w * G * 64;
+  const double nuw = A.nu[jw < A.ng ? jw : A.ng - 1];
 
   float s[G], c[G], ts[G], tc[G];
 #pragma unroll
@@ -316,7 +340,7 @@ __device__ __forceinline__ void voigt_body(const VoigtArgs& A) {
   for (int seg = 0; seg < 2; ++seg) {
     const int sb = seg == 0 ? lb : i1;
     const int se = seg == 0 ? i0 : le;
-    far_lines<TAN, G>(sb, se, R, RT, A.nu_c, nuj, s, c, ts, tc);
+    far_lines<TAN, G>(sb, se, R, RT, A.nu_c, nuj, nuw, s, c, ts, tc);
     if (seg == 0) near_lines<TAN, G>(i0, i1, R, RT, RC, A.nu_c, nuj, s, c, ts, tc);
   }
   if (A.near_pairs && lane == 0) {
@@ -343,11 +367,13 @@ __device__ __forceinline__ void voigt_body(const VoigtArgs& A) {
 // The kernels.  The tangent-mode loop needs 96 registers per lane, which
 // allows 5 waves per SIMD; asking for 7 keeps both line loops free of spills
 // (the spills land in the rarely taken core branch) and measured 9 % faster.
-// The forward kernel fits 8 waves without the hint.
+// The forward kernel needs 66 (7 waves); asking for 8 spills three registers
+// outside the line loops and measured 10 % faster.
 template <bool TAN, int G>
 __global__ void k_voigt_f32(VoigtArgs A);
 template <>
-__global__ __launch_bounds__(256) void k_voigt_f32<false, kVoigtG>(VoigtArgs A) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_voigt_f32<false, kVoigtG>(
+    VoigtArgs A) {
   voigt_body<false, kVoigtG>(A);
 }
 template <>
