@@ -222,6 +222,10 @@ __device__ __forceinline__ void far_lines(int sb, int se, const LineRec* __restr
 }
 
 // Near lines [sb, se): full wing polynomial, Algorithm-916 series in the core.
+// The line loop evaluates the wing and only marks the pairs inside the core
+// (x^2 + a^2 < 111), one bit per line of the chunk per point; the marked
+// pairs are evaluated after the loop, line by line in chunk order, with less
+// state live across the out-of-line core call than inside the loop.
 template <bool TAN, int G>
 __device__ __forceinline__ void near_lines(int sb, int se, const LineRec* __restrict__ R,
                                            const LineRecT* __restrict__ RT,
@@ -229,18 +233,21 @@ __device__ __forceinline__ void near_lines(int sb, int se, const LineRec* __rest
                                            const double* __restrict__ nuc, const double (&nuj)[G],
                                            float (&s)[G], float (&c)[G], float (&ts)[G],
                                            float (&tc)[G]) {
+  static_assert(kChunk == 32, "one mask bit per line of the chunk");
   for (int l0 = sb; l0 < se; l0 += kChunk) {
     const int l1 = min(l0 + kChunk, se);
     float blk[G], tblk[G];
+    uint32_t cm[G];
 #pragma unroll
-    for (int g = 0; g < G; ++g) blk[g] = tblk[g] = 0.f;
+    for (int g = 0; g < G; ++g) {
+      blk[g] = tblk[g] = 0.f;
+      cm[g] = 0u;
+    }
     LineRec qn = R[l0];
     double nun = nuc[l0];
     LineRecT qtn;
     if (TAN) qtn = RT[l0];
-    // (the forward loop does not unroll once its core call is in place)
-    constexpr int kUnroll = TAN ? 2 : 1;
-#pragma unroll kUnroll
+#pragma unroll 2
     for (int l = l0; l < l1; ++l) {
       const LineRec q = qn;
       const double nul = nun;
@@ -250,57 +257,63 @@ __device__ __forceinline__ void near_lines(int sb, int se, const LineRec* __rest
       qn = R[ln];
       nun = nuc[ln];
       if (TAN) qtn = RT[ln];
-      float dd[G], D[G], f[G], ft[G];
-      bool core = false;
 #pragma unroll
       for (int g = 0; g < G; ++g) {
-        dd[g] = (float)(nuj[g] - nul);  // FP64 offset, rounded once
-        D[g] = fmaf(dd[g], dd[g], q.gam2);
-        const float r = __builtin_amdgcn_rcpf(D[g]);
+        const float dd = (float)(nuj[g] - nul);  // FP64 offset, rounded once
+        const float D = fmaf(dd, dd, q.gam2);
+        const float r = __builtin_amdgcn_rcpf(D);
         float h = fmaf(q.e[6], r, q.e[5]);
         h = fmaf(h, r, q.e[4]);
         h = fmaf(h, r, q.e[3]);
         h = fmaf(h, r, q.e[2]);
         h = fmaf(h, r, q.e[1]);
         h = fmaf(h, r, q.e[0]);
-        f[g] = h * r;
+        float ht = 0.f;
         if (TAN) {
-          float ht = fmaf(qt.t[7], r, qt.t[6]);
+          ht = fmaf(qt.t[7], r, qt.t[6]);
           ht = fmaf(ht, r, qt.t[5]);
           ht = fmaf(ht, r, qt.t[4]);
           ht = fmaf(ht, r, qt.t[3]);
           ht = fmaf(ht, r, qt.t[2]);
           ht = fmaf(ht, r, qt.t[1]);
           ht = fmaf(ht, r, qt.t[0]);
-          ft[g] = ht * r;
         }
-        core |= D[g] < q.thr;
+        const bool in_core = D < q.thr;
+        cm[g] |= (uint32_t)in_core << (l - l0);
+        blk[g] += in_core ? 0.f : h * r;
+        if (TAN) tblk[g] += in_core ? 0.f : ht * r;
       }
-      // x^2 + a^2 < 111 for some point of this thread: Algorithm-916 series
-      if (__builtin_expect(core, 0)) {
+    }
+    // lines of the chunk with a core pair at any point of the wave
+    uint32_t u = 0u;
 #pragma unroll
-        for (int g = 0; g < G; ++g) {
-          if (D[g] < q.thr) {
-            const float x = dd[g] * q.winv;
-            if (TAN) {
-              const float2 HL = core_value_tan(x, q.a, q.ainv, q.erfcxa, q.C1, RC[l].w);
-              const float H = HL.x, L = HL.y;
-              // custom derivatives of Sec. 2.1.1:
-              //   dH/dx = 2aL - 2xH,  dH/da = 2xL + 2aH - 2/sqrt(pi)
-              const float Hx = 2.0f * (q.a * L - x * H);
-              const float Ha = 2.0f * (x * L + q.a * H) - 1.1283791670955126f;
-              f[g] = q.acore * H;
-              ft[g] = q.acore * (qt.kA * H + Hx * x * qt.kw + Ha * qt.da);
-            } else {
-              f[g] = q.acore * core_value(x, q.a, q.ainv, q.erfcxa, q.C1, RC[l].w);
-            }
-          }
-        }
-      }
+    for (int g = 0; g < G; ++g) u |= cm[g];
+    for (int o = 32; o > 0; o >>= 1) u |= (uint32_t)__shfl_xor((int)u, o);
+    u = __builtin_amdgcn_readfirstlane(u);
+    while (u) {
+      const int i = __builtin_ctz(u);
+      u &= u - 1u;
+      const int l = l0 + i;
+      const LineRec q = R[l];
+      const double nul = nuc[l];
 #pragma unroll
       for (int g = 0; g < G; ++g) {
-        blk[g] += f[g];
-        if (TAN) tblk[g] += ft[g];
+        if ((cm[g] >> i) & 1u) {
+          const float x = (float)(nuj[g] - nul) * q.winv;
+          if (TAN) {
+            const LineRecT qt = RT[l];
+            const float2 HL = core_value_tan(x, q.a, q.ainv, q.erfcxa, q.C1, RC[l].w);
+            const float H = HL.x, L = HL.y;
+            // custom derivatives of Sec. 2.1.1:
+            //   dH/dx = 2aL - 2xH,  dH/da = 2xL + 2aH - 2/sqrt(pi)
+            const float Hx = 2.0f * (q.a * L - x * H);
+            const float Ha = 2.0f * (x * L + q.a * H) - 1.1283791670955126f;
+            blk[g] += q.acore * H;
+            tblk[g] += q.acore * (qt.kA * H + Hx * x * qt.kw + Ha * qt.da);
+          } else {
+            blk[g] += q.acore * core_value(x, q.a, q.ainv, q.erfcxa, q.C1, RC[l].w);
+          }
+        }
       }
     }
 #pragma unroll
