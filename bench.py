@@ -52,6 +52,9 @@ def parse():
     ap.add_argument("--cpu-points", type=int, default=256)
     ap.add_argument("--serve-requests", type=int, default=48,
                     help="requests of the Poisson serving run (0: skip)")
+    ap.add_argument("--serve-load", type=float, nargs="+", default=[0.9],
+                    help="arrival rates of the serving runs as fractions of the measured capacity")
+    ap.add_argument("--serving-only", action="store_true", help="only the serving runs")
     ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write the traffic summary from two --pmc runs of --counters and exit")
     ap.add_argument("--summarize-valu", metavar="VALU_CSV",
@@ -303,6 +306,11 @@ def modit_bench(reps=5):
             run[f"modit_{prec}_ms"] = 1e3 * timed(lambda: ctx.cross_section_modit(0, T, P, prec), reps)
         run["direct_fp32_ms"] = 1e3 * timed(lambda: ctx.cross_section(0, T, P, "fp32"), 1 if stride == 1 else 3)
         run["direct_over_modit_fp32"] = run["direct_fp32_ms"] / run["modit_fp32_ms"]
+        run["direct_fp32_evals_per_s"] = sub.n * wl.nu.size / (1e-3 * run["direct_fp32_ms"])
+        if stride == 1:
+            # the plain FP64 form on the whole config-3 list (1e12 evaluations)
+            run["direct_fp64_ms"] = 1e3 * timed(lambda: ctx.cross_section(0, T, P, "fp64"), 1)
+            run["direct_fp32_over_fp64"] = run["direct_fp64_ms"] / run["direct_fp32_ms"]
         # weak-line pre-selection (App. G) of the same list on the config-3 atmosphere:
         # isothermal 1700 K, strengths scanned over 500-1700 K, margin 2 layers
         run["select_ms"] = 1e3 * timed(lambda: ctx.select_lines(0, math.log10(0.0023), atm, 1700.0, T_scan, 2),
@@ -312,6 +320,34 @@ def modit_bench(reps=5):
     ctx.close()
     out["emission"] = modit_emission_bench(reps)
     out["emission"]["direct_single_layer_fp32_ms"] = out["runs"][-1]["direct_fp32_ms"]
+    return out
+
+
+def config1_bench(reps=50):
+    """Configuration 1: one layer (1000 K, 1 bar) of 1000 lines on a
+    4000-point linear grid, FP32 and the plain FP64 form; median time per
+    call after a warm-up (a latency-bound call)."""
+    import torch
+    import synth
+    from paper_2105_14782_amd import api
+    wl = synth.make_config(1, "full")
+    ctx = api.Context(0)
+    ctx.set_lines(0, wl.lines[0])
+    ctx.set_grid(wl.nu)
+    out = {"workload": "config-1 cross-section: 1000 lines, 4000-point linear grid, 1000 K, 1 bar"}
+    for prec in ("fp32", "fp64"):
+        ctx.cross_section(0, wl.T, wl.P_bar, prec)
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            t = time.perf_counter()
+            ctx.cross_section(0, wl.T, wl.P_bar, prec)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t)
+        us = 1e6 * float(np.median(ts))
+        out[f"{prec}_us"] = us
+        out[f"{prec}_evals_per_s"] = wl.lines[0].n * wl.nu.size / (1e-6 * us)
+    ctx.close()
     return out
 
 
@@ -344,12 +380,13 @@ def modit_emission_bench(reps=5):
 SERVE_MARGIN = 260   # output margin (points) at R0 = 1e6: rotation + RV + 6-sigma IP reach < 200
 
 
-def serving_bench(n_req, n_streams=4, budget=48 << 30):
+def serving_bench(n_req, loads=(0.9,), n_streams=4, budget=48 << 30):
     """Continuous batching on a stream shaped like the serving configuration:
     16 resident lists (1e3-1e6 lines, 3900-5100 cm^-1), windows of 2e3-1e5
     points on an R0 = 1e6 grid, 50-200 layers, HMC-like parameter walk.
-    Capacity is measured closed-loop first; then Poisson arrivals at 0.9 x
-    capacity give the latency distribution (arrival -> spectrum on device)."""
+    Capacity is measured closed-loop first; then Poisson arrivals at each
+    load x capacity give the latency distribution (arrival -> spectrum on
+    device).  The top-level latency fields are those of the first load."""
     import torch
     import synth
     from paper_2105_14782_amd import api, serve
@@ -377,18 +414,23 @@ def serving_bench(n_req, n_streams=4, budget=48 << 30):
     cap = serve.run_stream(srv, closed)
     evals = lambda reqs: sum((lists[a.species[0]].n + lists[a.species[1]].n) * a.grid_len * len(a.P_bar)
                              for a, _ in reqs)
-    rate = 0.9 * cap["spectra_per_s"]
-    reqs = synth.serving_requests(n_req, rate, nu_master=nu)
-    stream = args(reqs)
-    arr = np.array([q.arrival_s for q in reqs])
-    res = serve.run_stream(srv, stream, arr)
+    runs = []
+    for rho in loads:
+        rate = rho * cap["spectra_per_s"]
+        reqs = synth.serving_requests(n_req, rate, nu_master=nu)
+        arr = np.array([q.arrival_s for q in reqs])
+        res = serve.run_stream(srv, args(reqs), arr)
+        runs.append({"load": rho, "arrival_rate_hz": rate, "spectra_per_s": res["spectra_per_s"],
+                     "p50_ms": res["p50_ms"], "p99_ms": res["p99_ms"]})
+        print(f"serving: load {rho}: p50 {res['p50_ms']:.0f} ms, p99 {res['p99_ms']:.0f} ms", file=sys.stderr, flush=True)
     st = srv.stats()
     srv.close()
     ctx.close()
+    first = runs[0]
     return {"requests": n_req, "streams": n_streams, "capacity_spectra_per_s": cap["spectra_per_s"],
             "capacity_evals_per_s": evals(closed) / cap["wall_s"],
-            "arrival_rate_hz": rate, "spectra_per_s": res["spectra_per_s"],
-            "p50_ms": res["p50_ms"], "p99_ms": res["p99_ms"],
+            "arrival_rate_hz": first["arrival_rate_hz"], "spectra_per_s": first["spectra_per_s"],
+            "p50_ms": first["p50_ms"], "p99_ms": first["p99_ms"], "loads": runs,
             "mem_peak_gb": st["mem_peak_bytes"] / 2 ** 30, "mem_budget_gb": st["mem_budget_bytes"] / 2 ** 30}
 
 
@@ -419,6 +461,9 @@ def main():
         return
     if args.modit_emission_only:
         print(json.dumps({"modit_emission": modit_emission_bench()}), flush=True)
+        return
+    if args.serving_only:
+        print(json.dumps({"serving": serving_bench(args.serve_requests, args.serve_load)}), flush=True)
         return
     import torch
     import synth
@@ -548,9 +593,10 @@ def main():
     }
     ctx.close()
     if args.serve_requests > 0:
-        out["serving"] = serving_bench(args.serve_requests)
+        out["serving"] = serving_bench(args.serve_requests, args.serve_load)
     if not args.no_modit:
         out["modit"] = modit_bench()
+    out["config1"] = config1_bench()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, theta, args.cpu_points)
     print(json.dumps(out), flush=True)
