@@ -55,6 +55,8 @@ def parse():
     ap.add_argument("--serve-load", type=float, nargs="+", default=[0.9],
                     help="arrival rates of the serving runs as fractions of the measured capacity")
     ap.add_argument("--serving-only", action="store_true", help="only the serving runs")
+    ap.add_argument("--config3-direct", action="store_true",
+                    help="only one direct-sum FP32 spectrum of the whole config-3 workload (~1e14 evaluations)")
     ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write the traffic summary from two --pmc runs of --counters and exit")
     ap.add_argument("--summarize-valu", metavar="VALU_CSV",
@@ -351,6 +353,32 @@ def config1_bench(reps=50):
     return out
 
 
+def config3_direct_bench():
+    """One FP32 forward spectrum (F0, no response) of the whole config-3
+    workload by the direct sum: 1e7 lines x 100,000 points x 100 layers."""
+    import torch
+    import synth
+    from paper_2105_14782_amd import api
+    wl = synth.make_config(3, "full")
+    ctx = api.Context(0)
+    ctx.set_lines(0, wl.lines[0])
+    ctx.set_grid(wl.nu)
+    atm = api.Atmos.from_workload(wl.atmos, [0])
+    ctx.profile(True)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    ctx.emission_flux(atm, None, "fp32")
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t
+    nl, kms, evals = ctx.profile_read()
+    near = ctx.profile_read_near()
+    ctx.close()
+    total = wl.lines[0].n * wl.nu.size * wl.atmos.P_bar.size
+    return {"workload": "config-3 direct-sum FP32 spectrum: 1e7 lines, 100,000 points, 100 layers",
+            "s": dt, "evals": total, "evals_per_s": total / dt, "voigt_kernel_ms": kms,
+            "near_fraction": near / max(evals, 1.0)}
+
+
 def modit_emission_bench(reps=5):
     """The whole config-3 emission spectrum (all 1e7 lines, 100 layers, no
     response) with MODIT opacities, FP32 and FP64; the direct sum would take
@@ -461,6 +489,9 @@ def main():
         return
     if args.modit_emission_only:
         print(json.dumps({"modit_emission": modit_emission_bench()}), flush=True)
+        return
+    if args.config3_direct:
+        print(json.dumps({"config3_direct": config3_direct_bench()}), flush=True)
         return
     if args.serving_only:
         print(json.dumps({"serving": serving_bench(args.serve_requests, args.serve_load)}), flush=True)
