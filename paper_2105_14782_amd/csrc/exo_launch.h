@@ -90,6 +90,9 @@ struct JvpArgs {
 
 // MODIT (Sec. 2.1.2) of one species on a batch of layers (blockIdx.y).
 constexpr int kModitMaxBins = 32;   // width bins of the lineshape density
+// The width rows are real: rows 2p and 2p + 1 travel as the real and the
+// imaginary part of one complex DFT row.
+constexpr int kModitRows = kModitMaxBins / 2;
 struct ModitBins {
   double lng0, d;   // ln gamma~_k = lng0 + k d
   int K;
@@ -119,13 +122,13 @@ struct ModitArgs {
   double* part;            // [nl][2 n_part] min/max partials of ln gamma~, one per line block
   int64_t n_part;
   ModitBins* bins;         // device [nl]
-  void *rows0, *rows1;     // [nl][kModitMaxBins][n_fft] complex (float2 or double2)
+  void *rows0, *rows1;     // [nl][kModitRows][n_fft] complex (float2 or double2), bins in pairs
   void* out;               // [nl][ng] float or double
   bool out64;
 };
 // Largest batch of layers per MODIT launch (the forward DFT grid has
-// nl * kModitMaxBins rows in blockIdx.y).
-constexpr int kModitMaxLayersPerLaunch = 65535 / kModitMaxBins;
+// nl * kModitRows rows in blockIdx.y).
+constexpr int kModitMaxLayersPerLaunch = 65535 / kModitRows;
 
 // Weak-line pre-selection (App. G) of one species in an isothermal atmosphere.
 struct SelectArgs {

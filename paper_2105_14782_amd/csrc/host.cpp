@@ -641,7 +641,7 @@ static ModitPlan modit_plan(int64_t n_in, int64_t ng, int nlay, bool fp64) {
   const int64_t ni = std::max<int64_t>(n_in, 1);
   q.n_fft = modit_fft_len(ng);
   q.nbl = (ni + 255) / 256;
-  const size_t per_layer = 2 * (size_t)kModitMaxBins * q.n_fft * csz + (size_t)ni * psz +
+  const size_t per_layer = 2 * (size_t)kModitRows * q.n_fft * csz + (size_t)ni * psz +
                            2 * (size_t)q.nbl * sizeof(double) + sizeof(ModitBins) + sizeof(ModitLayer);
   const size_t nb = std::max<size_t>(1, kModitBudget / per_layer);
   q.nb = (int)std::min<size_t>({nb, (size_t)nlay, (size_t)kModitMaxLayersPerLaunch});
@@ -650,7 +650,7 @@ static ModitPlan modit_plan(int64_t n_in, int64_t ng, int nlay, bool fp64) {
   q.off_rec = q.off_lay + align256((size_t)q.nb * sizeof(ModitLayer));
   q.lines_bytes = q.off_rec + (size_t)q.nb * ni * psz;
   q.part_bytes = align256((size_t)q.nb * 2 * q.nbl * sizeof(double)) + (size_t)q.nb * sizeof(ModitBins);
-  q.rows_bytes = (size_t)q.nb * kModitMaxBins * q.n_fft * csz;
+  q.rows_bytes = (size_t)q.nb * kModitRows * q.n_fft * csz;
   return q;
 }
 

@@ -11,9 +11,10 @@
 //      (j, k) nodes with linear weights, gathered per grid cell (the lines are
 //      sorted by centre, so a cell's lines are one contiguous range and the
 //      sum order is fixed);
-//   4. DFT of every width row (length n_fft, zero padded), the product with
-//      the Voigt transform exp(-2 pi^2 beta~^2 f^2 - 2 pi gamma~_k |f|) summed
-//      over k, inverse DFT;
+//   4. DFT of every width row (length n_fft, zero padded; the rows are real,
+//      so rows 2p and 2p + 1 share one complex DFT as its real and imaginary
+//      parts), the product with the Voigt transform
+//      exp(-2 pi^2 beta~^2 f^2 - 2 pi gamma~_k |f|) summed over k, inverse DFT;
 //   5. sigma(nu_i) = sigma(q_i) R0 / nu_i.
 // The DFTs are radix-4 / radix-2 Stockham passes through global memory.
 // Every kernel takes a batch of layers in blockIdx.y (the line positions x
@@ -234,7 +235,8 @@ __global__ __launch_bounds__(256) void k_modit_bins(const double* __restrict__ p
 }
 
 // -------------------------------------------------------------------------- 3
-// Lineshape density of layer n = blockIdx.y into rows[(n K_max + k) n_fft + j].
+// Lineshape density of layer n = blockIdx.y: width rows 2p and 2p + 1 into
+// the real and imaginary parts of rows[(n kModitRows + p) n_fft + j].
 // Cell j gathers the lines of cell j - 1 (weight f) and of cell j (weight
 // 1 - f).  A group of G = 2^lgG lanes shares a cell: lane g takes the lines
 // g, g + G, ... of each range (consecutive lanes read consecutive lines, so
@@ -262,8 +264,9 @@ __global__ __launch_bounds__(256) void k_modit_lsd(const int64_t* __restrict__ c
   __shared__ R acc[kModitMaxBins][256];
   const int n = blockIdx.y;
   rec += (int64_t)n * n_in;
-  rows += (int64_t)n * kModitMaxBins * n_fft;
+  rows += (int64_t)n * kModitRows * n_fft;
   const ModitBins b = bins[n];
+  const int Kp = (b.K + 1) / 2;
   const int G = 1 << lgG;
   const int64_t cell_blocks = ((ng << lgG) + 255) / 256;
   if ((int64_t)blockIdx.x >= cell_blocks) {   // zero padding (whole block)
@@ -272,14 +275,14 @@ __global__ __launch_bounds__(256) void k_modit_lsd(const int64_t* __restrict__ c
       C z;
       z.x = (R)0;
       z.y = (R)0;
-      for (int k = 0; k < b.K; ++k) rows[(int64_t)k * n_fft + j] = z;
+      for (int p = 0; p < Kp; ++p) rows[(int64_t)p * n_fft + j] = z;
     }
     return;
   }
   const R lng0 = (R)b.lng0, dinv = (R)(1.0 / b.d);
   const int g = threadIdx.x & (G - 1);
   const int64_t j = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> lgG;
-  for (int k = 0; k < b.K; ++k) acc[k][threadIdx.x] = (R)0;
+  for (int k = 0; k < 2 * Kp; ++k) acc[k][threadIdx.x] = (R)0;   // an odd K pairs with a zero row
   if (j < ng) {
     const int64_t a1 = cell[j], a2 = cell[j + 1];
     const int64_t a0 = j > 0 ? cell[j - 1] : a1;
@@ -289,13 +292,15 @@ __global__ __launch_bounds__(256) void k_modit_lsd(const int64_t* __restrict__ c
   __syncthreads();
   if (j < ng) {
     const int base = threadIdx.x & ~(G - 1);
-    for (int k = g; k < b.K; k += G) {
-      R sum = (R)0;
-      for (int q = 0; q < G; ++q) sum += acc[k][base + q];
+    for (int p = g; p < Kp; p += G) {
       C v;
-      v.x = sum;
+      v.x = (R)0;
       v.y = (R)0;
-      rows[(int64_t)k * n_fft + j] = v;
+      for (int q = 0; q < G; ++q) {
+        v.x += acc[2 * p][base + q];
+        v.y += acc[2 * p + 1][base + q];
+      }
+      rows[(int64_t)p * n_fft + j] = v;
     }
   }
 }
@@ -319,13 +324,14 @@ __device__ inline C cmul(C a, decltype(a.x) c, decltype(a.x) s) {
 
 // One Stockham pass of radix RADIX over rows of length n: the sub-transforms
 // of length L become transforms of length RADIX * L.  With bins, row
-// y = n K_max + k is width row k of layer n and is skipped when k >= K_n.
+// y = n kModitRows + p holds width rows 2p, 2p + 1 of layer n and is skipped
+// when 2p >= K_n.
 template <typename R, int RADIX>
 __global__ __launch_bounds__(256) void k_fft_pass(const typename Cplx<R>::T* __restrict__ in,
                                                   typename Cplx<R>::T* __restrict__ out, int64_t n,
                                                   int64_t L, const ModitBins* __restrict__ bins) {
   using C = typename Cplx<R>::T;
-  if (bins && (int)(blockIdx.y % kModitMaxBins) >= bins[blockIdx.y / kModitMaxBins].K) return;
+  if (bins && (int)(blockIdx.y % kModitRows) >= (bins[blockIdx.y / kModitRows].K + 1) / 2) return;
   const int64_t q = n / RADIX;
   const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (j >= q) return;
@@ -472,7 +478,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   constexpr int C = FftCols<R>::C, Cp = C + 1;
   __shared__ Cx lds[kFftMaxLds * Cp];
   __shared__ Cx tw[kFftMaxLds];
-  if (bins && (int)(blockIdx.y % kModitMaxBins) >= bins[blockIdx.y / kModitMaxBins].K) return;
+  if (bins && (int)(blockIdx.y % kModitRows) >= (bins[blockIdx.y / kModitRows].K + 1) / 2) return;
   const int P = 1 << lgP;
   const int64_t S = n >> lgP;
   const int64_t t0 = (int64_t)blockIdx.x * C;
@@ -499,7 +505,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   constexpr int C = FftCols<R>::C, Cp = C + 1;
   __shared__ Cx lds[kFftMaxLds * Cp];
   __shared__ Cx tw[kFftMaxLds];
-  if (bins && (int)(blockIdx.y % kModitMaxBins) >= bins[blockIdx.y / kModitMaxBins].K) return;
+  if (bins && (int)(blockIdx.y % kModitRows) >= (bins[blockIdx.y / kModitRows].K + 1) / 2) return;
   const int64_t P = (int64_t)1 << lgP;
   const int Q = (int)(n >> lgP);
   const int64_t k0 = (int64_t)blockIdx.x * C;
@@ -523,7 +529,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
 // -------------------------------------------------------------------------- 4'
 // Layer n = blockIdx.y:
 // Y_n = conj( sum_k X_nk exp(-2 pi^2 beta~_n^2 f^2 - 2 pi gamma~_nk |f|) ), f
-// the signed DFT frequency in cycles per grid step.  (The inverse DFT is then
+// the signed DFT frequency in cycles per grid step.  The DFT Z of row p packs
+// the real rows 2p and 2p + 1: with A = Z[m], B = conj(Z[-m]),
+// X_2p[m] = (A + B)/2 and X_2p+1[m] = (A - B)/(2i).  (The inverse DFT is then
 // a forward DFT of Y, conjugated and divided by n_fft.)
 template <typename R>
 __global__ __launch_bounds__(256) void k_modit_product(const typename Cplx<R>::T* __restrict__ X,
@@ -534,19 +542,27 @@ __global__ __launch_bounds__(256) void k_modit_product(const typename Cplx<R>::T
   const int64_t m = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (m >= n_fft) return;
   const int n = blockIdx.y;
-  X += (int64_t)n * kModitMaxBins * n_fft;
+  X += (int64_t)n * kModitRows * n_fft;
+  const int64_t mr = (n_fft - m) & (n_fft - 1);   // -m mod n_fft
   const double beta_t = modit_beta_t(T[n], mass, R0);
   const double f = (double)(m <= n_fft / 2 ? m : m - n_fft) / (double)n_fft;
   const double g = -2.0 * kPi * kPi * beta_t * beta_t * f * f;
   const double h = -2.0 * kPi * fabs(f);
   const ModitBins b = bins[n];
   double sx = 0.0, sy = 0.0;
-  for (int k = 0; k < b.K; ++k) {
-    const double gk = exp(b.lng0 + b.d * k);
-    const R w = (R)exp(g + h * gk);
-    const C v = X[(int64_t)k * n_fft + m];
-    sx += (double)(v.x * w);
-    sy += (double)(v.y * w);
+  for (int k = 0; k < b.K; k += 2) {
+    const C A = X[(int64_t)(k / 2) * n_fft + m];
+    const C Bc = X[(int64_t)(k / 2) * n_fft + mr];   // B = conj(Bc)
+    const double we = exp(g + h * exp(b.lng0 + b.d * k));
+    // (A + B)/2
+    sx += we * 0.5 * ((double)A.x + (double)Bc.x);
+    sy += we * 0.5 * ((double)A.y - (double)Bc.y);
+    if (k + 1 < b.K) {
+      const double wo = exp(g + h * exp(b.lng0 + b.d * (k + 1)));
+      // (A - B)/(2i) = -i (A - B)/2
+      sx += wo * 0.5 * ((double)A.y + (double)Bc.y);
+      sy -= wo * 0.5 * ((double)A.x - (double)Bc.x);
+    }
   }
   C y;
   y.x = (R)sx;
@@ -631,7 +647,7 @@ static hipError_t modit_impl(const ModitArgs& M, hipStream_t st) {
   const int64_t lsd_blocks = ((M.ng << lgG) + 255) / 256 + nblk(M.n_fft - M.ng);
   hipLaunchKernelGGL(k_modit_lsd<R>, dim3((unsigned)lsd_blocks, nl), dim3(256), 0, st, M.cell, M.ng, M.n_fft,
                      lgG, (const R*)M.f, (const P2*)M.rec, M.n_in, M.bins, (C*)M.rows0);
-  void* X = fft_rows<R>(M.rows0, M.rows1, M.n_fft, M.nl * kModitMaxBins, M.bins, st);
+  void* X = fft_rows<R>(M.rows0, M.rows1, M.n_fft, M.nl * kModitRows, M.bins, st);
   void* Y = X == M.rows0 ? M.rows1 : M.rows0;
   hipLaunchKernelGGL(k_modit_product<R>, dim3(nblk(M.n_fft), nl), dim3(256), 0, st, (const C*)X, M.n_fft,
                      M.bins, M.T, M.mass, M.R0, (C*)Y);
