@@ -113,10 +113,11 @@ int reserve_opacity(Workspace& ws, const OpacityPlan& P);
 size_t estimate_workspace(const exo_ctx* c, const exo_atmos* a, const exo_response* r, bool fp64,
                           bool vjp);
 int voigt_launch_profiled(exo_ctx* c, const VoigtArgs& A, bool fp64, bool tan, hipStream_t st);
+// d_T == nullptr: one layer at (T_one, P_one), passed to the kernels by value.
 int species_opacity(exo_ctx* c, Workspace& ws, const Species& sp, const double* d_T,
                     const double* d_P, const double* d_col, int nlay, double amp_scale, bool fp64,
                     bool tangent, const double* d_nu, int64_t ng, void* out, float* out_t,
-                    hipStream_t st);
+                    hipStream_t st, double T_one = 0.0, double P_one = 0.0);
 // MODIT cross-sections (d_col == NULL) or optical depths col_n sigma clamped
 // at zero, of nlay layers, from the lines with nu_lo <= nu_c <= nu_hi.
 int modit_opacity(exo_ctx* c, Workspace& ws, const Species& sp, const double* d_T, const double* d_P,

@@ -153,8 +153,10 @@ struct RespDev {
   int64_t ob, ol;        // output range on the model grid
 };
 
+// T_lay == nullptr: one layer at (T_one, P_one).
 hipError_t launch_line_records(const LinesDev& L, const double* T_lay, const double* P_lay,
-                               const double* col_lay, double amp_scale, int layer0, int nlay,
+                               const double* col_lay, double T_one, double P_one, double amp_scale,
+                               int layer0, int nlay,
                                LineRec* rec, LineRecT* rect, LineCore* core, LineRec64* rec64,
                                hipStream_t st);
 hipError_t launch_voigt(const VoigtArgs& A, bool fp64, bool tangent, hipStream_t st);

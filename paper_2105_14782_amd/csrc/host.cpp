@@ -480,7 +480,7 @@ int exo::reserve_opacity(Workspace& ws, const OpacityPlan& P) {
 int exo::species_opacity(exo_ctx* c, Workspace& ws, const Species& sp, const double* d_T,
                          const double* d_P, const double* d_col, int nlay, double amp_scale,
                          bool fp64, bool tangent, const double* d_nu, int64_t ng, void* out,
-                         float* out_t, hipStream_t st) {
+                         float* out_t, hipStream_t st, double T_one, double P_one) {
   const LinesDev L = lines_dev(sp);
   const OpacityPlan P = plan_opacity(sp.n, nlay, ng, fp64, tangent);
   int rc;
@@ -488,7 +488,7 @@ int exo::species_opacity(exo_ctx* c, Workspace& ws, const Species& sp, const dou
   const int nlc = P.nlc;
   for (int l0 = 0; l0 < nlay; l0 += nlc) {
     const int nl = std::min(nlc, nlay - l0);
-    HIP_TRY(launch_line_records(L, d_T, d_P, d_col, amp_scale, l0, nl,
+    HIP_TRY(launch_line_records(L, d_T, d_P, d_col, T_one, P_one, amp_scale, l0, nl,
                                 fp64 ? nullptr : (LineRec*)ws.rec.p,
                                 (!fp64 && tangent) ? (LineRecT*)ws.rect.p : nullptr,
                                 fp64 ? nullptr : (LineCore*)ws.core.p,
@@ -757,19 +757,14 @@ extern "C" int exo_cross_section(exo_ctx* c, int s, double T, double P, int prec
   hipStream_t st = (hipStream_t)stream;
   std::lock_guard<std::mutex> g(c->mu);
   Workspace& ws = c->ws;
-  int rc;
-  if ((rc = ws.reserve(ws.params, 16 * sizeof(double)))) return rc;
-  double hp[2] = {T, P};
-  double* dp = (double*)ws.params.p;
   const bool fp64 = precision == EXO_FP64;
   // FP32 records carry the amplitude times 2^64 so that the small strengths
   // of single-molecule cross-sections stay far from the FP32 subnormal range.
   const double scale = fp64 ? 1.0 : std::ldexp(1.0, 64);
+  // (T, P) go to the record kernel by value: no staging copy on this path
   return with_ws(ws, st, [&] {
-    int r = ws.stage_params(hp, 2, dp, st);
-    if (r) return r;
-    return species_opacity(c, ws, c->sp[s], dp, dp + 1, nullptr, 1, scale, fp64, false,
-                           (const double*)c->d_nu.p, c->n_nu, sigma, nullptr, st);
+    return species_opacity(c, ws, c->sp[s], nullptr, nullptr, nullptr, 1, scale, fp64, false,
+                           (const double*)c->d_nu.p, c->n_nu, sigma, nullptr, st, T, P);
   });
 }
 

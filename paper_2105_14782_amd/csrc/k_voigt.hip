@@ -9,10 +9,12 @@ namespace exo {
 constexpr double kAmpMax = 1e25;
 
 // grid: x over lines, y over layers of the chunk.  col == nullptr: column
-// factor 1 (single-layer cross-section).
+// factor 1 (single-layer cross-section).  T_lay == nullptr: one layer at
+// (T_one, P_one), passed by value.
 __global__ __launch_bounds__(256) void k_line_records(LinesDev L, const double* __restrict__ T_lay,
                                                       const double* __restrict__ P_lay,
                                                       const double* __restrict__ col_lay,
+                                                      double T_one, double P_one,
                                                       double amp_scale, int layer0,
                                                       LineRec* __restrict__ rec,
                                                       LineRecT* __restrict__ rect,
@@ -22,7 +24,7 @@ __global__ __launch_bounds__(256) void k_line_records(LinesDev L, const double* 
   if (l >= L.n) return;
   const int y = blockIdx.y;
   const int n = layer0 + y;
-  const double T = T_lay[n], P = P_lay[n];
+  const double T = T_lay ? T_lay[n] : T_one, P = T_lay ? P_lay[n] : P_one;
   const double col = col_lay ? col_lay[n] : 1.0;
   const LineState s = line_state(L, l, T, P);
   double A = s.S * col * amp_scale;
@@ -500,12 +502,12 @@ __global__ __launch_bounds__(256) void k_hjert_f64(int64_t n, const double* __re
 // Launchers
 // ---------------------------------------------------------------------------
 hipError_t launch_line_records(const LinesDev& L, const double* T_lay, const double* P_lay,
-                               const double* col_lay, double amp_scale, int layer0, int nlay,
-                               LineRec* rec, LineRecT* rect, LineCore* core, LineRec64* rec64,
-                               hipStream_t st) {
+                               const double* col_lay, double T_one, double P_one, double amp_scale,
+                               int layer0, int nlay, LineRec* rec, LineRecT* rect, LineCore* core,
+                               LineRec64* rec64, hipStream_t st) {
   dim3 grid((unsigned)((L.n + 255) / 256), (unsigned)nlay);
-  hipLaunchKernelGGL(k_line_records, grid, dim3(256), 0, st, L, T_lay, P_lay, col_lay, amp_scale,
-                     layer0, rec, rect, core, rec64);
+  hipLaunchKernelGGL(k_line_records, grid, dim3(256), 0, st, L, T_lay, P_lay, col_lay, T_one, P_one,
+                     amp_scale, layer0, rec, rect, core, rec64);
   return hipGetLastError();
 }
 

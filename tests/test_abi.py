@@ -73,3 +73,45 @@ def test_product_path_does_not_import_oracle():
             if f.endswith((".py", ".cpp", ".hip", ".h")):
                 txt = open(os.path.join(dirpath, f)).read()
                 assert "oracle" not in txt.replace("oracle is the oracle", ""), f
+
+
+def _c_layout(tmp_path, struct, fields):
+    """sizeof and offsetof of a struct of include/exohip.h, from gcc."""
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not found")
+    src = tmp_path / "layout.c"
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "exohip.h"', "int main(void) {",
+             f'  printf("%zu\\n", sizeof({struct}));']
+    lines += [f'  printf("%zu\\n", offsetof({struct}, {f}));' for f in fields]
+    lines += ["  return 0;", "}"]
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", f"-I{os.path.join(ROOT, 'include')}", str(src), "-o", str(exe)],
+                   check=True, capture_output=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()
+    return int(out[0]), [int(v) for v in out[1:]]
+
+
+@pytest.mark.parametrize("struct,ctype", [("exo_atmos", L.ExoAtmos), ("exo_response", L.ExoResponse)])
+def test_ctypes_structs_match_the_header(tmp_path, struct, ctype):
+    """The binding's ctypes mirrors have the C layout field by field."""
+    names = [f[0] for f in ctype._fields_]
+    size, offsets = _c_layout(tmp_path, struct, names)
+    assert ctypes.sizeof(ctype) == size
+    for name, off in zip(names, offsets):
+        assert getattr(ctype, name).offset == off, name
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """One GPU only: --gpus 2 exits with status 2 and a JSON message, before
+    touching a device."""
+    import json
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    msg = json.loads(r.stdout.strip().splitlines()[-1])
+    assert msg["n_gpus"] == 2 and "one GPU" in msg["error"]
