@@ -44,6 +44,7 @@ struct VoigtArgs {
   float2* part;
   float2* part_t;
   double* part64;
+  const float* far_reach2;         // [nlay] squared far-tier reach of each layer (cm^-2)
   unsigned long long* near_pairs;  // profiling only: pairs summed by the near tier
 };
 
@@ -154,11 +155,17 @@ struct RespDev {
 };
 
 // T_lay == nullptr: one layer at (T_one, P_one).
+// g2max_bits (FP32 records only, else nullptr): [nlay] running maximum of
+// gamma^2 over the lines as FP32 bit patterns, raised by atomicMax.
 hipError_t launch_line_records(const LinesDev& L, const double* T_lay, const double* P_lay,
                                const double* col_lay, double T_one, double P_one, double amp_scale,
                                int layer0, int nlay,
                                LineRec* rec, LineRecT* rect, LineCore* core, LineRec64* rec64,
-                               hipStream_t st);
+                               unsigned int* g2max_bits, hipStream_t st);
+// Squared far-tier reach of each layer from its records and g2max_bits,
+// which it resets to zero for the next chunk.
+hipError_t launch_far_reach(const LineRec* rec, int64_t n_lines, int nlay, unsigned int* g2max_bits,
+                            float* reach2, hipStream_t st);
 hipError_t launch_voigt(const VoigtArgs& A, bool fp64, bool tangent, hipStream_t st);
 hipError_t launch_modit(const ModitArgs& M, bool fp64, hipStream_t st);
 hipError_t launch_select_lines(const SelectArgs& A, hipStream_t st);

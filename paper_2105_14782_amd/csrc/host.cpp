@@ -129,6 +129,7 @@ void Workspace::bind_arena(char* base, size_t cap) {
   arena = base;
   arena_cap = cap;
   arena_used = 0;
+  tier_zeroed = nullptr;
 }
 
 int Workspace::begin(hipStream_t st) {
@@ -434,6 +435,7 @@ OpacityPlan exo::plan_opacity(int64_t n_lines, int nlay, int64_t ng, bool fp64, 
   } else {
     P.rec = (size_t)P.nlc * n_lines * sizeof(LineRec);
     P.core = (size_t)P.nlc * n_lines * sizeof(LineCore);
+    P.tier = (size_t)kMaxLayers * (sizeof(unsigned int) + sizeof(float));
     if (tangent) P.rect = (size_t)P.nlc * n_lines * sizeof(LineRecT);
   }
   // partial sums (the FP32 sum always passes its far-line state through
@@ -460,6 +462,7 @@ OpacityPlan exo::plan_opacity_all(const exo_ctx* c, const exo_atmos* a, int64_t 
     P.core = std::max(P.core, Q.core);
     P.rect = std::max(P.rect, Q.rect);
     P.rec64 = std::max(P.rec64, Q.rec64);
+    P.tier = std::max(P.tier, Q.tier);
     P.part = std::max(P.part, Q.part);
     P.part_t = std::max(P.part_t, Q.part_t);
   }
@@ -471,6 +474,7 @@ int exo::reserve_opacity(Workspace& ws, const OpacityPlan& P) {
   if (P.rec64 && (rc = ws.reserve(ws.rec64, P.rec64))) return rc;
   if (P.rec && (rc = ws.reserve(ws.rec, P.rec))) return rc;
   if (P.core && (rc = ws.reserve(ws.core, P.core))) return rc;
+  if (P.tier && (rc = ws.reserve(ws.tier, P.tier))) return rc;
   if (P.rect && (rc = ws.reserve(ws.rect, P.rect))) return rc;
   if (P.part && (rc = ws.reserve(ws.part, P.part))) return rc;
   if (P.part_t && (rc = ws.reserve(ws.part_t, P.part_t))) return rc;
@@ -486,13 +490,21 @@ int exo::species_opacity(exo_ctx* c, Workspace& ws, const Species& sp, const dou
   int rc;
   if ((rc = reserve_opacity(ws, P))) return rc;
   const int nlc = P.nlc;
+  // tier buffer: [kMaxLayers] gamma^2 maximum bits, then [kMaxLayers]
+  // squared reach; k_far_reach zeroes the bits of its chunk after use
+  unsigned int* g2bits = fp64 ? nullptr : (unsigned int*)ws.tier.p;
+  float* reach2 = fp64 ? nullptr : (float*)(g2bits + kMaxLayers);
+  if (!fp64 && ws.tier_zeroed != ws.tier.p)
+    HIP_TRY(hipMemsetAsync(g2bits, 0, (size_t)kMaxLayers * sizeof(unsigned int), st));
+  ws.tier_zeroed = nullptr;
   for (int l0 = 0; l0 < nlay; l0 += nlc) {
     const int nl = std::min(nlc, nlay - l0);
     HIP_TRY(launch_line_records(L, d_T, d_P, d_col, T_one, P_one, amp_scale, l0, nl,
                                 fp64 ? nullptr : (LineRec*)ws.rec.p,
                                 (!fp64 && tangent) ? (LineRecT*)ws.rect.p : nullptr,
                                 fp64 ? nullptr : (LineCore*)ws.core.p,
-                                fp64 ? (LineRec64*)ws.rec64.p : nullptr, st));
+                                fp64 ? (LineRec64*)ws.rec64.p : nullptr, g2bits, st));
+    if (!fp64) HIP_TRY(launch_far_reach((const LineRec*)ws.rec.p, sp.n, nl, g2bits, reach2, st));
     VoigtArgs A{};
     A.nu = d_nu;
     A.ng = ng;
@@ -502,6 +514,7 @@ int exo::species_opacity(exo_ctx* c, Workspace& ws, const Species& sp, const dou
     A.rect = (const LineRecT*)ws.rect.p;
     A.core = (const LineCore*)ws.core.p;
     A.rec64 = (const LineRec64*)ws.rec64.p;
+    A.far_reach2 = reach2;
     A.nlay = nl;
     A.out_scale = (float)(1.0 / amp_scale);
     A.out_scale64 = 1.0 / amp_scale;
@@ -522,6 +535,7 @@ int exo::species_opacity(exo_ctx* c, Workspace& ws, const Species& sp, const dou
     }
     if ((rc = voigt_launch_profiled(c, A, fp64, tangent, st))) return rc;
   }
+  if (!fp64) ws.tier_zeroed = ws.tier.p;
   return EXO_OK;
 }
 
@@ -968,7 +982,7 @@ size_t exo::estimate_workspace(const exo_ctx* c, const exo_atmos* a, const exo_r
     t += mb;
   } else {
     const OpacityPlan P = plan_opacity_all(c, a, gl, fp64, vjp);
-    for (size_t b : {P.rec, P.core, P.rect, P.rec64, P.part, P.part_t}) t += b ? R(b) : 0;
+    for (size_t b : {P.rec, P.core, P.rect, P.rec64, P.part, P.part_t, P.tier}) t += b ? R(b) : 0;
   }
   int64_t nmid = 0;
   if (r) {

@@ -10,7 +10,8 @@ constexpr double kAmpMax = 1e25;
 
 // grid: x over lines, y over layers of the chunk.  col == nullptr: column
 // factor 1 (single-layer cross-section).  T_lay == nullptr: one layer at
-// (T_one, P_one), passed by value.
+// (T_one, P_one), passed by value.  FP32 records also raise g2max_bits[y] to
+// the layer's largest gamma^2 (one atomic per wave).
 __global__ __launch_bounds__(256) void k_line_records(LinesDev L, const double* __restrict__ T_lay,
                                                       const double* __restrict__ P_lay,
                                                       const double* __restrict__ col_lay,
@@ -19,35 +20,48 @@ __global__ __launch_bounds__(256) void k_line_records(LinesDev L, const double* 
                                                       LineRec* __restrict__ rec,
                                                       LineRecT* __restrict__ rect,
                                                       LineCore* __restrict__ core,
-                                                      LineRec64* __restrict__ rec64) {
+                                                      LineRec64* __restrict__ rec64,
+                                                      unsigned int* __restrict__ g2max_bits) {
   const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (l >= L.n) return;
+  const bool in = l < L.n;
   const int y = blockIdx.y;
   const int n = layer0 + y;
   const double T = T_lay ? T_lay[n] : T_one, P = T_lay ? P_lay[n] : P_one;
   const double col = col_lay ? col_lay[n] : 1.0;
-  const LineState s = line_state(L, l, T, P);
-  double A = s.S * col * amp_scale;
-  double dlnA = s.dlnS;
   const int64_t o = (int64_t)y * L.n + l;
   if (rec64) {
+    if (!in) return;
+    const LineState s = line_state(L, l, T, P);
     LineRec64 r;
-    r.A = A;
+    r.A = s.S * col * amp_scale;
     r.beta = s.beta;
     r.gam = s.gam;
     r.erfcxa = erfcx(s.gam / (kSqrt2 * s.beta));
     rec64[o] = r;
     return;
   }
-  // FP32 range guard: an amplitude above kAmpMax makes every grid point of
-  // the window optically thick (dtau >> 700, T = 0) whether or not it is
-  // clipped, so clipping it changes no flux; it keeps FP32 sums finite.
-  if (A > kAmpMax) {
-    A = kAmpMax;
-    dlnA = 0.0;
+  float g2 = 0.f;
+  if (in) {
+    const LineState s = line_state(L, l, T, P);
+    double A = s.S * col * amp_scale;
+    double dlnA = s.dlnS;
+    // FP32 range guard: an amplitude above kAmpMax makes every grid point of
+    // the window optically thick (dtau >> 700, T = 0) whether or not it is
+    // clipped, so clipping it changes no flux; it keeps FP32 sums finite.
+    if (A > kAmpMax) {
+      A = kAmpMax;
+      dlnA = 0.0;
+    }
+    make_line_record(A, s.beta, s.gam, T, dlnA, s.dbeta, s.dgam, rec + o, rect ? rect + o : nullptr,
+                     core + o);
+    g2 = (float)(s.gam * s.gam);
   }
-  make_line_record(A, s.beta, s.gam, T, dlnA, s.dbeta, s.dgam, rec + o, rect ? rect + o : nullptr,
-                   core + o);
+  if (g2max_bits) {
+    // every lane of the wave takes part (none has returned on this path)
+#pragma unroll
+    for (int k = 32; k > 0; k >>= 1) g2 = fmaxf(g2, __shfl_xor(g2, k, 64));
+    if ((threadIdx.x & 63) == 0) atomicMax(g2max_bits + y, __float_as_uint(g2));
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -65,21 +79,83 @@ __global__ __launch_bounds__(256) void k_line_records(LinesDev L, const double* 
 constexpr int kChunk = 32;
 
 // ---------------------------------------------------------------------------
-// Far tier.  In the asymptotic branch the contribution is r P(r) with
-// r = 1/D and the degree-6 polynomial of make_line_record, whose k-th term is
-// of order (beta^2 r)^ceil(k/2) relative to 1 (gamma^2 r <= 1).  Where
-// beta^2 r <= kFarU, the terms after r^2 change the sum by at most 8e-9
-// relative and the tangent terms after r^3 by at most 4e-8 of the tangent's
-// scale: below FP32 rounding.  Those pairs drop the higher terms and the core
-// test.
+// Far tier.  In the asymptotic branch the contribution is E0 r sum_k c_k r^k
+// (make_line_record) with r = 1/D, D = dnu^2 + gamma^2.  With u = beta^2 r
+// and v = gamma^2 r, c_k r^k is a homogeneous polynomial of degree k in
+// (u, v): 1, 3u, 15u^2 - 4uv, 105u^3 - 60u^2 v, 48u^2 v^2 - 840u^3 v,
+// 1680u^3 v^2, -960u^3 v^3.  A far pair keeps k <= 2 of the value and k <= 3
+// of the tangent, and skips the core test.
+//
+// A line farther than `reach` from every grid point of a wave has, at each
+// of them, D >= reach^2 + gamma^2, so every monomial obeys
+//   u^p v^q <= U^p max_{g <= g_max} (g/R)^q / (1 + g/R)^(p+q),   R = reach^2,
+// U = beta_max^2 / R, g_max = the layer's largest gamma^2; the maximum sits
+// at g/R = min(g_max/R, q/p).  Summing these bounds over the dropped terms
+// bounds the dropped value relative to E0 r, and the dropped tangent relative
+// to E0 r (|d ln E0| + |d ln beta^2| + |d ln gamma^2|) (k-th derivative
+// terms are at most k times the term, and d/dT of r adds a factor (k+1) v).
+// k_far_reach picks, per layer, the smallest R (bisection in ln R) at which
+// the two bounds stay below kFarEpsV and kFarEpsT: the largest values the
+// same bounds take for U = 2e-5 at any g_max, so no layer is treated more
+// loosely than with that fixed U, and R never exceeds beta_max^2 / 2e-5.
+// Layers with narrow lines (low pressure) get a reach several times smaller.
+// R >= 2 * 111 beta_max^2 keeps every far pair out of the core branch.
 //
 // The Doppler width is proportional to the line centre (Eq. thermal) and the
 // lines are sorted by centre, so the last line of a layer has the largest
-// beta^2.  Every line farther than reach = sqrt(beta_max^2 / kFarU) from all
-// grid points a wave owns satisfies the bound at all of them, and these lines
-// are a prefix and a suffix of the sorted list, found by binary search.
+// beta^2.  The far lines of a wave are a prefix and a suffix of the sorted
+// list, found by binary search.
 // ---------------------------------------------------------------------------
 constexpr double kFarU = 2e-5;
+constexpr double kFarEpsV = 4.8e-9;
+constexpr double kFarEpsT = 1.42e-8;
+
+// bound of u^p v^q over the far pairs of a layer (gr = g_max / R)
+__device__ inline double far_monomial(int p, int q, double U, double gr) {
+  double m = 1.0;
+  for (int i = 0; i < p; ++i) m *= U;
+  if (q == 0) return m;
+  const double t = fmin(gr, (double)q / (double)p);
+  for (int i = 0; i < q; ++i) m *= t;
+  for (int i = 0; i < p + q; ++i) m /= 1.0 + t;
+  return m;
+}
+
+__device__ inline bool far_bound_holds(double U, double gr) {
+  auto M = [&](int p, int q) { return far_monomial(p, q, U, gr); };
+  // A_k: sum of |coefficient| x monomial bound of c_k r^k; Av_k: the same times v
+  const double A3 = 105.0 * M(3, 0) + 60.0 * M(2, 1), A4 = 48.0 * M(2, 2) + 840.0 * M(3, 1);
+  const double A5 = 1680.0 * M(3, 2), A6 = 960.0 * M(3, 3);
+  const double Av3 = 105.0 * M(3, 1) + 60.0 * M(2, 2), Av4 = 48.0 * M(2, 3) + 840.0 * M(3, 2);
+  const double Av5 = 1680.0 * M(3, 3), Av6 = 960.0 * M(3, 4);
+  const double ev = A3 + A4 + A5 + A6;
+  const double et = 4.0 * A4 + 5.0 * A5 + 6.0 * A6 + 4.0 * Av3 + 5.0 * Av4 + 6.0 * Av5 + 7.0 * Av6;
+  return ev <= kFarEpsV && et <= kFarEpsT;
+}
+
+// One thread per layer of the chunk.
+__global__ __launch_bounds__(64) void k_far_reach(const LineRec* __restrict__ rec, int64_t n_lines,
+                                                  int nlay, unsigned int* __restrict__ g2max_bits,
+                                                  float* __restrict__ reach2) {
+  const int y = blockIdx.x * 64 + threadIdx.x;
+  if (y >= nlay) return;
+  // beta_max^2 from the threshold 2 * 111 beta^2, with margin for its rounding
+  const double bmax = (double)rec[(int64_t)y * n_lines + n_lines - 1].thr * (1.001 / (2.0 * kHjertSwitch));
+  const unsigned int bits = g2max_bits[y];
+  g2max_bits[y] = 0u;
+  double lo = log(2.0 * kHjertSwitch * bmax), hi = log(bmax / kFarU);
+  // an unknown maximum (not a finite non-negative float) keeps the fixed-U reach
+  if (bits <= 0x7f7fffffu && lo < hi) {
+    const double gmax = (double)__uint_as_float(bits) * 1.001;
+    for (int it = 0; it < 32; ++it) {
+      const double mid = 0.5 * (lo + hi), R = exp(mid);
+      if (far_bound_holds(bmax / R, gmax / R)) hi = mid;
+      else lo = mid;
+    }
+  }
+  // rounded up so that the FP32 value does not undercut the bound
+  reach2[y] = (float)(exp(hi) * (1.0 + 1e-6));
+}
 
 // first index i in [lo, hi) with a[i] >= v (strict: a[i] > v); hi if none
 template <bool STRICT>
@@ -139,14 +215,11 @@ __device__ __forceinline__ void load_points(const VoigtArgs& A, int64_t tile0, i
 
 // Near lines [i0, i1) of wave w within [lb, le); the rest of [lb, le) is far.
 template <int G>
-__device__ __forceinline__ void near_range(const VoigtArgs& A, const LineRec* __restrict__ R,
-                                           int64_t tile0, int w, int lb, int le, int& i0, int& i1) {
+__device__ __forceinline__ void near_range(const VoigtArgs& A, int64_t tile0, int w, int lb, int le, int& i0, int& i1) {
   const int64_t jw = tile0 + (int64_t)w * G * 64, jlast = A.ng - 1;
   const double lo = A.nu[jw < jlast ? jw : jlast];
   const double hi = A.nu[jw + G * 64 - 1 < jlast ? jw + G * 64 - 1 : jlast];
-  // beta_max^2 from the threshold 2 * 111 beta^2, with margin for its rounding
-  const double bmax = (double)R[A.n_lines - 1].thr * (1.001 / (2.0 * kHjertSwitch));
-  const double reach = sqrt(bmax / kFarU);
+  const double reach = sqrt((double)A.far_reach2[blockIdx.y]);
   i0 = __builtin_amdgcn_readfirstlane(search_sorted<false>(A.nu_c, lb, le, lo - reach));
   i1 = __builtin_amdgcn_readfirstlane(search_sorted<true>(A.nu_c, i0, le, hi + reach));
 }
@@ -343,7 +416,7 @@ __device__ __forceinline__ void voigt_body(const VoigtArgs& A) {
   const LineRecT* __restrict__ RT = TAN ? A.rect + (int64_t)y * A.n_lines : nullptr;
   const LineCore* __restrict__ RC = A.core + (int64_t)y * A.n_lines;
   int i0, i1;
-  near_range<G>(A, R, tile0, w, lb, le, i0, i1);
+  near_range<G>(A, tile0, w, lb, le, i0, i1);
   // base of the far tier's FP32 offsets: the wave's first point (uniform)
   const int64_t jw = tile0 + (int64_t)w * G * 64;
   const double nuw = A.nu[jw < A.ng ? jw : A.ng - 1];
@@ -504,10 +577,17 @@ __global__ __launch_bounds__(256) void k_hjert_f64(int64_t n, const double* __re
 hipError_t launch_line_records(const LinesDev& L, const double* T_lay, const double* P_lay,
                                const double* col_lay, double T_one, double P_one, double amp_scale,
                                int layer0, int nlay, LineRec* rec, LineRecT* rect, LineCore* core,
-                               LineRec64* rec64, hipStream_t st) {
+                               LineRec64* rec64, unsigned int* g2max_bits, hipStream_t st) {
   dim3 grid((unsigned)((L.n + 255) / 256), (unsigned)nlay);
   hipLaunchKernelGGL(k_line_records, grid, dim3(256), 0, st, L, T_lay, P_lay, col_lay, T_one, P_one,
-                     amp_scale, layer0, rec, rect, core, rec64);
+                     amp_scale, layer0, rec, rect, core, rec64, rec64 ? nullptr : g2max_bits);
+  return hipGetLastError();
+}
+
+hipError_t launch_far_reach(const LineRec* rec, int64_t n_lines, int nlay, unsigned int* g2max_bits,
+                            float* reach2, hipStream_t st) {
+  hipLaunchKernelGGL(k_far_reach, dim3((unsigned)((nlay + 63) / 64)), dim3(64), 0, st, rec, n_lines, nlay,
+                     g2max_bits, reach2);
   return hipGetLastError();
 }
 

@@ -1,0 +1,29 @@
+"""CPU checks of the far-tier truncation rule (no GPU)."""
+import numpy as np
+
+from far_tier import far_reach2
+
+
+def test_far_reach_bound_covers_truncation():
+    """Host-side check of the far-tier rule: at the reach it picks, dropping the
+    wing terms beyond r^3 (value) and r^4 (tangent) changes no far pair by more
+    than the stated bounds (dense scan over gamma^2 <= g_max, dnu^2 >= R)."""
+    for bmax, gmax in [(1e-4, 0.0), (1e-4, 1e-8), (1e-4, 1e-4), (1e-4, 1e-2), (1e-4, 1.0), (1e-4, 100.0)]:
+        R = far_reach2(bmax, gmax)
+        assert 222.0 * bmax <= R <= bmax / 2e-5 * (1 + 1e-5)
+        g = np.concatenate([[0.0], gmax * np.logspace(-6, 0, 200)])[:, None]
+        D = R * np.logspace(0, 3, 300)[None, :] + g
+        r, b = 1.0 / D, bmax
+        c = [np.ones_like(D), 3 * b + 0 * g, 15 * b * b - 4 * b * g, 105 * b ** 3 - 60 * b * b * g,
+             48 * b * b * g * g - 840 * b ** 3 * g, 1680 * b ** 3 * g * g, -960 * b ** 3 * g ** 3]
+        dropped = sum(c[k] * r ** k for k in range(3, 7))
+        assert np.max(np.abs(dropped)) <= 4.8e-9
+        # tangent: derivatives along b and g with unit log-steps (scale 1 per log-derivative)
+        dcb = [0 * D, 3 * b + 0 * g, 30 * b * b - 4 * b * g, 315 * b ** 3 - 120 * b * b * g,
+               96 * b * b * g * g - 2520 * b ** 3 * g, 5040 * b ** 3 * g * g, -2880 * b ** 3 * g ** 3]
+        dcg = [0 * D, 0 * D, -4 * b * g, -60 * b * b * g, 96 * b * b * g * g - 840 * b ** 3 * g,
+               3360 * b ** 3 * g * g, -2880 * b ** 3 * g ** 3]
+        tb = sum(dcb[k] * r ** k for k in range(4, 7))
+        tg = sum(dcg[k] * r ** k for k in range(4, 7)) - sum((k + 1) * c[k] * r ** k * (g * r) for k in range(3, 7))
+        tE = sum(c[k] * r ** k for k in range(4, 7))
+        assert np.max(np.abs(tb) + np.abs(tg) + np.abs(tE)) <= 1.42e-8 * 3

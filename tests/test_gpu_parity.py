@@ -15,6 +15,7 @@ import torch
 
 import synth
 from oracle import oracle as O
+from far_tier import far_reach2
 
 pytestmark = pytest.mark.gpu
 
@@ -176,12 +177,16 @@ def test_cross_section_far_lines_only(exo):
         assert err < 2e-6
 
 
-def _near_pairs_expected(ll, T, nu, wave_points=256):
-    """Pairs the near tier should take: lines within reach of the points a wave owns."""
+def _near_pairs_expected(ll, T, nu, wave_points=256, P=1.0):
+    """Pairs the near tier should take: lines within the layer's far reach of
+    the points a wave owns."""
     kKB, kMU, kC = 1.380649e-16, 1.66053906660e-24, 2.99792458e10
     beta_last = math.sqrt(kKB * T / (ll.mass_amu * kMU)) * ll.nu_c[-1] / kC
     thr = float(np.float32(2.0 * 111.0 * beta_last * beta_last))
-    reach = math.sqrt(thr * (1.001 / 222.0) / 2e-5)
+    bmax = thr * (1.001 / 222.0)
+    gam = ll.alpha_ref * (T / 296.0) ** (-ll.n_texp) * P
+    gmax = float(np.max((gam * gam).astype(np.float32))) * 1.001
+    reach = math.sqrt(far_reach2(bmax, gmax))
     total = 0
     for j0 in range(0, nu.size, wave_points):
         j1 = min(j0 + wave_points, nu.size) - 1
