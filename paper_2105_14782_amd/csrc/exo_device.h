@@ -175,39 +175,66 @@ __device__ inline void make_line_record(double A, double beta, double gam, doubl
 // and C1 = sum_n w_n,
 //   S1 = e^{-x^2} C1,  S2 + S3 = e^{-x^2} sum_n w_n (X^n + X^-n),
 //   S5 - S4 = e^{-x^2} sum_n (eta n) w_n (X^n - X^-n).
-// X^n + X^-n and X^n - X^-n obey u_{n+1} = (X + 1/X) u_n - u_{n-1}, one FMA
-// per term in FP64, where e^{-x^2} X^27 (x^2 + a^2 < 111) stays in range.
+// c_n = X^n + X^-n obeys c_{n+1} = (X + 1/X) c_n - c_{n-1}, one FMA per term
+// in FP64, where e^{-x^2} X^27 (x^2 + a^2 < 111) stays in range; its
+// x-derivative e_n = n (X^n - X^-n) obeys the derivative of that recurrence,
+// e_{n+1} = (X + 1/X) e_n + (X - 1/X) c_n - e_{n-1}, so that
+// S5 - S4 = e^{-x^2} eta sum_n w_n e_n needs no multiplication by eta n.
 // sin 2ax and cos 2ax come from sin ax, cos ax by the double-angle formulas.
 // Same terms and same M as the series; only the order of operations differs.
 // ---------------------------------------------------------------------------
+// e^t for the core branch's arguments (|t| <= 112, far from over- and
+// underflow): t = k ln2 + r with |r| <= ln2/2 (Cody-Waite reduction with a
+// two-part ln2), e^r by its Taylor series to r^9 (truncation below 1.1e-11
+// relative), times 2^k.
+__device__ __forceinline__ double exp_core(double t) {
+  constexpr double kLog2e = 1.4426950408889634, kLn2Hi = 0.6931471805599453, kLn2Lo = 2.3190468138462996e-17;
+  const double k = rint(t * kLog2e);
+  double r = fma(-k, kLn2Hi, t);
+  r = fma(-k, kLn2Lo, r);
+  double p = 1.0 / 362880.0;
+  p = fma(p, r, 1.0 / 40320.0);
+  p = fma(p, r, 1.0 / 5040.0);
+  p = fma(p, r, 1.0 / 720.0);
+  p = fma(p, r, 1.0 / 120.0);
+  p = fma(p, r, 1.0 / 24.0);
+  p = fma(p, r, 1.0 / 6.0);
+  p = fma(p, r, 0.5);
+  p = fma(p, r, 1.0);
+  p = fma(p, r, 1.0);
+  return ldexp(p, (int)k);
+}
+
 template <bool WANT_L, typename WeightPtr>
 __device__ __forceinline__ float hjert_core_fac(float xf, float af, float ainv, float erfcxa, float C1,
                                                 WeightPtr wn, float* Lout) {
   constexpr double twoeta_pi = 1.0 / kPi;  // 2 eta / pi
   const double x = (double)xf;
-  const double ex2 = exp(-x * x);
-  const double X = exp(x);
+  const double ex2 = exp_core(-x * x);
+  const double X = exp_core(x);
   // 1/X: hardware reciprocal and two Newton steps (X lies in [e^-10.6, e^10.6])
   double Y = __builtin_amdgcn_rcp(X);
   Y = fma(Y, fma(-X, Y, 1.0), Y);
   Y = fma(Y, fma(-X, Y, 1.0), Y);
-  const double k = X + Y;
-  double c0 = 2.0, c1 = k, d0 = 0.0, d1 = X - Y, sc = 0.0, sd = 0.0;
+  const double k = X + Y, kp = X - Y;
+  // c_n = X^n + X^-n and e_n = n (X^n - X^-n) = dc_n/dx
+  double c0 = 2.0, c1 = k, e0 = 0.0, e1 = kp, sc = 0.0, se = 0.0;
   constexpr int kUnroll = WANT_L ? 9 : 3;
 #pragma unroll kUnroll
   for (int n = 1; n <= kM916; ++n) {
     const double w = wn[n - 1];
     sc = fma(w, c1, sc);
+    if (WANT_L) {
+      se = fma(w, e1, se);
+      const double e2 = fma(k, e1, fma(kp, c1, -e0));
+      e0 = e1;
+      e1 = e2;
+    }
     const double c2 = fma(k, c1, -c0);
     c0 = c1;
     c1 = c2;
-    if (WANT_L) {
-      sd = fma(w * (0.5 * n), d1, sd);
-      const double d2 = fma(k, d1, -d0);
-      d0 = d1;
-      d1 = d2;
-    }
   }
+  const double sd = 0.5 * se;  // sum_n (eta n) w_n (X^n - X^-n)
   const double a = (double)af, S1 = ex2 * (double)C1;
   const float ax = af * xf;
   float sax, cax;
