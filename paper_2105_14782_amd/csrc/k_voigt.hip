@@ -94,7 +94,7 @@ constexpr int kChunk = 32;
 // bounds the dropped value relative to E0 r, and the dropped tangent relative
 // to E0 r (|d ln E0| + |d ln beta^2| + |d ln gamma^2|) (k-th derivative
 // terms are at most k times the term, and d/dT of r adds a factor (k+1) v).
-// k_far_reach picks, per layer, the smallest R (bisection in ln R) at which
+// k_far_reach picks, per layer, the smallest R (a search in ln R) at which
 // the two bounds stay below kFarEpsV and kFarEpsT: the largest values the
 // same bounds take for U = 2e-5 at any g_max, so no layer is treated more
 // loosely than with that fixed U, and R never exceeds beta_max^2 / 2e-5.
@@ -116,9 +116,10 @@ __device__ inline double far_monomial(int p, int q, double U, double gr) {
   for (int i = 0; i < p; ++i) m *= U;
   if (q == 0) return m;
   const double t = fmin(gr, (double)q / (double)p);
+  double den = 1.0;
   for (int i = 0; i < q; ++i) m *= t;
-  for (int i = 0; i < p + q; ++i) m /= 1.0 + t;
-  return m;
+  for (int i = 0; i < p + q; ++i) den *= 1.0 + t;
+  return m / den;
 }
 
 __device__ inline bool far_bound_holds(double U, double gr) {
@@ -133,28 +134,41 @@ __device__ inline bool far_bound_holds(double U, double gr) {
   return ev <= kFarEpsV && et <= kFarEpsT;
 }
 
-// One thread per layer of the chunk.
+// One 64-lane block per layer of the chunk: a two-level search on ln R,
+// 64 candidates per level, each lane testing one (the bound is monotone in R,
+// so the first candidate that holds is the smallest); the result lies within
+// ln(225)/4096 of the smallest R, rounded upwards.
 __global__ __launch_bounds__(64) void k_far_reach(const LineRec* __restrict__ rec, int64_t n_lines,
-                                                  int nlay, unsigned int* __restrict__ g2max_bits,
+                                                  unsigned int* __restrict__ g2max_bits,
                                                   float* __restrict__ reach2) {
-  const int y = blockIdx.x * 64 + threadIdx.x;
-  if (y >= nlay) return;
+  const int y = blockIdx.x, k = threadIdx.x;
   // beta_max^2 from the threshold 2 * 111 beta^2, with margin for its rounding
   const double bmax = (double)rec[(int64_t)y * n_lines + n_lines - 1].thr * (1.001 / (2.0 * kHjertSwitch));
   const unsigned int bits = g2max_bits[y];
-  g2max_bits[y] = 0u;
-  double lo = log(2.0 * kHjertSwitch * bmax), hi = log(bmax / kFarU);
+  __syncthreads();  // every lane has read the maximum before lane 0 clears it
+  const double lo = log(2.0 * kHjertSwitch * bmax), hi = log(bmax / kFarU);
+  double x = hi;
   // an unknown maximum (not a finite non-negative float) keeps the fixed-U reach
   if (bits <= 0x7f7fffffu && lo < hi) {
     const double gmax = (double)__uint_as_float(bits) * 1.001;
-    for (int it = 0; it < 32; ++it) {
-      const double mid = 0.5 * (lo + hi), R = exp(mid);
-      if (far_bound_holds(bmax / R, gmax / R)) hi = mid;
-      else lo = mid;
+    double a = lo, b = hi;
+    for (int level = 0; level < 2; ++level) {
+      const double xk = a + (b - a) * (double)(k + 1) * (1.0 / 64.0);
+      const double R = exp(xk);
+      const unsigned long long ok = __ballot(far_bound_holds(bmax / R, gmax / R));
+      if (ok == 0ull) break;  // not even b holds: keep the previous upper end
+      const int k1 = __builtin_ctzll(ok);
+      const double bn = a + (b - a) * (double)(k1 + 1) * (1.0 / 64.0);
+      a = k1 == 0 ? a : a + (b - a) * (double)k1 * (1.0 / 64.0);
+      b = bn;
+      x = b;
     }
   }
-  // rounded up so that the FP32 value does not undercut the bound
-  reach2[y] = (float)(exp(hi) * (1.0 + 1e-6));
+  if (k == 0) {
+    g2max_bits[y] = 0u;
+    // rounded up so that the FP32 value does not undercut the bound
+    reach2[y] = (float)(exp(x) * (1.0 + 1e-6));
+  }
 }
 
 // first index i in [lo, hi) with a[i] >= v (strict: a[i] > v); hi if none
@@ -587,8 +601,7 @@ hipError_t launch_line_records(const LinesDev& L, const double* T_lay, const dou
 
 hipError_t launch_far_reach(const LineRec* rec, int64_t n_lines, int nlay, unsigned int* g2max_bits,
                             float* reach2, hipStream_t st) {
-  hipLaunchKernelGGL(k_far_reach, dim3((unsigned)((nlay + 63) / 64)), dim3(64), 0, st, rec, n_lines, nlay,
-                     g2max_bits, reach2);
+  hipLaunchKernelGGL(k_far_reach, dim3((unsigned)nlay), dim3(64), 0, st, rec, n_lines, g2max_bits, reach2);
   return hipGetLastError();
 }
 

@@ -20,9 +20,10 @@ def far_monomial(p, q, U, gr):
 
 def far_reach2(bmax, gmax):
     """Squared far-tier reach of a layer: the smallest R in [222 b, b / 2e-5]
-    (bisection in ln R) at which the bounds of the dropped wing terms, with
+    at which the bounds of the dropped wing terms, with
     u^p v^q <= U^p max_g (g/R)^q / (1 + g/R)^(p+q), stay within the largest
-    values they take at U = 2e-5."""
+    values they take at U = 2e-5; found by a two-level search on ln R with 64
+    candidates per level (the first candidate that holds)."""
     def holds(U, gr):
         M = lambda p, q: far_monomial(p, q, U, gr)
         A3, A4 = 105 * M(3, 0) + 60 * M(2, 1), 48 * M(2, 2) + 840 * M(3, 1)
@@ -33,11 +34,14 @@ def far_reach2(bmax, gmax):
         et = 4 * A4 + 5 * A5 + 6 * A6 + 4 * Av3 + 5 * Av4 + 6 * Av5 + 7 * Av6
         return ev <= 4.8e-9 and et <= 1.42e-8
     lo, hi = math.log(222.0 * bmax), math.log(bmax / 2e-5)
-    for _ in range(32):
-        mid = 0.5 * (lo + hi)
-        R = math.exp(mid)
-        if holds(bmax / R, gmax / R):
-            hi = mid
-        else:
-            lo = mid
-    return float(np.float32(math.exp(hi) * (1.0 + 1e-6)))
+    a, b, x = lo, hi, hi
+    for _ in range(2):
+        ok = [holds(bmax / math.exp(a + (b - a) * (k + 1) * (1.0 / 64.0)),
+                    gmax / math.exp(a + (b - a) * (k + 1) * (1.0 / 64.0))) for k in range(64)]
+        if not any(ok):
+            break
+        k1 = ok.index(True)
+        bn = a + (b - a) * (k1 + 1) * (1.0 / 64.0)
+        a = a if k1 == 0 else a + (b - a) * k1 * (1.0 / 64.0)
+        b = x = bn
+    return float(np.float32(math.exp(x) * (1.0 + 1e-6)))
