@@ -246,45 +246,70 @@ __device__ __forceinline__ void near_range(const VoigtArgs& A, int64_t tile0, in
 // reciprocal serves two points: r0 = D1 / (D0 D1), r1 = D0 / (D0 D1) (D >= the
 // squared reach, so the product stays a normal FP32 number for any physical
 // width).
+//
+// Each chunk's line data pass through a slice of LDS private to the wave:
+// lanes 0..31 load the value coefficients and gamma^2 and form the lines'
+// offsets nu_l - nu_w (one FP64 subtraction for 32 lines), lanes 32..63 load
+// the tangent coefficients, all with vector loads; the line loop reads them
+// back as wave-uniform LDS broadcasts into vector registers.  Per-line scalar
+// loads of the same records were slower (their latency stalled the loop), and
+// coefficients in vector registers need no copies to get round the one-scalar
+// operand limit of a VALU instruction.  The stage needs no workgroup barrier:
+// LDS operations of one wave complete in order.
+struct FarStage {
+  float4 eg[kChunk];  // e0, e1, e2, gamma^2
+  float4 t[kChunk];   // tangent t0..t3
+  float dl[kChunk];   // (float)(nu_l - nu_w)
+};
+// Orders one wave's LDS writes before its later reads of another lane's
+// data, and its reads before later overwrites.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 template <bool TAN, int G>
 __device__ __forceinline__ void far_lines(int sb, int se, const LineRec* __restrict__ R,
                                           const LineRecT* __restrict__ RT,
                                           const double* __restrict__ nuc, const double (&nuj)[G], double nuw,
+                                          FarStage* __restrict__ st, int lane,
                                           float (&s)[G], float (&c)[G], float (&ts)[G],
                                           float (&tc)[G]) {
   static_assert(G % 2 == 0, "points go in pairs");
   float dj[G];
 #pragma unroll
   for (int g = 0; g < G; ++g) dj[g] = (float)(nuj[g] - nuw);
+  const int half = lane & 31;
   for (int l0 = sb; l0 < se; l0 += kChunk) {
     const int l1 = min(l0 + kChunk, se);
+    // stage the chunk
+    const int li = l0 + half;
+    if (li < l1) {
+      if (lane < 32) {
+        const float4 e = *reinterpret_cast<const float4*>(R[li].e);
+        st->eg[half] = make_float4(e.x, e.y, e.z, R[li].gam2);
+        st->dl[half] = (float)(nuc[li] - nuw);
+      } else if (TAN) {
+        st->t[half] = *reinterpret_cast<const float4*>(RT[li].t);
+      }
+    }
+    wave_lds_sync();
     float blk[G], tblk[G];
 #pragma unroll
     for (int g = 0; g < G; ++g) blk[g] = tblk[g] = 0.f;
-    // the next line's record is requested one iteration ahead so that the
-    // scalar-load latency overlaps the current line's arithmetic
-    float4 en = *reinterpret_cast<const float4*>(R[l0].e);
-    float g2n = R[l0].gam2;
-    double nun = nuc[l0];
-    float4 tn;
-    if (TAN) tn = *reinterpret_cast<const float4*>(RT[l0].t);
+    const int n = l1 - l0;
 #pragma unroll 2
-    for (int l = l0; l < l1; ++l) {
-      const float4 e = en;
-      const float g2 = g2n;
-      const float dl = (float)(nun - nuw);
+    for (int i = 0; i < n; ++i) {
+      const float4 e = st->eg[i];
+      const float dl = st->dl[i];
       float4 t;
-      if (TAN) t = tn;
-      const int ln = l + 1 < l1 ? l + 1 : l;
-      en = *reinterpret_cast<const float4*>(R[ln].e);
-      g2n = R[ln].gam2;
-      nun = nuc[ln];
-      if (TAN) tn = *reinterpret_cast<const float4*>(RT[ln].t);
+      if (TAN) t = st->t[i];
       float D[G], r[G];
 #pragma unroll
       for (int g = 0; g < G; ++g) {
         const float d = dj[g] - dl;
-        D[g] = fmaf(d, d, g2);
+        D[g] = fmaf(d, d, e.w);
       }
 #pragma unroll
       for (int g = 0; g < G; g += 2) {
@@ -307,6 +332,8 @@ __device__ __forceinline__ void far_lines(int sb, int se, const LineRec* __restr
       neumaier(s[g], c[g], blk[g]);
       if (TAN) neumaier(ts[g], tc[g], tblk[g]);
     }
+    // the next chunk overwrites the stage only after these reads
+    wave_lds_sync();
   }
 }
 
@@ -420,6 +447,7 @@ __device__ __forceinline__ void voigt_body(const VoigtArgs& A) {
   const int y = blockIdx.y;
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  __shared__ FarStage stage[4];
   const int64_t tile0 = (int64_t)blockIdx.x * (256 * G);
   double nuj[G];
   load_points<G>(A, tile0, w, lane, nuj);
@@ -442,7 +470,7 @@ __device__ __forceinline__ void voigt_body(const VoigtArgs& A) {
   for (int seg = 0; seg < 2; ++seg) {
     const int sb = seg == 0 ? lb : i1;
     const int se = seg == 0 ? i0 : le;
-    far_lines<TAN, G>(sb, se, R, RT, A.nu_c, nuj, nuw, s, c, ts, tc);
+    far_lines<TAN, G>(sb, se, R, RT, A.nu_c, nuj, nuw, &stage[w], lane, s, c, ts, tc);
     if (seg == 0) near_lines<TAN, G>(i0, i1, R, RT, RC, A.nu_c, nuj, s, c, ts, tc);
   }
   if (A.near_pairs && lane == 0) {
