@@ -69,12 +69,12 @@ __global__ __launch_bounds__(256) void k_line_records(LinesDev L, const double* 
 //
 // Block = 256 threads = 4 waves; thread (wave w, lane) owns grid points
 // j = tile0 + (w*G + g)*64 + lane, g < G.  All lanes walk the same line
-// sequence, so line records are wave-uniform (scalar loads).  The offset
-// nu_j - nu_l is one FP64 subtraction per pair, rounded once to FP32: an
-// FP32 offset would carry an absolute error of ulp(nu) ~ 5e-4 cm^-1, a few
-// percent of a Doppler width.  Contributions of a block of
-// kChunk lines are summed in plain FP32, and every block sum enters a
-// Neumaier-compensated accumulator.
+// sequence, so line records are wave-uniform (LDS broadcasts in the far
+// tier, scalar loads in the near tier).  A near pair's offset nu_j - nu_l is
+// one FP64 subtraction, rounded once to FP32: an FP32 offset would carry an
+// absolute error of ulp(nu) ~ 5e-4 cm^-1, a few percent of a Doppler width.
+// Contributions of a block of lines (64 far, kChunk near) are summed in plain
+// FP32, and every block sum enters a Neumaier-compensated accumulator.
 // ---------------------------------------------------------------------------
 constexpr int kChunk = 32;
 
@@ -247,19 +247,21 @@ __device__ __forceinline__ void near_range(const VoigtArgs& A, int64_t tile0, in
 // squared reach, so the product stays a normal FP32 number for any physical
 // width).
 //
-// Each chunk's line data pass through a slice of LDS private to the wave:
-// lanes 0..31 load the value coefficients and gamma^2 and form the lines'
-// offsets nu_l - nu_w (one FP64 subtraction for 32 lines), lanes 32..63 load
-// the tangent coefficients, all with vector loads; the line loop reads them
-// back as wave-uniform LDS broadcasts into vector registers.  Per-line scalar
+// Each chunk of 64 far lines passes through a slice of LDS private to the
+// wave: lane i loads line i's value and tangent coefficients and gamma^2 with
+// vector loads and forms its offset nu_l - nu_w (one FP64 subtraction for the
+// 64 lines); the line loop reads them back as wave-uniform LDS broadcasts
+// into vector registers, and sums the chunk in plain FP32 before it enters
+// the compensated accumulator.  Per-line scalar
 // loads of the same records were slower (their latency stalled the loop), and
 // coefficients in vector registers need no copies to get round the one-scalar
 // operand limit of a VALU instruction.  The stage needs no workgroup barrier:
 // LDS operations of one wave complete in order.
+constexpr int kFarChunk = 64;
 struct FarStage {
-  float4 eg[kChunk];  // e0, e1, e2, gamma^2
-  float4 t[kChunk];   // tangent t0..t3
-  float dl[kChunk];   // (float)(nu_l - nu_w)
+  float4 eg[kFarChunk];  // e0, e1, e2, gamma^2
+  float4 t[kFarChunk];   // tangent t0..t3
+  float dl[kFarChunk];   // (float)(nu_l - nu_w)
 };
 // Orders one wave's LDS writes before its later reads of another lane's
 // data, and its reads before later overwrites.
@@ -280,19 +282,15 @@ __device__ __forceinline__ void far_lines(int sb, int se, const LineRec* __restr
   float dj[G];
 #pragma unroll
   for (int g = 0; g < G; ++g) dj[g] = (float)(nuj[g] - nuw);
-  const int half = lane & 31;
-  for (int l0 = sb; l0 < se; l0 += kChunk) {
-    const int l1 = min(l0 + kChunk, se);
-    // stage the chunk
-    const int li = l0 + half;
+  for (int l0 = sb; l0 < se; l0 += kFarChunk) {
+    const int l1 = min(l0 + kFarChunk, se);
+    // stage the chunk: lane i holds line l0 + i
+    const int li = l0 + lane;
     if (li < l1) {
-      if (lane < 32) {
-        const float4 e = *reinterpret_cast<const float4*>(R[li].e);
-        st->eg[half] = make_float4(e.x, e.y, e.z, R[li].gam2);
-        st->dl[half] = (float)(nuc[li] - nuw);
-      } else if (TAN) {
-        st->t[half] = *reinterpret_cast<const float4*>(RT[li].t);
-      }
+      const float4 e = *reinterpret_cast<const float4*>(R[li].e);
+      st->eg[lane] = make_float4(e.x, e.y, e.z, R[li].gam2);
+      st->dl[lane] = (float)(nuc[li] - nuw);
+      if (TAN) st->t[lane] = *reinterpret_cast<const float4*>(RT[li].t);
     }
     wave_lds_sync();
     float blk[G], tblk[G];
