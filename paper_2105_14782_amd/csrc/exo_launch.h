@@ -45,6 +45,7 @@ struct VoigtArgs {
   float2* part_t;
   double* part64;
   const float* far_reach2;         // [nlay] squared far-tier reach of each layer (cm^-2)
+  const int* far_t3;               // [nlay] tangent mode: 1 if far pairs keep the tangent's r^4 term
   unsigned long long* near_pairs;  // profiling only: pairs summed by the near tier
 };
 
@@ -164,8 +165,8 @@ hipError_t launch_line_records(const LinesDev& L, const double* T_lay, const dou
                                unsigned int* g2max_bits, hipStream_t st);
 // Squared far-tier reach of each layer from its records and g2max_bits,
 // which it resets to zero for the next chunk.
-hipError_t launch_far_reach(const LineRec* rec, int64_t n_lines, int nlay, unsigned int* g2max_bits,
-                            float* reach2, hipStream_t st);
+hipError_t launch_far_reach(const LineRec* rec, int64_t n_lines, int nlay, bool tangent,
+                            unsigned int* g2max_bits, float* reach2, int* t3, hipStream_t st);
 hipError_t launch_voigt(const VoigtArgs& A, bool fp64, bool tangent, hipStream_t st);
 hipError_t launch_modit(const ModitArgs& M, bool fp64, hipStream_t st);
 hipError_t launch_select_lines(const SelectArgs& A, hipStream_t st);

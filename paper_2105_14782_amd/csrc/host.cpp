@@ -435,7 +435,7 @@ OpacityPlan exo::plan_opacity(int64_t n_lines, int nlay, int64_t ng, bool fp64, 
   } else {
     P.rec = (size_t)P.nlc * n_lines * sizeof(LineRec);
     P.core = (size_t)P.nlc * n_lines * sizeof(LineCore);
-    P.tier = (size_t)kMaxLayers * (sizeof(unsigned int) + sizeof(float));
+    P.tier = (size_t)kMaxLayers * (sizeof(unsigned int) + sizeof(float) + sizeof(int));
     if (tangent) P.rect = (size_t)P.nlc * n_lines * sizeof(LineRecT);
   }
   // partial sums (the FP32 sum always passes its far-line state through
@@ -494,6 +494,7 @@ int exo::species_opacity(exo_ctx* c, Workspace& ws, const Species& sp, const dou
   // squared reach; k_far_reach zeroes the bits of its chunk after use
   unsigned int* g2bits = fp64 ? nullptr : (unsigned int*)ws.tier.p;
   float* reach2 = fp64 ? nullptr : (float*)(g2bits + kMaxLayers);
+  int* t3 = fp64 ? nullptr : (int*)(g2bits + 2 * kMaxLayers);
   if (!fp64 && ws.tier_zeroed != ws.tier.p)
     HIP_TRY(hipMemsetAsync(g2bits, 0, (size_t)kMaxLayers * sizeof(unsigned int), st));
   ws.tier_zeroed = nullptr;
@@ -504,7 +505,7 @@ int exo::species_opacity(exo_ctx* c, Workspace& ws, const Species& sp, const dou
                                 (!fp64 && tangent) ? (LineRecT*)ws.rect.p : nullptr,
                                 fp64 ? nullptr : (LineCore*)ws.core.p,
                                 fp64 ? (LineRec64*)ws.rec64.p : nullptr, g2bits, st));
-    if (!fp64) HIP_TRY(launch_far_reach((const LineRec*)ws.rec.p, sp.n, nl, g2bits, reach2, st));
+    if (!fp64) HIP_TRY(launch_far_reach((const LineRec*)ws.rec.p, sp.n, nl, tangent, g2bits, reach2, t3, st));
     VoigtArgs A{};
     A.nu = d_nu;
     A.ng = ng;
@@ -515,6 +516,7 @@ int exo::species_opacity(exo_ctx* c, Workspace& ws, const Species& sp, const dou
     A.core = (const LineCore*)ws.core.p;
     A.rec64 = (const LineRec64*)ws.rec64.p;
     A.far_reach2 = reach2;
+    A.far_t3 = t3;
     A.nlay = nl;
     A.out_scale = (float)(1.0 / amp_scale);
     A.out_scale64 = 1.0 / amp_scale;

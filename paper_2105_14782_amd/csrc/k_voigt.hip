@@ -100,6 +100,11 @@ constexpr int kChunk = 32;
 // loosely than with that fixed U, and R never exceeds beta_max^2 / 2e-5.
 // Layers with narrow lines (low pressure) get a reach several times smaller.
 // R >= 2 * 111 beta_max^2 keeps every far pair out of the core branch.
+// In tangent mode it also tries a tangent cut after r^3 (one FMA less per
+// far pair; its dropped terms add 3 A_3 and 3 A_2 v to the tangent bound)
+// and takes it where the reach that bound needs is at most twice R: a few
+// more near pairs against fewer FMAs on every far pair.  Where the Lorentz
+// widths are small (v ~ 0) the two reaches nearly coincide.
 //
 // The Doppler width is proportional to the line centre (Eq. thermal) and the
 // lines are sorted by centre, so the last line of a layer has the largest
@@ -122,25 +127,48 @@ __device__ inline double far_monomial(int p, int q, double U, double gr) {
   return m / den;
 }
 
-__device__ inline bool far_bound_holds(double U, double gr) {
+// t3: the tangent keeps its r^4 term (else it stops at r^3)
+__device__ inline bool far_bound_holds(double U, double gr, bool t3) {
   auto M = [&](int p, int q) { return far_monomial(p, q, U, gr); };
   // A_k: sum of |coefficient| x monomial bound of c_k r^k; Av_k: the same times v
   const double A3 = 105.0 * M(3, 0) + 60.0 * M(2, 1), A4 = 48.0 * M(2, 2) + 840.0 * M(3, 1);
   const double A5 = 1680.0 * M(3, 2), A6 = 960.0 * M(3, 3);
+  const double Av2 = 15.0 * M(2, 1) + 4.0 * M(1, 2);
   const double Av3 = 105.0 * M(3, 1) + 60.0 * M(2, 2), Av4 = 48.0 * M(2, 3) + 840.0 * M(3, 2);
   const double Av5 = 1680.0 * M(3, 3), Av6 = 960.0 * M(3, 4);
   const double ev = A3 + A4 + A5 + A6;
-  const double et = 4.0 * A4 + 5.0 * A5 + 6.0 * A6 + 4.0 * Av3 + 5.0 * Av4 + 6.0 * Av5 + 7.0 * Av6;
+  double et = 4.0 * A4 + 5.0 * A5 + 6.0 * A6 + 4.0 * Av3 + 5.0 * Av4 + 6.0 * Av5 + 7.0 * Av6;
+  if (!t3) et += 3.0 * A3 + 3.0 * Av2;
   return ev <= kFarEpsV && et <= kFarEpsT;
 }
 
-// One 64-lane block per layer of the chunk: a two-level search on ln R,
-// 64 candidates per level, each lane testing one (the bound is monotone in R,
-// so the first candidate that holds is the smallest); the result lies within
-// ln(225)/4096 of the smallest R, rounded upwards.
+// Two-level search on ln R in [lo, hi] by the 64 lanes of a wave: the
+// smallest candidate (to ln(225)/4096) at which the bound holds; fails if
+// it does not hold at hi.
+__device__ inline bool far_search(double bmax, double gmax, double lo, double hi, bool t3, int k,
+                                  double* x) {
+  double a = lo, b = hi;
+  bool found = false;
+  for (int level = 0; level < 2; ++level) {
+    const double xk = a + (b - a) * (double)(k + 1) * (1.0 / 64.0);
+    const double R = exp(xk);
+    const unsigned long long ok = __ballot(far_bound_holds(bmax / R, gmax / R, t3));
+    if (ok == 0ull) break;
+    const int k1 = __builtin_ctzll(ok);
+    const double bn = a + (b - a) * (double)(k1 + 1) * (1.0 / 64.0);
+    a = k1 == 0 ? a : a + (b - a) * (double)k1 * (1.0 / 64.0);
+    b = bn;
+    found = true;
+  }
+  *x = b;
+  return found;
+}
+
+// One 64-lane block per layer of the chunk.  t3[y] (tangent mode): 1 if
+// far pairs keep the tangent's r^4 term.
 __global__ __launch_bounds__(64) void k_far_reach(const LineRec* __restrict__ rec, int64_t n_lines,
-                                                  unsigned int* __restrict__ g2max_bits,
-                                                  float* __restrict__ reach2) {
+                                                  int tangent, unsigned int* __restrict__ g2max_bits,
+                                                  float* __restrict__ reach2, int* __restrict__ t3) {
   const int y = blockIdx.x, k = threadIdx.x;
   // beta_max^2 from the threshold 2 * 111 beta^2, with margin for its rounding
   const double bmax = (double)rec[(int64_t)y * n_lines + n_lines - 1].thr * (1.001 / (2.0 * kHjertSwitch));
@@ -148,26 +176,22 @@ __global__ __launch_bounds__(64) void k_far_reach(const LineRec* __restrict__ re
   __syncthreads();  // every lane has read the maximum before lane 0 clears it
   const double lo = log(2.0 * kHjertSwitch * bmax), hi = log(bmax / kFarU);
   double x = hi;
+  int keep3 = 1;
   // an unknown maximum (not a finite non-negative float) keeps the fixed-U reach
   if (bits <= 0x7f7fffffu && lo < hi) {
     const double gmax = (double)__uint_as_float(bits) * 1.001;
-    double a = lo, b = hi;
-    for (int level = 0; level < 2; ++level) {
-      const double xk = a + (b - a) * (double)(k + 1) * (1.0 / 64.0);
-      const double R = exp(xk);
-      const unsigned long long ok = __ballot(far_bound_holds(bmax / R, gmax / R));
-      if (ok == 0ull) break;  // not even b holds: keep the previous upper end
-      const int k1 = __builtin_ctzll(ok);
-      const double bn = a + (b - a) * (double)(k1 + 1) * (1.0 / 64.0);
-      a = k1 == 0 ? a : a + (b - a) * (double)k1 * (1.0 / 64.0);
-      b = bn;
-      x = b;
+    double x3, x2;
+    if (far_search(bmax, gmax, lo, hi, true, k, &x3)) x = x3;
+    if (tangent && far_search(bmax, gmax, lo, hi, false, k, &x2) && x2 <= x + 0.6931471805599453) {
+      x = x2;
+      keep3 = 0;
     }
   }
   if (k == 0) {
     g2max_bits[y] = 0u;
     // rounded up so that the FP32 value does not undercut the bound
     reach2[y] = (float)(exp(x) * (1.0 + 1e-6));
+    t3[y] = keep3;
   }
 }
 
@@ -245,7 +269,8 @@ __device__ __forceinline__ void near_range(const VoigtArgs& A, int64_t tile0, in
 // reach) this errs by ~1e-7 relative, like rounding the FP64 offset.  One
 // reciprocal serves two points: r0 = D1 / (D0 D1), r1 = D0 / (D0 D1) (D >= the
 // squared reach, so the product stays a normal FP32 number for any physical
-// width).
+// width).  T3: the tangent keeps its r^4 term (false where the layer's
+// bound allows the tangent to stop at r^3).
 //
 // Each chunk of 64 far lines passes through a slice of LDS private to the
 // wave: lane i loads line i's value and tangent coefficients and gamma^2 with
@@ -271,7 +296,7 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <bool TAN, int G>
+template <bool TAN, bool T3, int G>
 __device__ __forceinline__ void far_lines(int sb, int se, const LineRec* __restrict__ R,
                                           const LineRecT* __restrict__ RT,
                                           const double* __restrict__ nuc, const double (&nuj)[G], double nuw,
@@ -320,7 +345,8 @@ __device__ __forceinline__ void far_lines(int sb, int se, const LineRec* __restr
         const float h = fmaf(fmaf(e.z, r[g], e.y), r[g], e.x);
         blk[g] = fmaf(h, r[g], blk[g]);
         if (TAN) {
-          const float ht = fmaf(fmaf(fmaf(t.w, r[g], t.z), r[g], t.y), r[g], t.x);
+          const float ht = T3 ? fmaf(fmaf(fmaf(t.w, r[g], t.z), r[g], t.y), r[g], t.x)
+                              : fmaf(fmaf(t.z, r[g], t.y), r[g], t.x);
           tblk[g] = fmaf(ht, r[g], tblk[g]);
         }
       }
@@ -468,7 +494,8 @@ __device__ __forceinline__ void voigt_body(const VoigtArgs& A) {
   for (int seg = 0; seg < 2; ++seg) {
     const int sb = seg == 0 ? lb : i1;
     const int se = seg == 0 ? i0 : le;
-    far_lines<TAN, G>(sb, se, R, RT, A.nu_c, nuj, nuw, &stage[w], lane, s, c, ts, tc);
+    if (!TAN || A.far_t3[y]) far_lines<TAN, true, G>(sb, se, R, RT, A.nu_c, nuj, nuw, &stage[w], lane, s, c, ts, tc);
+    else far_lines<TAN, false, G>(sb, se, R, RT, A.nu_c, nuj, nuw, &stage[w], lane, s, c, ts, tc);
     if (seg == 0) near_lines<TAN, G>(i0, i1, R, RT, RC, A.nu_c, nuj, s, c, ts, tc);
   }
   if (A.near_pairs && lane == 0) {
@@ -625,9 +652,10 @@ hipError_t launch_line_records(const LinesDev& L, const double* T_lay, const dou
   return hipGetLastError();
 }
 
-hipError_t launch_far_reach(const LineRec* rec, int64_t n_lines, int nlay, unsigned int* g2max_bits,
-                            float* reach2, hipStream_t st) {
-  hipLaunchKernelGGL(k_far_reach, dim3((unsigned)nlay), dim3(64), 0, st, rec, n_lines, g2max_bits, reach2);
+hipError_t launch_far_reach(const LineRec* rec, int64_t n_lines, int nlay, bool tangent,
+                            unsigned int* g2max_bits, float* reach2, int* t3, hipStream_t st) {
+  hipLaunchKernelGGL(k_far_reach, dim3((unsigned)nlay), dim3(64), 0, st, rec, n_lines, tangent ? 1 : 0, g2max_bits,
+                     reach2, t3);
   return hipGetLastError();
 }
 

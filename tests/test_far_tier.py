@@ -9,7 +9,7 @@ def test_far_reach_bound_covers_truncation():
     wing terms beyond r^3 (value) and r^4 (tangent) changes no far pair by more
     than the stated bounds (dense scan over gamma^2 <= g_max, dnu^2 >= R)."""
     for bmax, gmax in [(1e-4, 0.0), (1e-4, 1e-8), (1e-4, 1e-4), (1e-4, 1e-2), (1e-4, 1.0), (1e-4, 100.0)]:
-        R = far_reach2(bmax, gmax)
+        R, _ = far_reach2(bmax, gmax)
         assert 222.0 * bmax <= R <= bmax / 2e-5 * (1 + 1e-5)
         g = np.concatenate([[0.0], gmax * np.logspace(-6, 0, 200)])[:, None]
         D = R * np.logspace(0, 3, 300)[None, :] + g
@@ -27,3 +27,31 @@ def test_far_reach_bound_covers_truncation():
         tg = sum(dcg[k] * r ** k for k in range(4, 7)) - sum((k + 1) * c[k] * r ** k * (g * r) for k in range(3, 7))
         tE = sum(c[k] * r ** k for k in range(4, 7))
         assert np.max(np.abs(tb) + np.abs(tg) + np.abs(tE)) <= 1.42e-8 * 3
+
+
+def test_far_tangent_cut_after_r3_bound():
+    """Where the tangent stops at r^3 (tangent mode, narrow Lorentz widths), the
+    dropped tangent terms from r^4 on stay within the stated bound, and where
+    the Lorentz widths are wide the r^4 term is kept."""
+    n_cut = 0
+    for bmax, gmax in [(1e-4, 0.0), (1e-4, 1e-10), (1e-4, 1e-6), (1e-4, 1e-4), (1e-4, 1e-2), (1e-4, 1.0)]:
+        R, t3 = far_reach2(bmax, gmax, tangent=True)
+        if t3:
+            continue
+        n_cut += 1
+        g = np.concatenate([[0.0], gmax * np.logspace(-6, 0, 200)])[:, None]
+        D = R * np.logspace(0, 3, 300)[None, :] + g
+        r, b = 1.0 / D, bmax
+        c = [np.ones_like(D), 3 * b + 0 * g, 15 * b * b - 4 * b * g, 105 * b ** 3 - 60 * b * b * g,
+             48 * b * b * g * g - 840 * b ** 3 * g, 1680 * b ** 3 * g * g, -960 * b ** 3 * g ** 3]
+        dcb = [0 * D, 3 * b + 0 * g, 30 * b * b - 4 * b * g, 315 * b ** 3 - 120 * b * b * g,
+               96 * b * b * g * g - 2520 * b ** 3 * g, 5040 * b ** 3 * g * g, -2880 * b ** 3 * g ** 3]
+        dcg = [0 * D, 0 * D, -4 * b * g, -60 * b * b * g, 96 * b * b * g * g - 840 * b ** 3 * g,
+               3360 * b ** 3 * g * g, -2880 * b ** 3 * g ** 3]
+        tb = sum(dcb[k] * r ** k for k in range(3, 7))
+        tg = sum(dcg[k] * r ** k for k in range(3, 7)) - sum((k + 1) * c[k] * r ** k * (g * r) for k in range(2, 7))
+        tE = sum(c[k] * r ** k for k in range(3, 7))
+        assert np.max(np.abs(tb) + np.abs(tg) + np.abs(tE)) <= 1.42e-8 * 3
+    assert n_cut >= 3
+    assert far_reach2(1e-4, 100.0, tangent=True)[1]
+

@@ -186,7 +186,7 @@ def _near_pairs_expected(ll, T, nu, wave_points=256, P=1.0):
     bmax = thr * (1.001 / 222.0)
     gam = ll.alpha_ref * (T / 296.0) ** (-ll.n_texp) * P
     gmax = float(np.max((gam * gam).astype(np.float32))) * 1.001
-    reach = math.sqrt(far_reach2(bmax, gmax))
+    reach = math.sqrt(far_reach2(bmax, gmax)[0])
     total = 0
     for j0 in range(0, nu.size, wave_points):
         j1 = min(j0 + wave_points, nu.size) - 1
