@@ -32,9 +32,11 @@ PEAK_FP32_TFLOPS = 157.3      # MI355X published FP32 vector peak (packed FMA)
 # are counted at this rate too): offset 1, D 2, 1/D 1, value polynomial
 # 12 + 1, tangent polynomial 14 + 1, two accumulations 2.  Far tier
 # (polynomial truncated below FP32 rounding): offset 1, D 2, 1/D 1, value
-# polynomial 4, tangent polynomial 6, two accumulations 4.
+# polynomial 4, tangent polynomial 6 (4 in layers where it stops at r^3),
+# two accumulations 4.
 FLOPS_PER_EVAL_NEAR = 34.0
 FLOPS_PER_EVAL_FAR = 18.0
+FLOPS_PER_EVAL_FAR_CUT = 16.0   # far pair whose tangent polynomial stops at r^3
 
 
 def parse():
@@ -545,6 +547,7 @@ def main():
     T = time.perf_counter() - t0
     nl, kms, kevals = ctx.profile_read()
     knear = ctx.profile_read_near()
+    kcut = ctx.profile_read_far_cut()
     ctx.profile(False)
     lat = np.array([a.elapsed_time(b) for a, b in ev])
     ms = 1e3 * T / args.steps
@@ -587,7 +590,8 @@ def main():
     tjvp = (time.perf_counter() - tj0) / max(3, args.steps // 2)
 
     avg_launch_ms = kms / max(nl, 1)
-    flops_per_launch = (FLOPS_PER_EVAL_NEAR * knear + FLOPS_PER_EVAL_FAR * (kevals - knear)) / max(nl, 1)
+    flops_per_launch = (FLOPS_PER_EVAL_NEAR * knear + FLOPS_PER_EVAL_FAR * (kevals - knear - kcut)
+                        + FLOPS_PER_EVAL_FAR_CUT * kcut) / max(nl, 1)
     achieved = flops_per_launch / (avg_launch_ms * 1e-3) / 1e12
     out = {
         "metric": METRIC,
@@ -619,7 +623,9 @@ def main():
                      "kernel": "k_voigt_f32<tangent>", "avg_launch_ms": avg_launch_ms,
                      "launches": nl, "evals_per_launch": kevals / max(nl, 1),
                      "near_fraction": knear / max(kevals, 1.0),
-                     "flops_per_eval": {"near": FLOPS_PER_EVAL_NEAR, "far": FLOPS_PER_EVAL_FAR},
+                     "far_cut_fraction": kcut / max(kevals, 1.0),
+                     "flops_per_eval": {"near": FLOPS_PER_EVAL_NEAR, "far": FLOPS_PER_EVAL_FAR,
+                                        "far_cut": FLOPS_PER_EVAL_FAR_CUT},
                      "evals_per_s": kevals / (kms * 1e-3)},
     }
     ctx.close()

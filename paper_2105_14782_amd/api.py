@@ -295,6 +295,13 @@ class Context:
         L.check(self._lib.exo_profile_read_near(self._h, ctypes.byref(ev)))
         return ev.value
 
+    def profile_read_far_cut(self) -> float:
+        """Far-tier pair evaluations of the profiled tangent launches whose
+        T-derivative polynomial stops at r^3."""
+        ev = ctypes.c_double()
+        L.check(self._lib.exo_profile_read_far_cut(self._h, ctypes.byref(ev)))
+        return ev.value
+
 
 def hjert_f32(x: torch.Tensor, a: torch.Tensor, want_L: bool = False, stream=None):
     lib = L.load_library()

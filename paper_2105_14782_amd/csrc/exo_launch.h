@@ -46,7 +46,8 @@ struct VoigtArgs {
   double* part64;
   const float* far_reach2;         // [nlay] squared far-tier reach of each layer (cm^-2)
   const int* far_t3;               // [nlay] tangent mode: 1 if far pairs keep the tangent's r^4 term
-  unsigned long long* near_pairs;  // profiling only: pairs summed by the near tier
+  unsigned long long* near_pairs;  // profiling only: [0] pairs summed by the near tier,
+                                   // [1] far pairs whose tangent stops at r^3
 };
 
 // Per-layer quantities of one atmosphere.

@@ -330,8 +330,8 @@ extern "C" int exo_profile_enable(exo_ctx* c, int on) {
   }
   c->prof.clear();
   if (on) {
-    if (c->prof_near.reserve(sizeof(unsigned long long))) return EXO_ENOMEM;
-    HIP_TRY(hipMemset(c->prof_near.p, 0, sizeof(unsigned long long)));
+    if (c->prof_near.reserve(2 * sizeof(unsigned long long))) return EXO_ENOMEM;
+    HIP_TRY(hipMemset(c->prof_near.p, 0, 2 * sizeof(unsigned long long)));
   }
   c->profile = on != 0;
   return EXO_OK;
@@ -345,6 +345,17 @@ extern "C" int exo_profile_read_near(exo_ctx* c, double* near_evals) {
   unsigned long long n = 0;
   if (c->prof_near.p) HIP_TRY(hipMemcpy(&n, c->prof_near.p, sizeof(n), hipMemcpyDeviceToHost));
   *near_evals = (double)n;
+  return EXO_OK;
+}
+
+extern "C" int exo_profile_read_far_cut(exo_ctx* c, double* far_cut_evals) {
+  if (!c) return set_err(EXO_EINVAL, "ctx is NULL");
+  if (!far_cut_evals) return set_err(EXO_EINVAL, "far_cut_evals is NULL");
+  HIP_TRY(hipSetDevice(c->device));
+  for (auto& p : c->prof) HIP_TRY(hipEventSynchronize(p.b));
+  unsigned long long n[2] = {0, 0};
+  if (c->prof_near.p) HIP_TRY(hipMemcpy(n, c->prof_near.p, sizeof(n), hipMemcpyDeviceToHost));
+  *far_cut_evals = (double)n[1];
   return EXO_OK;
 }
 

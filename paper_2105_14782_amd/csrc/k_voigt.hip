@@ -500,7 +500,11 @@ __device__ __forceinline__ void voigt_body(const VoigtArgs& A) {
   }
   if (A.near_pairs && lane == 0) {
     const int64_t npts = min((int64_t)G * 64, A.ng - (tile0 + (int64_t)w * G * 64));
-    if (npts > 0) atomicAdd(A.near_pairs, (unsigned long long)(i1 - i0) * (unsigned long long)npts);
+    if (npts > 0) {
+      atomicAdd(A.near_pairs, (unsigned long long)(i1 - i0) * (unsigned long long)npts);
+      if (TAN && !A.far_t3[y])
+        atomicAdd(A.near_pairs + 1, (unsigned long long)((le - lb) - (i1 - i0)) * (unsigned long long)npts);
+    }
   }
 
 #pragma unroll
