@@ -156,16 +156,18 @@ def summarize_counters(fetch_csv, write_csv, out_path):
         f"{f_fac:.3f} and WRITE_SIZE by {w_fac:.3f}.", "",
         f"Tangent Voigt launches measured: {len(fv)} (1e5 lines x 20,000 points x 100 layers each).", "",
         "Algorithmic bytes per launch: line records 1e7 x (64 + 64) B + centres 0.8 MB read, "
-        "outputs 2 x 100 x 20,000 x 8 B (split partial sums) written: 1.33e9 B.  Register spills of the",
-        "core-branch call (the kernel asks for 7 waves per SIMD) add scratch writes and reads.", "",
+        "outputs 2 x 100 x 20,000 x 8 B (split partial sums) written: 1.33e9 B.  Register spills around the",
+        "out-of-line core-branch call (the kernel asks for 8 waves per SIMD, 64 registers per lane) add",
+        "scratch writes and reads.", "",
         f"- fetch_kib_per_launch: {np.mean(fv):.1f}",
         f"- write_kib_per_launch: {np.mean(wv):.1f}",
         f"- traffic_bytes_per_launch: {fetch + write:.4e}",
         f"- kernel_source_sha256: `{voigt_source_hash()}`", "",
-        "The fetched bytes exceed the algorithmic record stream because every wave streams",
-        "the records of its (layer, split) through the scalar cache and the per-XCD L2 cannot",
-        "hold the streams of all resident workgroups; at the kernel's duration this is well",
-        "below HBM bandwidth (the kernel is VALU-issue bound).",
+        "The fetched bytes exceed the algorithmic record stream because every wave loads the",
+        "records of its (layer, split) chunk by chunk into its own LDS slice, and the per-XCD L2",
+        "does not hold the streams of all resident workgroups; most written bytes are the spills",
+        "around the core call.  At the kernel's duration this is well below HBM bandwidth (the",
+        "kernel is VALU-issue bound).",
     ]
     open(out_path, "w").write("\n".join(lines) + "\n")
     print("\n".join(lines))
@@ -212,9 +214,12 @@ def summarize_valu(csv_path, out_path):
         f"- SQ_ACTIVE_INST_VALU per launch: {m['SQ_ACTIVE_INST_VALU']:.4e}",
         f"- VALU issue occupancy (instructions x 4 cycles / (1024 SIMDs x cycles)): {issue:.3f}",
         "",
-        "Transcendental instructions (v_rcp_f32 and the like) run at a quarter of the",
-        "VALU rate, so with them the SIMDs are busier than the occupancy above; the",
-        "kernel is bound by VALU issue, not by memory.",
+        "A throughput probe (independent FMA chains, packed FP32 disabled) runs a 64-wide",
+        "v_fma_f32 every 4 cycles per SIMD (76.9 TFLOP/s, 98 % of 78.6) and a v_rcp_f32 with",
+        "its dependent add every 12.  An occupancy near or above 1 therefore means the SIMDs",
+        "issue VALU work on (nearly) every cycle; above 1, some counted instructions (moves,",
+        "masks, lane operations) hold the SIMD for fewer than 4 cycles.  The kernel is bound",
+        "by VALU issue, not by memory: the lever is the instruction count per pair.",
     ]
     open(out_path, "w").write("\n".join(lines) + "\n")
     print("\n".join(lines))
@@ -259,7 +264,9 @@ def summarize_stats(csv_path, out_path, modit=False):
             "Workload: 2 species x 1e5 lines, 20,000-point log-uniform grid, 100 layers.",
             "The run does 1 warm-up + 3 timed flux_vjp steps (two tangent-mode Voigt sums each),",
             "then 4 FP32 forward spectra and 2 plain-FP64 forward spectra (two Voigt sums each),",
-            "then 4 loss_grad (leapfrog step) and 4 flux_jvp calls (tangent-mode Voigt sums as well).", "",
+            "then 4 loss_grad (leapfrog step) and 4 flux_jvp calls (tangent-mode Voigt sums as well),",
+            "then the config-1 cross-section timing (1000 lines x 4000 points, one layer: 51 FP32 and",
+            "51 plain-FP64 calls, hence the many short `k_voigt_f32<false, 4>` and `k_voigt_f64` launches).", "",
         ]
     lines = head + ["| kernel | calls | avg ms | total ms | % |", "|---|---:|---:|---:|---:|"]
     for r in rows:

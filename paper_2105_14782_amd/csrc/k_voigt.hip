@@ -69,8 +69,7 @@ __global__ __launch_bounds__(256) void k_line_records(LinesDev L, const double* 
 //
 // Block = 256 threads = 4 waves; thread (wave w, lane) owns grid points
 // j = tile0 + (w*G + g)*64 + lane, g < G.  All lanes walk the same line
-// sequence, so line records are wave-uniform (LDS broadcasts in the far
-// tier, scalar loads in the near tier).  A near pair's offset nu_j - nu_l is
+// sequence, so line records are wave-uniform (LDS broadcasts).  A near pair's offset nu_j - nu_l is
 // one FP64 subtraction, rounded once to FP32: an FP32 offset would carry an
 // absolute error of ulp(nu) ~ 5e-4 cm^-1, a few percent of a Doppler width.
 // Contributions of a block of lines (64 far, kChunk near) are summed in plain
@@ -288,6 +287,23 @@ struct FarStage {
   float4 t[kFarChunk];   // tangent t0..t3
   float dl[kFarChunk];   // (float)(nu_l - nu_w)
 };
+// The near tier stages its lines the same way (full polynomials, the core
+// threshold and the FP64 centre; lanes 0..31 the value side, 32..63 the
+// tangent side of 32 lines), and walks them one line per iteration: two
+// lines in flight spill inside the loop at 64 registers per lane.
+struct NearStage {
+  float4 e03[kChunk];  // e0..e3
+  float4 e4g[kChunk];  // e4, e5, e6, gamma^2
+  float4 t03[kChunk];  // tangent t0..t3
+  float4 t47[kChunk];  // tangent t4..t7
+  double nu[kChunk];   // line centre
+  float thr[kChunk];   // core threshold
+};
+union LineStage {
+  FarStage far;
+  NearStage near;
+};
+
 // Orders one wave's LDS writes before its later reads of another lane's
 // data, and its reads before later overwrites.
 __device__ __forceinline__ void wave_lds_sync() {
@@ -371,11 +387,26 @@ __device__ __forceinline__ void near_lines(int sb, int se, const LineRec* __rest
                                            const LineRecT* __restrict__ RT,
                                            const LineCore* __restrict__ RC,
                                            const double* __restrict__ nuc, const double (&nuj)[G],
+                                           NearStage* __restrict__ st, int lane,
                                            float (&s)[G], float (&c)[G], float (&ts)[G],
                                            float (&tc)[G]) {
   static_assert(kChunk == 32, "one mask bit per line of the chunk");
+  const int half = lane & 31;
   for (int l0 = sb; l0 < se; l0 += kChunk) {
     const int l1 = min(l0 + kChunk, se);
+    const int li = l0 + half;
+    if (li < l1) {
+      if (lane < 32) {
+        st->e03[half] = *reinterpret_cast<const float4*>(R[li].e);
+        st->e4g[half] = *reinterpret_cast<const float4*>(R[li].e + 4);
+        st->thr[half] = R[li].thr;
+        st->nu[half] = nuc[li];
+      } else if (TAN) {
+        st->t03[half] = *reinterpret_cast<const float4*>(RT[li].t);
+        st->t47[half] = *reinterpret_cast<const float4*>(RT[li].t + 4);
+      }
+    }
+    wave_lds_sync();
     float blk[G], tblk[G];
     uint32_t cm[G];
 #pragma unroll
@@ -383,47 +414,45 @@ __device__ __forceinline__ void near_lines(int sb, int se, const LineRec* __rest
       blk[g] = tblk[g] = 0.f;
       cm[g] = 0u;
     }
-    LineRec qn = R[l0];
-    double nun = nuc[l0];
-    LineRecT qtn;
-    if (TAN) qtn = RT[l0];
-#pragma unroll 2
-    for (int l = l0; l < l1; ++l) {
-      const LineRec q = qn;
-      const double nul = nun;
-      LineRecT qt;
-      if (TAN) qt = qtn;
-      const int ln = l + 1 < l1 ? l + 1 : l;
-      qn = R[ln];
-      nun = nuc[ln];
-      if (TAN) qtn = RT[ln];
+    const int n = l1 - l0;
+#pragma unroll 1
+    for (int i = 0; i < n; ++i) {
+      const float4 e03 = st->e03[i], e4g = st->e4g[i];
+      const float thr = st->thr[i];
+      const double nul = st->nu[i];
+      float4 t03, t47;
+      if (TAN) {
+        t03 = st->t03[i];
+        t47 = st->t47[i];
+      }
 #pragma unroll
       for (int g = 0; g < G; ++g) {
         const float dd = (float)(nuj[g] - nul);  // FP64 offset, rounded once
-        const float D = fmaf(dd, dd, q.gam2);
+        const float D = fmaf(dd, dd, e4g.w);
         const float r = __builtin_amdgcn_rcpf(D);
-        float h = fmaf(q.e[6], r, q.e[5]);
-        h = fmaf(h, r, q.e[4]);
-        h = fmaf(h, r, q.e[3]);
-        h = fmaf(h, r, q.e[2]);
-        h = fmaf(h, r, q.e[1]);
-        h = fmaf(h, r, q.e[0]);
+        float h = fmaf(e4g.z, r, e4g.y);
+        h = fmaf(h, r, e4g.x);
+        h = fmaf(h, r, e03.w);
+        h = fmaf(h, r, e03.z);
+        h = fmaf(h, r, e03.y);
+        h = fmaf(h, r, e03.x);
         float ht = 0.f;
         if (TAN) {
-          ht = fmaf(qt.t[7], r, qt.t[6]);
-          ht = fmaf(ht, r, qt.t[5]);
-          ht = fmaf(ht, r, qt.t[4]);
-          ht = fmaf(ht, r, qt.t[3]);
-          ht = fmaf(ht, r, qt.t[2]);
-          ht = fmaf(ht, r, qt.t[1]);
-          ht = fmaf(ht, r, qt.t[0]);
+          ht = fmaf(t47.w, r, t47.z);
+          ht = fmaf(ht, r, t47.y);
+          ht = fmaf(ht, r, t47.x);
+          ht = fmaf(ht, r, t03.w);
+          ht = fmaf(ht, r, t03.z);
+          ht = fmaf(ht, r, t03.y);
+          ht = fmaf(ht, r, t03.x);
         }
-        const bool in_core = D < q.thr;
-        cm[g] |= (uint32_t)in_core << (l - l0);
+        const bool in_core = D < thr;
+        cm[g] |= (uint32_t)in_core << i;
         blk[g] += in_core ? 0.f : h * r;
         if (TAN) tblk[g] += in_core ? 0.f : ht * r;
       }
     }
+    wave_lds_sync();
     // lines of the chunk with a core pair at any point of the wave
     uint32_t u = 0u;
 #pragma unroll
@@ -471,7 +500,7 @@ __device__ __forceinline__ void voigt_body(const VoigtArgs& A) {
   const int y = blockIdx.y;
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  __shared__ FarStage stage[4];
+  __shared__ LineStage stage[4];
   const int64_t tile0 = (int64_t)blockIdx.x * (256 * G);
   double nuj[G];
   load_points<G>(A, tile0, w, lane, nuj);
@@ -494,9 +523,9 @@ __device__ __forceinline__ void voigt_body(const VoigtArgs& A) {
   for (int seg = 0; seg < 2; ++seg) {
     const int sb = seg == 0 ? lb : i1;
     const int se = seg == 0 ? i0 : le;
-    if (!TAN || A.far_t3[y]) far_lines<TAN, true, G>(sb, se, R, RT, A.nu_c, nuj, nuw, &stage[w], lane, s, c, ts, tc);
-    else far_lines<TAN, false, G>(sb, se, R, RT, A.nu_c, nuj, nuw, &stage[w], lane, s, c, ts, tc);
-    if (seg == 0) near_lines<TAN, G>(i0, i1, R, RT, RC, A.nu_c, nuj, s, c, ts, tc);
+    if (!TAN || A.far_t3[y]) far_lines<TAN, true, G>(sb, se, R, RT, A.nu_c, nuj, nuw, &stage[w].far, lane, s, c, ts, tc);
+    else far_lines<TAN, false, G>(sb, se, R, RT, A.nu_c, nuj, nuw, &stage[w].far, lane, s, c, ts, tc);
+    if (seg == 0) near_lines<TAN, G>(i0, i1, R, RT, RC, A.nu_c, nuj, &stage[w].near, lane, s, c, ts, tc);
   }
   if (A.near_pairs && lane == 0) {
     const int64_t npts = min((int64_t)G * 64, A.ng - (tile0 + (int64_t)w * G * 64));
