@@ -219,8 +219,10 @@ __device__ __forceinline__ float hjert_core_fac(float xf, float af, float ainv, 
   const double k = X + Y, kp = X - Y;
   // c_n = X^n + X^-n and e_n = n (X^n - X^-n) = dc_n/dx
   double c0 = 2.0, c1 = k, e0 = 0.0, e1 = kp, sc = 0.0, se = 0.0;
-  constexpr int kUnroll = WANT_L ? 9 : 3;
-#pragma unroll kUnroll
+  // 9 terms per iteration: one batch of scalar weight loads each; a full
+  // unroll measured 18 % slower in the tangent kernel (more spills), 3 terms
+  // 3.5 % slower in the forward kernel
+#pragma unroll 9
   for (int n = 1; n <= kM916; ++n) {
     const double w = wn[n - 1];
     sc = fma(w, c1, sc);
