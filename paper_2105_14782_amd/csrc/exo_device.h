@@ -26,6 +26,11 @@ constexpr double kLn10 = 2.30258509299404568402;
 constexpr double kHjertSwitch = 111.0;
 constexpr int kM916 = 27;                  // series length M
 constexpr float kEta = 0.5f;               // series step eta
+// Core branch of lines with a >= kWeidAmin: Weideman's rational
+// approximation of w with kWeidN terms (Weideman 1994, SIAM J. Numer. Anal.
+// 31, 1497), whose H stays within 2.4e-7 relative over x^2 + a^2 < 111 there.
+constexpr int kWeidN = 32;
+constexpr double kWeidAmin = 1e-5;
 
 // Records written by the line-parameter kernel for one (line, layer) and read
 // uniformly (scalar loads) by the Voigt-sum kernel.  Wing branch in physical
@@ -46,7 +51,8 @@ struct LineRec {
   float acore;    // amplitude / (sqrt(2 pi) beta): contribution = acore * H(x, a)
   float C1;       // sum_n w_n of LineCore  (S1 = e^{-x^2} C1)
   float ainv;     // 1 / a (infinite for a = 0, where it is not used)
-  float pad;
+  float weid;     // 1: the core branch uses the rational approximation of w
+                  // (a >= kWeidAmin); 0: the Algorithm-916 series
 };
 static_assert(sizeof(LineRec) == 64, "LineRec layout");
 
@@ -128,7 +134,7 @@ __device__ inline void make_line_record(double A, double beta, double gam, doubl
     if (RC) *RC = core;
   }
   r.ainv = (float)(1.0 / (gam * winv));
-  r.pad = 0.f;
+  r.weid = (gam * winv >= kWeidAmin) ? 1.f : 0.f;
   *R = r;
   if (RT) {
     // db/dT, dg/dT

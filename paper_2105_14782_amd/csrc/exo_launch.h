@@ -169,6 +169,9 @@ hipError_t launch_line_records(const LinesDev& L, const double* T_lay, const dou
 hipError_t launch_far_reach(const LineRec* rec, int64_t n_lines, int nlay, bool tangent,
                             unsigned int* g2max_bits, float* reach2, int* t3, hipStream_t st);
 hipError_t launch_voigt(const VoigtArgs& A, bool fp64, bool tangent, hipStream_t st);
+// Fills the coefficient table of the core branch's rational approximation on
+// the current device (once per process and device; synchronises the device).
+hipError_t ensure_weideman();
 hipError_t launch_modit(const ModitArgs& M, bool fp64, hipStream_t st);
 hipError_t launch_select_lines(const SelectArgs& A, hipStream_t st);
 hipError_t launch_hjert_f32(int64_t n, const float* x, const float* a, float* H, float* L,

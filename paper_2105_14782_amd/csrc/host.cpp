@@ -178,6 +178,7 @@ extern "C" int exo_create(int device, exo_ctx** out) {
   HIP_TRY(hipGetDeviceCount(&n));
   if (device < 0 || device >= n) return set_err(EXO_EINVAL, "device %d out of range (%d devices)", device, n);
   HIP_TRY(hipSetDevice(device));
+  HIP_TRY(ensure_weideman());
   exo_ctx* c = new exo_ctx();
   c->device = device;
   *out = c;

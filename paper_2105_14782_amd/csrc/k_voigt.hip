@@ -3,6 +3,9 @@
 #include "exo_launch.h"
 #include "exo_lines.h"
 
+#include <mutex>
+#include <vector>
+
 namespace exo {
 
 // Largest FP32 line amplitude (see k_line_records).
@@ -213,6 +216,65 @@ __device__ inline void neumaier(float& s, float& c, float v) {
   s = t;
 }
 
+// ---------------------------------------------------------------------------
+// Rational approximation of w for the core branch of lines with a >= kWeidAmin
+// (Weideman 1994):  w(z) ~ u/sqrt(pi) + 2 u^2 sum_{n=1..N} c_n Z^(n-1), with
+// u = 1/(L - iz), Z = (L + iz)/(L - iz), L = (N/sqrt2)^(1/2), and
+// c_n = (1/2M) sum_{|k|<M} f(t_k) cos(n theta_k), theta_k = k pi/M,
+// t_k = L tan(theta_k/2), f(t) = e^{-t^2} (L^2 + t^2), M = 2N.  About half the
+// operations of the series (no exponentials, no sine), with H and L = Im w
+// from the same evaluation.  Its absolute error is a small fraction of |w|,
+// which near the real axis far from the centre (small a) is much larger
+// than H; below kWeidAmin the series keeps the relative accuracy.
+// ---------------------------------------------------------------------------
+__device__ double g_weid[kWeidN];  // c_1 .. c_N, filled once per device
+
+__global__ __launch_bounds__(64) void k_weid_init() {
+  const int n = threadIdx.x + 1;
+  if (n > kWeidN) return;
+  constexpr int M = 2 * kWeidN;
+  const double L = sqrt((double)kWeidN / kSqrt2);
+  double s = 0.0;
+  for (int k = -M + 1; k <= M - 1; ++k) {
+    const double th = k * (kPi / M);
+    const double t = L * tan(0.5 * th);
+    s += exp(-t * t) * (L * L + t * t) * cos(n * th);
+  }
+  g_weid[n - 1] = s / (2.0 * M);
+}
+
+// Re w and Im w at z = x + ia (a > 0) in FP64 from the coefficients.
+__device__ inline void weideman_w(double x, double a, const double __attribute__((address_space(4)))* c,
+                                  double* re, double* im) {
+  const double L = sqrt((double)kWeidN / kSqrt2);
+  // u = 1/(L - iz) = 1/((L + a) - ix) = ((L + a) + ix)/den
+  const double p = L + a;
+  const double den = fma(p, p, x * x);
+  double inv = __builtin_amdgcn_rcp(den);
+  inv = fma(inv, fma(-den, inv, 1.0), inv);
+  inv = fma(inv, fma(-den, inv, 1.0), inv);
+  const double ur = p * inv, ui = x * inv;
+  // Z = (L + iz) u = ((L - a) + ix) u
+  const double q = L - a;
+  const double zr = fma(q, ur, -x * ui), zi = fma(q, ui, x * ur);
+  double sr = c[kWeidN - 1], si = 0.0;
+#pragma unroll 8
+  for (int n = kWeidN - 2; n >= 0; --n) {
+    const double tr = fma(sr, zr, fma(-si, zi, c[n]));
+    si = fma(sr, zi, si * zr);
+    sr = tr;
+  }
+  // w = u (1/sqrt(pi) + 2 u s)
+  const double vr = 0.56418958354775628 + 2.0 * fma(ur, sr, -ui * si);
+  const double vi = 2.0 * fma(ur, si, ui * sr);
+  *re = fma(ur, vr, -ui * vi);
+  *im = fma(ur, vi, ui * vr);
+}
+
+__device__ inline const double __attribute__((address_space(4)))* weid_coeffs() {
+  return (const double __attribute__((address_space(4)))*)(const double*)g_weid;
+}
+
 // Core evaluations are kept out of line: their FP64 temporaries would
 // otherwise set the register budget of the whole loop and cut occupancy.
 // The weight pointer is wave-uniform; reading it into scalar registers and
@@ -226,13 +288,24 @@ __device__ inline const double __attribute__((address_space(4)))* uniform_weight
   return (const double __attribute__((address_space(4)))*)(((uint64_t)hi << 32) | lo);
 }
 
+// weid != 0: the rational approximation (uniform per line, so no divergence)
 __device__ __attribute__((noinline)) float core_value(float x, float a, float ainv, float erfcxa,
-                                                      float C1, const double* __restrict__ wn) {
+                                                      float C1, const double* __restrict__ wn, float weid) {
+  if (weid != 0.f) {
+    double re, im;
+    weideman_w((double)x, (double)a, weid_coeffs(), &re, &im);
+    return (float)re;
+  }
   return hjert_core_fac<false>(x, a, ainv, erfcxa, C1, uniform_weights(wn), nullptr);
 }
 
 __device__ __attribute__((noinline)) float2 core_value_tan(float x, float a, float ainv, float erfcxa,
-                                                           float C1, const double* __restrict__ wn) {
+                                                           float C1, const double* __restrict__ wn, float weid) {
+  if (weid != 0.f) {
+    double re, im;
+    weideman_w((double)x, (double)a, weid_coeffs(), &re, &im);
+    return make_float2((float)re, (float)im);
+  }
   float L;
   const float H = hjert_core_fac<true>(x, a, ainv, erfcxa, C1, uniform_weights(wn), &L);
   return make_float2(H, L);
@@ -471,7 +544,7 @@ __device__ __forceinline__ void near_lines(int sb, int se, const LineRec* __rest
           const float x = (float)(nuj[g] - nul) * q.winv;
           if (TAN) {
             const LineRecT qt = RT[l];
-            const float2 HL = core_value_tan(x, q.a, q.ainv, q.erfcxa, q.C1, RC[l].w);
+            const float2 HL = core_value_tan(x, q.a, q.ainv, q.erfcxa, q.C1, RC[l].w, q.weid);
             const float H = HL.x, L = HL.y;
             // custom derivatives of Sec. 2.1.1:
             //   dH/dx = 2aL - 2xH,  dH/da = 2xL + 2aH - 2/sqrt(pi)
@@ -480,7 +553,7 @@ __device__ __forceinline__ void near_lines(int sb, int se, const LineRec* __rest
             blk[g] += q.acore * H;
             tblk[g] += q.acore * (qt.kA * H + Hx * x * qt.kw + Ha * qt.da);
           } else {
-            blk[g] += q.acore * core_value(x, q.a, q.ainv, q.erfcxa, q.C1, RC[l].w);
+            blk[g] += q.acore * core_value(x, q.a, q.ainv, q.erfcxa, q.C1, RC[l].w, q.weid);
           }
         }
       }
@@ -657,7 +730,14 @@ __global__ __launch_bounds__(256) void k_hjert_f32(int64_t n, const float* __res
   float f = h * r;
   float l = 0.f;
   if (D < q.thr) {
-    f = q.acore * hjert_core_fac<true>(d * q.winv, q.a, q.ainv, q.erfcxa, q.C1, qc.w, &l);
+    if (q.weid != 0.f) {
+      double re, im;
+      weideman_w((double)(d * q.winv), (double)q.a, weid_coeffs(), &re, &im);
+      f = q.acore * (float)re;
+      l = (float)im;
+    } else {
+      f = q.acore * hjert_core_fac<true>(d * q.winv, q.a, q.ainv, q.erfcxa, q.C1, qc.w, &l);
+    }
   } else if (L) {
     hjert_asy_f32(d, q.a, &l);
   }
@@ -714,8 +794,26 @@ hipError_t launch_voigt(const VoigtArgs& A, bool fp64, bool tangent, hipStream_t
   return hipGetLastError();
 }
 
+hipError_t ensure_weideman() {
+  static std::mutex mu;
+  static std::vector<char> done;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> g(mu);
+  if ((int)done.size() <= dev) done.resize(dev + 1, 0);
+  if (done[dev]) return hipSuccess;
+  hipLaunchKernelGGL(k_weid_init, dim3(1), dim3(64), 0, 0);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if ((e = hipDeviceSynchronize()) != hipSuccess) return e;
+  done[dev] = 1;
+  return hipSuccess;
+}
+
 hipError_t launch_hjert_f32(int64_t n, const float* x, const float* a, float* H, float* L,
                             hipStream_t st) {
+  const hipError_t e = ensure_weideman();
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_hjert_f32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, x, a, H, L);
   return hipGetLastError();
 }

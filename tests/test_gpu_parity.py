@@ -62,6 +62,15 @@ def test_hjert_f32_error_map(exo):
     assert np.max(rel[(x[big] ** 2 + a[big] ** 2) >= 111]) < 2e-6
     core = (x ** 2 + a ** 2) < 111
     assert np.max(np.abs(Lg[core] - w.imag[core])) < 2e-6
+    # core pairs of lines with a >= 1e-5 take the rational approximation of
+    # w: relative accuracy of H there, down to the Lorentz tail of the core
+    # (FP32 inputs and outputs included)
+    a32 = a.astype(np.float32).astype(float)
+    rat = core & (a32 >= 1e-5) & (w.real > 1e-30)
+    assert rat.sum() > 1000
+    relr = errH[rat] / w.real[rat]
+    _say(f"  rational-core max rel err {relr.max():.2e}")
+    assert relr.max() < 1e-6, (relr.max(), x[rat][relr.argmax()], a[rat][relr.argmax()])
 
 
 def test_hjert_f64_error_map(exo):
