@@ -94,6 +94,38 @@ def test_jvp_single_directions_without_response(exo):
         assert err < RTOL_GRAD, k
 
 
+def test_jvp_full_config2_against_fp64_differences(exo):
+    """Full configuration-4 size (the config-2 atmosphere: 2 x 1e5 lines,
+    20,000 points, 100 layers), in the launch shapes the bench times: the FP32
+    forward-mode derivative along T0 and along alpha, which runs the tangent
+    Voigt sums with the per-layer far reach and the far tier's cut tangent,
+    against central differences of the plain FP64 spectrum (no FP32 tangent
+    records involved).  The spectrum is far from linear in alpha at this size
+    (near strong lines a step of 1e-4 already moves the central difference
+    by 3-15 % of the derivative, and the oracle's own differences
+    converge to its forward-mode tangent only below 1e-5), so the steps are
+    0.01 K and 1e-6; the FP64 sums resolve such steps to ~1e-9 of the
+    derivative.  Tolerance 1e-3 of max |J e_k|."""
+    _say("flux_jvp full config-2 size vs FP64 central differences")
+    wl = synth.make_config(4, "full")
+    th = np.array(wl.theta, dtype=float)
+    c = _ctx(exo, wl)
+    for k, h in [(0, 0.01), (1, 1e-6)]:
+        e = np.zeros(6)
+        e[k] = 1.0
+        atm, resp = _inputs(exo, wl, th)
+        _, dF = c.flux_jvp(atm, resp, e)
+        Fs = []
+        for sgn in (1.0, -1.0):
+            atm_s, resp_s = _inputs(exo, wl, th + sgn * h * e)
+            Fs.append(c.emission_flux(atm_s, resp_s, "fp64").cpu().numpy())
+        fd = (Fs[0] - Fs[1]) / (2.0 * h)
+        err = _rel(dF.cpu().double().numpy(), fd)
+        _say(f"  direction {k}: max rel err {err:.2e}")
+        assert err < RTOL_GRAD, (k, err)
+    c.close()
+
+
 def test_jvp_vjp_dot_product(exo):
     wl = synth.make_config(4, "small")
     th = wl.theta
