@@ -288,27 +288,38 @@ __device__ inline const double __attribute__((address_space(4)))* uniform_weight
   return (const double __attribute__((address_space(4)))*)(((uint64_t)hi << 32) | lo);
 }
 
-// weid != 0: the rational approximation (uniform per line, so no divergence)
-__device__ __attribute__((noinline)) float core_value(float x, float a, float ainv, float erfcxa,
-                                                      float C1, const double* __restrict__ wn, float weid) {
-  if (weid != 0.f) {
-    double re, im;
-    weideman_w((double)x, (double)a, weid_coeffs(), &re, &im);
-    return (float)re;
+// H = Re w and L = Im w at z = x + ia in the core branch.  For a >= kWeidAmin
+// the rational approximation at z.  Below, w to first order in a about the
+// real axis, where w(x) = e^{-x^2} + i Im w(x) and w'(z) = -2z w(z) + 2i/sqrt(pi):
+//   H = e^{-x^2} + 2a (x Im w(x) - 1/sqrt(pi)),  L = Im w(x) - 2ax e^{-x^2},
+// with Im w(x) from the rational approximation (accurate there relative to
+// |w| ~ Im w) and e^{-x^2} exact.  The neglected terms are O(a^2 x^2)
+// relative (2e-9 at a = 1e-5 over the core); the rational form's own error in
+// H never enters, since H is mostly e^{-x^2} or the small difference
+// x Im w - 1/sqrt(pi), both formed from accurate parts.  a is uniform per
+// line, so the branch does not diverge.
+__device__ inline void core_w(double x, double a, double* H, double* L) {
+  if (a >= kWeidAmin) {
+    weideman_w(x, a, weid_coeffs(), H, L);
+    return;
   }
-  return hjert_core_fac<false>(x, a, ainv, erfcxa, C1, uniform_weights(wn), nullptr);
+  double re, im;
+  weideman_w(x, 0.0, weid_coeffs(), &re, &im);
+  const double ex2 = exp_core(-x * x);
+  *H = ex2 + 2.0 * a * fma(x, im, -0.56418958354775628);
+  *L = im - 2.0 * a * x * ex2;
 }
 
-__device__ __attribute__((noinline)) float2 core_value_tan(float x, float a, float ainv, float erfcxa,
-                                                           float C1, const double* __restrict__ wn, float weid) {
-  if (weid != 0.f) {
-    double re, im;
-    weideman_w((double)x, (double)a, weid_coeffs(), &re, &im);
-    return make_float2((float)re, (float)im);
-  }
-  float L;
-  const float H = hjert_core_fac<true>(x, a, ainv, erfcxa, C1, uniform_weights(wn), &L);
-  return make_float2(H, L);
+__device__ __attribute__((noinline)) float core_value(float x, float a) {
+  double H, L;
+  core_w((double)x, (double)a, &H, &L);
+  return (float)H;
+}
+
+__device__ __attribute__((noinline)) float2 core_value_tan(float x, float a) {
+  double H, L;
+  core_w((double)x, (double)a, &H, &L);
+  return make_float2((float)H, (float)L);
 }
 
 // Grid points of thread (wave w, lane): j = tile0 + (w*G + g)*64 + lane.
@@ -544,7 +555,7 @@ __device__ __forceinline__ void near_lines(int sb, int se, const LineRec* __rest
           const float x = (float)(nuj[g] - nul) * q.winv;
           if (TAN) {
             const LineRecT qt = RT[l];
-            const float2 HL = core_value_tan(x, q.a, q.ainv, q.erfcxa, q.C1, RC[l].w, q.weid);
+            const float2 HL = core_value_tan(x, q.a);
             const float H = HL.x, L = HL.y;
             // custom derivatives of Sec. 2.1.1:
             //   dH/dx = 2aL - 2xH,  dH/da = 2xL + 2aH - 2/sqrt(pi)
@@ -553,7 +564,7 @@ __device__ __forceinline__ void near_lines(int sb, int se, const LineRec* __rest
             blk[g] += q.acore * H;
             tblk[g] += q.acore * (qt.kA * H + Hx * x * qt.kw + Ha * qt.da);
           } else {
-            blk[g] += q.acore * core_value(x, q.a, q.ainv, q.erfcxa, q.C1, RC[l].w, q.weid);
+            blk[g] += q.acore * core_value(x, q.a);
           }
         }
       }
@@ -730,14 +741,10 @@ __global__ __launch_bounds__(256) void k_hjert_f32(int64_t n, const float* __res
   float f = h * r;
   float l = 0.f;
   if (D < q.thr) {
-    if (q.weid != 0.f) {
-      double re, im;
-      weideman_w((double)(d * q.winv), (double)q.a, weid_coeffs(), &re, &im);
-      f = q.acore * (float)re;
-      l = (float)im;
-    } else {
-      f = q.acore * hjert_core_fac<true>(d * q.winv, q.a, q.ainv, q.erfcxa, q.C1, qc.w, &l);
-    }
+    double Hc, Lc;
+    core_w((double)(d * q.winv), (double)q.a, &Hc, &Lc);
+    f = q.acore * (float)Hc;
+    l = (float)Lc;
   } else if (L) {
     hjert_asy_f32(d, q.a, &l);
   }

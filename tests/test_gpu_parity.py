@@ -46,7 +46,7 @@ def maxrel(a, b):
 def test_hjert_f32_error_map(exo):
     _say("hjert_f32 error map")
     xs = np.concatenate([[0.0], np.logspace(-4, 5, 181)])
-    as_ = np.concatenate([[0.0], np.logspace(-4, 5, 91)])
+    as_ = np.concatenate([[0.0], np.logspace(-9, -4.2, 13), np.logspace(-4, 5, 91)])
     X, A = np.meshgrid(xs, as_)
     x, a = X.ravel(), A.ravel()
     H, Lg = exo.hjert_f32(torch.tensor(x, dtype=torch.float32, device="cuda"),
@@ -62,15 +62,20 @@ def test_hjert_f32_error_map(exo):
     assert np.max(rel[(x[big] ** 2 + a[big] ** 2) >= 111]) < 2e-6
     core = (x ** 2 + a ** 2) < 111
     assert np.max(np.abs(Lg[core] - w.imag[core])) < 2e-6
-    # core pairs of lines with a >= 1e-5 take the rational approximation of
-    # w: relative accuracy of H there, down to the Lorentz tail of the core
-    # (FP32 inputs and outputs included)
+    # the core branch: the rational approximation of w for a >= 1e-5, its
+    # first-order expansion about the real axis below; relative accuracy of
+    # H and of L in both parts, down to the Lorentz tail of the core (FP32
+    # inputs and outputs included)
     a32 = a.astype(np.float32).astype(float)
-    rat = core & (a32 >= 1e-5) & (w.real > 1e-30)
-    assert rat.sum() > 1000
-    relr = errH[rat] / w.real[rat]
-    _say(f"  rational-core max rel err {relr.max():.2e}")
-    assert relr.max() < 1e-6, (relr.max(), x[rat][relr.argmax()], a[rat][relr.argmax()])
+    for name, part in (("a >= 1e-5", a32 >= 1e-5), ("a < 1e-5", a32 < 1e-5)):
+        sel = core & part & (w.real > 1e-30)
+        assert sel.sum() > 100
+        relr = errH[sel] / w.real[sel]
+        sel_l = core & part & (np.abs(w.imag) > 1e-30)
+        rell = np.abs(Lg[sel_l] - w.imag[sel_l]) / np.abs(w.imag[sel_l])
+        _say(f"  core {name}: max rel err H {relr.max():.2e}, L {rell.max():.2e}")
+        assert relr.max() < 1e-6, (name, relr.max(), x[sel][relr.argmax()], a[sel][relr.argmax()])
+        assert rell.max() < 1e-6, (name, rell.max())
 
 
 def test_hjert_f64_error_map(exo):
