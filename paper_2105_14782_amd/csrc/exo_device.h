@@ -24,16 +24,16 @@ constexpr double kLn10 = 2.30258509299404568402;
 // Voigt-Hjerting branch switch of the paper's hjert: series for
 // x^2 + a^2 < 111, asymptotic w_2 otherwise (Sec. 2.1.1).
 constexpr double kHjertSwitch = 111.0;
-constexpr int kM916 = 27;                  // series length M
-constexpr float kEta = 0.5f;               // series step eta
-// Core branch of lines with a >= kWeidAmin: Weideman's rational
-// approximation of w with kWeidN terms (Weideman 1994, SIAM J. Numer. Anal.
-// 31, 1497), whose H stays within 2.4e-7 relative over x^2 + a^2 < 111 there.
+constexpr int kM916 = 27;                  // series length M (plain FP64 form)
+// Core branch of the FP32 sum: Weideman's rational approximation of w with
+// kWeidN terms (Weideman 1994, SIAM J. Numer. Anal. 31, 1497) at z for
+// a >= kWeidAmin (H within 2.4e-7 relative over x^2 + a^2 < 111 there), and
+// on the real axis, continued to first order in a, below.
 constexpr int kWeidN = 32;
 constexpr double kWeidAmin = 1e-5;
 
 // Records written by the line-parameter kernel for one (line, layer) and read
-// uniformly (scalar loads) by the Voigt-sum kernel.  Wing branch in physical
+// uniformly (staged per wave through LDS) by the Voigt-sum kernel.  Wing branch in physical
 // variables: with D = dnu^2 + gamma^2 and r = 1/D, the real part of the
 // asymptotic w_2 (Eq. asywofz, n = 2) divided by sqrt(2 pi) beta is exactly
 //   (gamma/pi) r [1 + 3b r + (15b^2 - 4bg) r^2 + (105b^3 - 60b^2 g) r^3
@@ -47,34 +47,10 @@ struct LineRec {
   float thr;      // 2 beta^2 * 111: core branch iff D < thr
   float winv;     // 1 / (sqrt2 beta)
   float a;        // gamma / (sqrt2 beta)
-  float erfcxa;   // erfcx(a)
   float acore;    // amplitude / (sqrt(2 pi) beta): contribution = acore * H(x, a)
-  float C1;       // sum_n w_n of LineCore  (S1 = e^{-x^2} C1)
-  float ainv;     // 1 / a (infinite for a = 0, where it is not used)
-  float weid;     // 1: the core branch uses the rational approximation of w
-                  // (a >= kWeidAmin); 0: the Algorithm-916 series
+  float pad[4];
 };
 static_assert(sizeof(LineRec) == 64, "LineRec layout");
-
-// Series weights of the core branch for one (line, layer):
-// w_n = e^{-eta^2 n^2} / (eta^2 n^2 + a^2), n = 1..27 (w[27..31] = 0), in
-// FP64 because e^{-eta^2 n^2} falls below the FP32 range for n >= 19.
-struct LineCore {
-  double w[32];
-};
-static_assert(sizeof(LineCore) == 256, "LineCore layout");
-
-// e^{-eta^2 n^2} for eta = 1/2, n = 1..27.
-__device__ constexpr double kGauss916[27] = {
-    0.77880078307140488, 0.36787944117144233, 0.10539922456186433, 0.018315638888734179,
-    0.0019304541362277093, 0.00012340980408667956, 4.7851173921290088e-06,
-    1.1253517471925912e-07, 1.6052280551856116e-09, 1.3887943864964021e-11,
-    7.2877240958196922e-14, 2.3195228302435696e-16, 4.4777324417183015e-19,
-    5.2428856633634639e-22, 3.7233631217505106e-25, 1.6038108905486379e-28,
-    4.1900931944943974e-32, 6.6396771995807348e-36, 6.3815034480607908e-40,
-    3.7200759760208361e-44, 1.3153258948574645e-48, 2.8207700884601352e-53,
-    3.6690596154291634e-58, 2.8946403116483003e-63, 1.3851193699226017e-68,
-    4.0200602157433552e-74, 7.0766981754295491e-80};
 
 // d/dT of the same contribution (tangent mode).
 struct LineRecT {
@@ -99,7 +75,7 @@ struct LineRec64 {
 // ---------------------------------------------------------------------------
 __device__ inline void make_line_record(double A, double beta, double gam, double T,
                                         double dlnA, double dbeta, double dgam,
-                                        LineRec* R, LineRecT* RT, LineCore* RC) {
+                                        LineRec* R, LineRecT* RT) {
   const double b = beta * beta, g = gam * gam;
   const double E0 = A * gam / kPi;
   double c[7];
@@ -118,23 +94,8 @@ __device__ inline void make_line_record(double A, double beta, double gam, doubl
   const double winv = 1.0 / (kSqrt2 * beta);
   r.winv = (float)winv;
   r.a = (float)(gam * winv);
-  r.erfcxa = (float)erfcx(gam * winv);
   r.acore = (float)(A * winv / kSqrtPi);
-  {
-    const double a = gam * winv;
-    double c1 = 0.0;
-    LineCore core;
-    for (int n = 1; n <= kM916; ++n) {
-      const double en = 0.5 * n;
-      core.w[n - 1] = kGauss916[n - 1] / (en * en + a * a);
-      c1 += core.w[n - 1];
-    }
-    for (int n = kM916; n < 32; ++n) core.w[n] = 0.0;
-    r.C1 = (float)c1;
-    if (RC) *RC = core;
-  }
-  r.ainv = (float)(1.0 / (gam * winv));
-  r.weid = (gam * winv >= kWeidAmin) ? 1.f : 0.f;
+  for (int k = 0; k < 4; ++k) r.pad[k] = 0.f;
   *R = r;
   if (RT) {
     // db/dT, dg/dT
@@ -169,26 +130,6 @@ __device__ inline void make_line_record(double A, double beta, double gam, doubl
 }
 
 // ---------------------------------------------------------------------------
-// Algorithm-916 series (Eq. algo916) with eta = 1/2, M = 27.  With
-// Lout != nullptr also the imaginary part (App. C), read as
-//   L = -e^{-x^2} erfcx(a) sin 2xa + (2 eta x/pi) e^{-x^2} sinc(2ax/pi)
-//       + (2 eta/pi) [a sin(2ax) S1 - S4/2 + S5/2],
-// the reading that reproduces the Dawson limit L(x, 0) = 2 D(x)/sqrt(pi).
-//
-// Evaluation: the Gaussians factorise exactly,
-//   e^{-(eta n -/+ x)^2} = e^{-x^2} e^{-eta^2 n^2} X^{+/-n},  X = e^x,
-// so with the per-(line, layer) weights w_n = e^{-eta^2 n^2}/(eta^2 n^2 + a^2)
-// and C1 = sum_n w_n,
-//   S1 = e^{-x^2} C1,  S2 + S3 = e^{-x^2} sum_n w_n (X^n + X^-n),
-//   S5 - S4 = e^{-x^2} sum_n (eta n) w_n (X^n - X^-n).
-// c_n = X^n + X^-n obeys c_{n+1} = (X + 1/X) c_n - c_{n-1}, one FMA per term
-// in FP64, where e^{-x^2} X^27 (x^2 + a^2 < 111) stays in range; its
-// x-derivative e_n = n (X^n - X^-n) obeys the derivative of that recurrence,
-// e_{n+1} = (X + 1/X) e_n + (X - 1/X) c_n - e_{n-1}, so that
-// S5 - S4 = e^{-x^2} eta sum_n w_n e_n needs no multiplication by eta n.
-// sin 2ax and cos 2ax come from sin ax, cos ax by the double-angle formulas.
-// Same terms and same M as the series; only the order of operations differs.
-// ---------------------------------------------------------------------------
 // e^t for the core branch's arguments (|t| <= 112, far from over- and
 // underflow): t = k ln2 + r with |r| <= ln2/2 (Cody-Waite reduction with a
 // two-part ln2), e^r by its Taylor series to r^9 (truncation below 1.1e-11
@@ -209,55 +150,6 @@ __device__ __forceinline__ double exp_core(double t) {
   p = fma(p, r, 1.0);
   p = fma(p, r, 1.0);
   return ldexp(p, (int)k);
-}
-
-template <bool WANT_L, typename WeightPtr>
-__device__ __forceinline__ float hjert_core_fac(float xf, float af, float ainv, float erfcxa, float C1,
-                                                WeightPtr wn, float* Lout) {
-  constexpr double twoeta_pi = 1.0 / kPi;  // 2 eta / pi
-  const double x = (double)xf;
-  const double ex2 = exp_core(-x * x);
-  const double X = exp_core(x);
-  // 1/X: hardware reciprocal and two Newton steps (X lies in [e^-10.6, e^10.6])
-  double Y = __builtin_amdgcn_rcp(X);
-  Y = fma(Y, fma(-X, Y, 1.0), Y);
-  Y = fma(Y, fma(-X, Y, 1.0), Y);
-  const double k = X + Y, kp = X - Y;
-  // c_n = X^n + X^-n and e_n = n (X^n - X^-n) = dc_n/dx
-  double c0 = 2.0, c1 = k, e0 = 0.0, e1 = kp, sc = 0.0, se = 0.0;
-  // 9 terms per iteration: one batch of scalar weight loads each; a full
-  // unroll measured 18 % slower in the tangent kernel (more spills), 3 terms
-  // 3.5 % slower in the forward kernel
-#pragma unroll 9
-  for (int n = 1; n <= kM916; ++n) {
-    const double w = wn[n - 1];
-    sc = fma(w, c1, sc);
-    if (WANT_L) {
-      se = fma(w, e1, se);
-      const double e2 = fma(k, e1, fma(kp, c1, -e0));
-      e0 = e1;
-      e1 = e2;
-    }
-    const double c2 = fma(k, c1, -c0);
-    c0 = c1;
-    c1 = c2;
-  }
-  const double sd = 0.5 * se;  // sum_n (eta n) w_n (X^n - X^-n)
-  const double a = (double)af, S1 = ex2 * (double)C1;
-  const float ax = af * xf;
-  float sax, cax;
-  sincosf(ax, &sax, &cax);
-  const double sa = (double)sax, ca = (double)cax;
-  const double s2xa = 2.0 * sa * ca, c2xa = 1.0 - 2.0 * sa * sa;
-  // (2 eta x sin(ax)/pi) e^{-x^2} sinc(ax/pi) = (2 eta/pi) e^{-x^2} sin^2(ax)/a
-  const double t2 = (ax != 0.f) ? twoeta_pi * ex2 * sa * sa * (double)ainv : 0.0;
-  const double H = ex2 * (double)erfcxa * c2xa + t2 + twoeta_pi * a * (-c2xa * S1 + 0.5 * ex2 * sc);
-  if (WANT_L) {
-    // (2 eta x/pi) e^{-x^2} sinc(2ax/pi) = (2 eta/pi) e^{-x^2} sin(2ax)/(2a)
-    const double t2l = (ax != 0.f) ? twoeta_pi * ex2 * s2xa * (0.5 * (double)ainv) : twoeta_pi * ex2 * x;
-    *Lout = (float)(-ex2 * (double)erfcxa * s2xa + t2l + twoeta_pi * (a * s2xa * S1 + 0.5 * ex2 * sd));
-  }
-  return (float)H;
 }
 
 // Asymptotic branch Re/Im of w_2^asy(x + i a) in FP32 (diagnostics).

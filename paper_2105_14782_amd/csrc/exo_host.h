@@ -31,7 +31,7 @@ struct DevBuf {
 // synchronous API; the serving engine owns one per slot.
 struct Workspace {
   static constexpr size_t kStageDoubles = 1 << 14;
-  DevBuf rec, rect, core, rec64, tier, tau, taut, part, part_t, F0, F0bar, mid, midbar, Fup, taubar, layer,
+  DevBuf rec, rect, rec64, tier, tau, taut, part, part_t, F0, F0bar, mid, midbar, Fup, taubar, layer,
       col, taps, partT, partX, partR, gout, params, mlines, mpart, mrows0, mrows1, lossF, lossC, lossP;
   // tier.p when its gamma^2 maximum bits are known to be zero (every FP32
   // Voigt chunk leaves them zero); otherwise they are cleared before use
@@ -46,7 +46,7 @@ struct Workspace {
   int reserve(DevBuf& b, size_t bytes);
   void bind_arena(char* base, size_t cap);
   std::vector<DevBuf*> bufs() {
-    return {&rec, &rect, &core, &rec64, &tier, &tau, &taut, &part, &part_t, &F0, &F0bar, &mid, &midbar,
+    return {&rec, &rect, &rec64, &tier, &tau, &taut, &part, &part_t, &F0, &F0bar, &mid, &midbar,
             &Fup, &taubar, &layer, &col, &taps, &partT, &partX, &partR, &gout, &params,
             &mlines, &mpart, &mrows0, &mrows1, &lossF, &lossC, &lossP};
   }
@@ -60,7 +60,7 @@ struct Workspace {
   int stage_params(const double* host, size_t n, double* dev, hipStream_t st);
   size_t bytes() const {
     size_t b = 0;
-    for (const DevBuf* x : {&rec, &rect, &core, &rec64, &tier, &tau, &taut, &part, &part_t, &F0, &F0bar, &mid,
+    for (const DevBuf* x : {&rec, &rect, &rec64, &tier, &tau, &taut, &part, &part_t, &F0, &F0bar, &mid,
                             &midbar, &Fup, &taubar, &layer, &col, &taps, &partT, &partX, &partR,
                             &gout, &params})
       b += x->cap;
@@ -106,7 +106,7 @@ struct exo_ctx {
 namespace exo {
 struct OpacityPlan {
   int nlc;  // layers per record chunk
-  size_t rec, core, rect, rec64, part, part_t;
+  size_t rec, rect, rec64, part, part_t;
   size_t tier;  // FP32 far tier: per layer of a chunk, the gamma^2 maximum bits and the squared reach
 };
 OpacityPlan plan_opacity(int64_t n_lines, int nlay, int64_t ng, bool fp64, bool tangent);

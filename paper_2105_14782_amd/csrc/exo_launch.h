@@ -30,7 +30,6 @@ struct VoigtArgs {
   int64_t n_lines;
   const LineRec* rec;
   const LineRecT* rect;
-  const LineCore* core;
   const LineRec64* rec64;
   int64_t lines_per_split;
   int ksplit;
@@ -162,7 +161,7 @@ struct RespDev {
 hipError_t launch_line_records(const LinesDev& L, const double* T_lay, const double* P_lay,
                                const double* col_lay, double T_one, double P_one, double amp_scale,
                                int layer0, int nlay,
-                               LineRec* rec, LineRecT* rect, LineCore* core, LineRec64* rec64,
+                               LineRec* rec, LineRecT* rect, LineRec64* rec64,
                                unsigned int* g2max_bits, hipStream_t st);
 // Squared far-tier reach of each layer from its records and g2max_bits,
 // which it resets to zero for the next chunk.

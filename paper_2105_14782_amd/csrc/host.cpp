@@ -440,13 +440,12 @@ static void split_plan(int64_t ng, int nl, int64_t n_lines, bool fp64, int64_t* 
 OpacityPlan exo::plan_opacity(int64_t n_lines, int nlay, int64_t ng, bool fp64, bool tangent) {
   OpacityPlan P{};
   const size_t per_layer = (size_t)n_lines * (fp64 ? sizeof(LineRec64)
-                                                   : sizeof(LineRec) + sizeof(LineCore) + (tangent ? sizeof(LineRecT) : 0));
+                                                   : sizeof(LineRec) + (tangent ? sizeof(LineRecT) : 0));
   P.nlc = (int)std::max<size_t>(1, std::min<size_t>((size_t)nlay, kRecBudget / per_layer));
   if (fp64) {
     P.rec64 = (size_t)P.nlc * n_lines * sizeof(LineRec64);
   } else {
     P.rec = (size_t)P.nlc * n_lines * sizeof(LineRec);
-    P.core = (size_t)P.nlc * n_lines * sizeof(LineCore);
     P.tier = (size_t)kMaxLayers * (sizeof(unsigned int) + sizeof(float) + sizeof(int));
     if (tangent) P.rect = (size_t)P.nlc * n_lines * sizeof(LineRecT);
   }
@@ -471,7 +470,6 @@ OpacityPlan exo::plan_opacity_all(const exo_ctx* c, const exo_atmos* a, int64_t 
   for (int m = 0; m < a->n_species; ++m) {
     const OpacityPlan Q = plan_opacity(c->sp[a->species[m]].n, a->n_layers, gl, fp64, tangent);
     P.rec = std::max(P.rec, Q.rec);
-    P.core = std::max(P.core, Q.core);
     P.rect = std::max(P.rect, Q.rect);
     P.rec64 = std::max(P.rec64, Q.rec64);
     P.tier = std::max(P.tier, Q.tier);
@@ -485,7 +483,6 @@ int exo::reserve_opacity(Workspace& ws, const OpacityPlan& P) {
   int rc;
   if (P.rec64 && (rc = ws.reserve(ws.rec64, P.rec64))) return rc;
   if (P.rec && (rc = ws.reserve(ws.rec, P.rec))) return rc;
-  if (P.core && (rc = ws.reserve(ws.core, P.core))) return rc;
   if (P.tier && (rc = ws.reserve(ws.tier, P.tier))) return rc;
   if (P.rect && (rc = ws.reserve(ws.rect, P.rect))) return rc;
   if (P.part && (rc = ws.reserve(ws.part, P.part))) return rc;
@@ -515,7 +512,6 @@ int exo::species_opacity(exo_ctx* c, Workspace& ws, const Species& sp, const dou
     HIP_TRY(launch_line_records(L, d_T, d_P, d_col, T_one, P_one, amp_scale, l0, nl,
                                 fp64 ? nullptr : (LineRec*)ws.rec.p,
                                 (!fp64 && tangent) ? (LineRecT*)ws.rect.p : nullptr,
-                                fp64 ? nullptr : (LineCore*)ws.core.p,
                                 fp64 ? (LineRec64*)ws.rec64.p : nullptr, g2bits, st));
     if (!fp64) HIP_TRY(launch_far_reach((const LineRec*)ws.rec.p, sp.n, nl, tangent, g2bits, reach2, t3, st));
     VoigtArgs A{};
@@ -525,7 +521,6 @@ int exo::species_opacity(exo_ctx* c, Workspace& ws, const Species& sp, const dou
     A.n_lines = sp.n;
     A.rec = (const LineRec*)ws.rec.p;
     A.rect = (const LineRecT*)ws.rect.p;
-    A.core = (const LineCore*)ws.core.p;
     A.rec64 = (const LineRec64*)ws.rec64.p;
     A.far_reach2 = reach2;
     A.far_t3 = t3;
@@ -996,7 +991,7 @@ size_t exo::estimate_workspace(const exo_ctx* c, const exo_atmos* a, const exo_r
     t += mb;
   } else {
     const OpacityPlan P = plan_opacity_all(c, a, gl, fp64, vjp);
-    for (size_t b : {P.rec, P.core, P.rect, P.rec64, P.part, P.part_t, P.tier}) t += b ? R(b) : 0;
+    for (size_t b : {P.rec, P.rect, P.rec64, P.part, P.part_t, P.tier}) t += b ? R(b) : 0;
   }
   int64_t nmid = 0;
   if (r) {

@@ -22,7 +22,6 @@ __global__ __launch_bounds__(256) void k_line_records(LinesDev L, const double* 
                                                       double amp_scale, int layer0,
                                                       LineRec* __restrict__ rec,
                                                       LineRecT* __restrict__ rect,
-                                                      LineCore* __restrict__ core,
                                                       LineRec64* __restrict__ rec64,
                                                       unsigned int* __restrict__ g2max_bits) {
   const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -55,8 +54,7 @@ __global__ __launch_bounds__(256) void k_line_records(LinesDev L, const double* 
       A = kAmpMax;
       dlnA = 0.0;
     }
-    make_line_record(A, s.beta, s.gam, T, dlnA, s.dbeta, s.dgam, rec + o, rect ? rect + o : nullptr,
-                     core + o);
+    make_line_record(A, s.beta, s.gam, T, dlnA, s.dbeta, s.dgam, rec + o, rect ? rect + o : nullptr);
     g2 = (float)(s.gam * s.gam);
   }
   if (g2max_bits) {
@@ -275,19 +273,6 @@ __device__ inline const double __attribute__((address_space(4)))* weid_coeffs() 
   return (const double __attribute__((address_space(4)))*)(const double*)g_weid;
 }
 
-// Core evaluations are kept out of line: their FP64 temporaries would
-// otherwise set the register budget of the whole loop and cut occupancy.
-// The weight pointer is wave-uniform; reading it into scalar registers and
-// addressing it as constant memory lets the weights arrive by scalar loads
-// (in the tangent kernel this costs spills around the call but measured 2.4 %
-// faster than vector loads of the same weights).
-__device__ inline const double __attribute__((address_space(4)))* uniform_weights(const double* wn) {
-  const uint64_t p = (uint64_t)wn;
-  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)p);
-  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(p >> 32));
-  return (const double __attribute__((address_space(4)))*)(((uint64_t)hi << 32) | lo);
-}
-
 // H = Re w and L = Im w at z = x + ia in the core branch.  For a >= kWeidAmin
 // the rational approximation at z.  Below, w to first order in a about the
 // real axis, where w(x) = e^{-x^2} + i Im w(x) and w'(z) = -2z w(z) + 2i/sqrt(pi):
@@ -310,6 +295,8 @@ __device__ inline void core_w(double x, double a, double* H, double* L) {
   *L = im - 2.0 * a * x * ex2;
 }
 
+// Core evaluations are out-of-line calls: their FP64 temporaries would
+// otherwise set the register budget of the line loops and cut occupancy.
 __device__ __attribute__((noinline)) float core_value(float x, float a) {
   double H, L;
   core_w((double)x, (double)a, &H, &L);
@@ -469,7 +456,6 @@ __device__ __forceinline__ void far_lines(int sb, int se, const LineRec* __restr
 template <bool TAN, int G>
 __device__ __forceinline__ void near_lines(int sb, int se, const LineRec* __restrict__ R,
                                            const LineRecT* __restrict__ RT,
-                                           const LineCore* __restrict__ RC,
                                            const double* __restrict__ nuc, const double (&nuj)[G],
                                            NearStage* __restrict__ st, int lane,
                                            float (&s)[G], float (&c)[G], float (&ts)[G],
@@ -593,7 +579,6 @@ __device__ __forceinline__ void voigt_body(const VoigtArgs& A) {
   const int le = min(lb + (int)A.lines_per_split, (int)A.n_lines);
   const LineRec* __restrict__ R = A.rec + (int64_t)y * A.n_lines;
   const LineRecT* __restrict__ RT = TAN ? A.rect + (int64_t)y * A.n_lines : nullptr;
-  const LineCore* __restrict__ RC = A.core + (int64_t)y * A.n_lines;
   int i0, i1;
   near_range<G>(A, tile0, w, lb, le, i0, i1);
   // base of the far tier's FP32 offsets: the wave's first point (uniform)
@@ -609,7 +594,7 @@ __device__ __forceinline__ void voigt_body(const VoigtArgs& A) {
     const int se = seg == 0 ? i0 : le;
     if (!TAN || A.far_t3[y]) far_lines<TAN, true, G>(sb, se, R, RT, A.nu_c, nuj, nuw, &stage[w].far, lane, s, c, ts, tc);
     else far_lines<TAN, false, G>(sb, se, R, RT, A.nu_c, nuj, nuw, &stage[w].far, lane, s, c, ts, tc);
-    if (seg == 0) near_lines<TAN, G>(i0, i1, R, RT, RC, A.nu_c, nuj, &stage[w].near, lane, s, c, ts, tc);
+    if (seg == 0) near_lines<TAN, G>(i0, i1, R, RT, A.nu_c, nuj, &stage[w].near, lane, s, c, ts, tc);
   }
   if (A.near_pairs && lane == 0) {
     const int64_t npts = min((int64_t)G * 64, A.ng - (tile0 + (int64_t)w * G * 64));
@@ -727,8 +712,7 @@ __global__ __launch_bounds__(256) void k_hjert_f32(int64_t n, const float* __res
   if (i >= n) return;
   const double beta = 1.0 / kSqrt2;
   LineRec q;
-  LineCore qc;
-  make_line_record(kSqrtPi, beta, (double)a[i], 1.0, 0.0, 0.0, 0.0, &q, nullptr, &qc);
+  make_line_record(kSqrtPi, beta, (double)a[i], 1.0, 0.0, 0.0, 0.0, &q, nullptr);
   const float d = x[i];
   const float D = fmaf(d, d, q.gam2);
   const float r = __builtin_amdgcn_rcpf(D);
@@ -764,11 +748,11 @@ __global__ __launch_bounds__(256) void k_hjert_f64(int64_t n, const double* __re
 // ---------------------------------------------------------------------------
 hipError_t launch_line_records(const LinesDev& L, const double* T_lay, const double* P_lay,
                                const double* col_lay, double T_one, double P_one, double amp_scale,
-                               int layer0, int nlay, LineRec* rec, LineRecT* rect, LineCore* core,
-                               LineRec64* rec64, unsigned int* g2max_bits, hipStream_t st) {
+                               int layer0, int nlay, LineRec* rec, LineRecT* rect, LineRec64* rec64,
+                               unsigned int* g2max_bits, hipStream_t st) {
   dim3 grid((unsigned)((L.n + 255) / 256), (unsigned)nlay);
   hipLaunchKernelGGL(k_line_records, grid, dim3(256), 0, st, L, T_lay, P_lay, col_lay, T_one, P_one,
-                     amp_scale, layer0, rec, rect, core, rec64, rec64 ? nullptr : g2max_bits);
+                     amp_scale, layer0, rec, rect, rec64, rec64 ? nullptr : g2max_bits);
   return hipGetLastError();
 }
 
