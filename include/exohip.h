@@ -9,9 +9,11 @@
  *     (Sec. 2.1.1, Eq. thermal), pressure + natural Lorentz width
  *     (Eq. gammaexomol, Eq. naturalgamma);
  *   - Voigt profile through the Voigt-Hjerting function H = Re w(x+ia),
- *     evaluated with the paper's "hjert": the Algorithm-916 series with
- *     eta = 0.5, M = 27 for x^2 + a^2 < 111 and the asymptotic w_2 otherwise
- *     (Sec. 2.1.1, Eq. algo916, Eq. asywofz);
+ *     with the branches of the paper's "hjert" (Sec. 2.1.1): the asymptotic
+ *     w_2 for x^2 + a^2 >= 111 (Eq. asywofz); inside, the plain FP64 form
+ *     takes the Algorithm-916 series (eta = 0.5, M = 27, Eq. algo916) and the
+ *     FP32 form a rational approximation of w (Weideman 1994), continued to
+ *     first order in a from the real axis for a < 1e-5;
  *   - cross-section sum over lines (Eq. crosssec), layer optical depth
  *     (Sec. 3, Eq. dtau_line2) plus H2-H2 CIA (Sec. 2.4, Eq. taucont);
  *   - pure-absorption two-stream transfer F_n = T_n F_{n+1} + (1-T_n) S_n
@@ -285,7 +287,7 @@ int exo_broaden(exo_ctx* ctx, int64_t grid_begin, int64_t grid_len,
                 void* stream);
 
 /* The Voigt-Hjerting function exactly as the FP32 hot kernel evaluates it
- * (Sec. 2.1.1 hjert; App. C ljert with the Dawson-consistent reading):
+ * (Sec. 2.1.1 hjert branches; the core as described at the top of this file):
  * x_dev, a_dev device [n] float (a >= 0); H_dev device [n] float;
  * L_dev device [n] float or NULL (Im w).  Errors: EXO_EINVAL, EXO_EDEVICE. */
 int exo_hjert_f32(int64_t n, const float* x_dev, const float* a_dev, float* H_dev,
