@@ -21,8 +21,8 @@ constexpr double kSqrtPi = 1.77245385090551602730;
 constexpr double kSqrt2 = 1.41421356237309504880;
 constexpr double kLn10 = 2.30258509299404568402;
 
-// Voigt-Hjerting branch switch of the paper's hjert: series for
-// x^2 + a^2 < 111, asymptotic w_2 otherwise (Sec. 2.1.1).
+// Voigt-Hjerting branch switch of the paper's hjert: core (the series in the
+// paper) for x^2 + a^2 < 111, asymptotic w_2 otherwise (Sec. 2.1.1).
 constexpr double kHjertSwitch = 111.0;
 constexpr int kM916 = 27;                  // series length M (plain FP64 form)
 // Core branch of the FP32 sum: Weideman's rational approximation of w with

@@ -215,15 +215,16 @@ __device__ inline void neumaier(float& s, float& c, float v) {
 }
 
 // ---------------------------------------------------------------------------
-// Rational approximation of w for the core branch of lines with a >= kWeidAmin
-// (Weideman 1994):  w(z) ~ u/sqrt(pi) + 2 u^2 sum_{n=1..N} c_n Z^(n-1), with
+// Rational approximation of w for the core branch (Weideman 1994):
+//   w(z) ~ u/sqrt(pi) + 2 u^2 sum_{n=1..N} c_n Z^(n-1), with
 // u = 1/(L - iz), Z = (L + iz)/(L - iz), L = (N/sqrt2)^(1/2), and
 // c_n = (1/2M) sum_{|k|<M} f(t_k) cos(n theta_k), theta_k = k pi/M,
 // t_k = L tan(theta_k/2), f(t) = e^{-t^2} (L^2 + t^2), M = 2N.  About half the
-// operations of the series (no exponentials, no sine), with H and L = Im w
-// from the same evaluation.  Its absolute error is a small fraction of |w|,
-// which near the real axis far from the centre (small a) is much larger
-// than H; below kWeidAmin the series keeps the relative accuracy.
+// operations of the paper's Algorithm-916 series (no exponentials, no sine),
+// with H and L = Im w from the same evaluation.  Its absolute error is a
+// small fraction of |w|, which near the real axis far from the centre
+// (small a) is much larger than H; below kWeidAmin it is therefore used on
+// the real axis only (core_w below).
 // ---------------------------------------------------------------------------
 __device__ double g_weid[kWeidN];  // c_1 .. c_N, filled once per device
 
@@ -448,7 +449,7 @@ __device__ __forceinline__ void far_lines(int sb, int se, const LineRec* __restr
   }
 }
 
-// Near lines [sb, se): full wing polynomial, Algorithm-916 series in the core.
+// Near lines [sb, se): full wing polynomial, core_w in the core.
 // The line loop evaluates the wing and only marks the pairs inside the core
 // (x^2 + a^2 < 111), one bit per line of the chunk per point; the marked
 // pairs are evaluated after the loop, line by line in chunk order, with less
@@ -624,7 +625,7 @@ __device__ __forceinline__ void voigt_body(const VoigtArgs& A) {
 // The kernels.  Both ask for 8 waves per SIMD (64 registers per lane): the
 // line loops stay free of spills (the tangent kernel's land around the
 // out-of-line core call and the chunk bookkeeping), and the extra waves hide
-// the scalar-load latency of the line records: the tangent kernel measured
+// memory and LDS latency: with scalar-loaded line records the tangent kernel measured
 // 2.6 % faster than at 7 waves (72 registers), 9 % faster than at 5 (96, its
 // spill-free budget); the forward kernel 10 % faster than at 7.
 template <bool TAN, int G>
