@@ -33,10 +33,12 @@ PEAK_FP32_TFLOPS = 157.3      # MI355X published FP32 vector peak (packed FMA)
 # 12 + 1, tangent polynomial 14 + 1, two accumulations 2.  Far tier
 # (polynomial truncated below FP32 rounding): offset 1, D 2, 1/D 1, value
 # polynomial 4, tangent polynomial 6 (4 in layers where it stops at r^3),
-# two accumulations 4.
+# two accumulations 4.  Beyond the outer reach both polynomials stop at r^2:
+# value 2, tangent 2.
 FLOPS_PER_EVAL_NEAR = 34.0
 FLOPS_PER_EVAL_FAR = 18.0
 FLOPS_PER_EVAL_FAR_CUT = 16.0   # far pair whose tangent polynomial stops at r^3
+FLOPS_PER_EVAL_OUTER = 12.0     # far pair beyond the outer reach
 
 
 def parse():
@@ -555,6 +557,7 @@ def main():
     nl, kms, kevals = ctx.profile_read()
     knear = ctx.profile_read_near()
     kcut = ctx.profile_read_far_cut()
+    kout = ctx.profile_read_far_outer()
     ctx.profile(False)
     lat = np.array([a.elapsed_time(b) for a, b in ev])
     ms = 1e3 * T / args.steps
@@ -597,8 +600,8 @@ def main():
     tjvp = (time.perf_counter() - tj0) / max(3, args.steps // 2)
 
     avg_launch_ms = kms / max(nl, 1)
-    flops_per_launch = (FLOPS_PER_EVAL_NEAR * knear + FLOPS_PER_EVAL_FAR * (kevals - knear - kcut)
-                        + FLOPS_PER_EVAL_FAR_CUT * kcut) / max(nl, 1)
+    flops_per_launch = (FLOPS_PER_EVAL_NEAR * knear + FLOPS_PER_EVAL_FAR * (kevals - knear - kcut - kout)
+                        + FLOPS_PER_EVAL_FAR_CUT * kcut + FLOPS_PER_EVAL_OUTER * kout) / max(nl, 1)
     achieved = flops_per_launch / (avg_launch_ms * 1e-3) / 1e12
     out = {
         "metric": METRIC,
@@ -631,8 +634,9 @@ def main():
                      "launches": nl, "evals_per_launch": kevals / max(nl, 1),
                      "near_fraction": knear / max(kevals, 1.0),
                      "far_cut_fraction": kcut / max(kevals, 1.0),
+                     "outer_fraction": kout / max(kevals, 1.0),
                      "flops_per_eval": {"near": FLOPS_PER_EVAL_NEAR, "far": FLOPS_PER_EVAL_FAR,
-                                        "far_cut": FLOPS_PER_EVAL_FAR_CUT},
+                                        "far_cut": FLOPS_PER_EVAL_FAR_CUT, "outer": FLOPS_PER_EVAL_OUTER},
                      "evals_per_s": kevals / (kms * 1e-3)},
     }
     ctx.close()

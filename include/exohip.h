@@ -317,11 +317,16 @@ int exo_profile_read(exo_ctx* ctx, int64_t* n_launches, double* total_ms,
  * truncated far-tier polynomial.  Synchronises like exo_profile_read.
  * Errors: EXO_EINVAL, EXO_EDEVICE. */
 int exo_profile_read_near(exo_ctx* ctx, double* near_evals);
-/* Of the far-tier evaluations of the profiled tangent-mode launches, the
- * number whose T-derivative polynomial stops at r^3 (layers whose truncation
- * bound allows it; the others keep the r^4 term).  Synchronises like
- * exo_profile_read.  Errors: EXO_EINVAL, EXO_EDEVICE. */
+/* Of the far-tier evaluations of the profiled tangent-mode launches inside
+ * the outer reach, the number whose T-derivative polynomial stops at r^3
+ * (layers whose truncation bound allows it; the others keep the r^4 term).
+ * Synchronises like exo_profile_read.  Errors: EXO_EINVAL, EXO_EDEVICE. */
 int exo_profile_read_far_cut(exo_ctx* ctx, double* far_cut_evals);
+/* Of the far-tier evaluations of the profiled FP32 launches, the number
+ * beyond the layer's outer reach, summed with the value (and tangent)
+ * polynomial cut after r^2.  Synchronises like exo_profile_read.
+ * Errors: EXO_EINVAL, EXO_EDEVICE. */
+int exo_profile_read_far_outer(exo_ctx* ctx, double* outer_evals);
 
 #ifdef __cplusplus
 }

@@ -100,6 +100,7 @@ def load_library(path: str = LIB_PATH):
         "exo_profile_read": ([V, ctypes.POINTER(I64), ctypes.POINTER(D), ctypes.POINTER(D)], I),
         "exo_profile_read_near": ([V, ctypes.POINTER(D)], I),
         "exo_profile_read_far_cut": ([V, ctypes.POINTER(D)], I),
+        "exo_profile_read_far_outer": ([V, ctypes.POINTER(D)], I),
         "exo_cross_section_modit": ([V, I, D, D, I, D, V, V], I),
         "exo_select_lines": ([V, I, D, ctypes.POINTER(ExoAtmos), D, _c_dp, I, I, V,
                               ctypes.POINTER(I64), V], I),

@@ -296,10 +296,17 @@ class Context:
         return ev.value
 
     def profile_read_far_cut(self) -> float:
-        """Far-tier pair evaluations of the profiled tangent launches whose
-        T-derivative polynomial stops at r^3."""
+        """Far-tier pair evaluations of the profiled tangent launches, inside
+        the outer reach, whose T-derivative polynomial stops at r^3."""
         ev = ctypes.c_double()
         L.check(self._lib.exo_profile_read_far_cut(self._h, ctypes.byref(ev)))
+        return ev.value
+
+    def profile_read_far_outer(self) -> float:
+        """Far-tier pair evaluations of the profiled FP32 launches beyond the
+        outer reach (value and tangent polynomials cut after r^2)."""
+        ev = ctypes.c_double()
+        L.check(self._lib.exo_profile_read_far_outer(self._h, ctypes.byref(ev)))
         return ev.value
 
 

@@ -45,8 +45,9 @@ struct VoigtArgs {
   double* part64;
   const float* far_reach2;         // [nlay] squared far-tier reach of each layer (cm^-2)
   const int* far_t3;               // [nlay] tangent mode: 1 if far pairs keep the tangent's r^4 term
+  const float* far_outer2;         // [nlay] squared outer reach (>= far_reach2; FLT_MAX: none)
   unsigned long long* near_pairs;  // profiling only: [0] pairs summed by the near tier,
-                                   // [1] far pairs whose tangent stops at r^3
+                                   // [1] far pairs whose tangent stops at r^3, [2] outer pairs
 };
 
 // Per-layer quantities of one atmosphere.
@@ -163,10 +164,10 @@ hipError_t launch_line_records(const LinesDev& L, const double* T_lay, const dou
                                int layer0, int nlay,
                                LineRec* rec, LineRecT* rect, LineRec64* rec64,
                                unsigned int* g2max_bits, hipStream_t st);
-// Squared far-tier reach of each layer from its records and g2max_bits,
-// which it resets to zero for the next chunk.
+// Squared far-tier and outer reaches of each layer from its records and
+// g2max_bits, which it resets to zero for the next chunk.
 hipError_t launch_far_reach(const LineRec* rec, int64_t n_lines, int nlay, bool tangent,
-                            unsigned int* g2max_bits, float* reach2, int* t3, hipStream_t st);
+                            unsigned int* g2max_bits, float* reach2, int* t3, float* outer2, hipStream_t st);
 hipError_t launch_voigt(const VoigtArgs& A, bool fp64, bool tangent, hipStream_t st);
 // Fills the coefficient table of the core branch's rational approximation on
 // the current device (once per process and device; synchronises the device).

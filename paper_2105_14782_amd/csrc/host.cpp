@@ -331,8 +331,8 @@ extern "C" int exo_profile_enable(exo_ctx* c, int on) {
   }
   c->prof.clear();
   if (on) {
-    if (c->prof_near.reserve(2 * sizeof(unsigned long long))) return EXO_ENOMEM;
-    HIP_TRY(hipMemset(c->prof_near.p, 0, 2 * sizeof(unsigned long long)));
+    if (c->prof_near.reserve(3 * sizeof(unsigned long long))) return EXO_ENOMEM;
+    HIP_TRY(hipMemset(c->prof_near.p, 0, 3 * sizeof(unsigned long long)));
   }
   c->profile = on != 0;
   return EXO_OK;
@@ -357,6 +357,17 @@ extern "C" int exo_profile_read_far_cut(exo_ctx* c, double* far_cut_evals) {
   unsigned long long n[2] = {0, 0};
   if (c->prof_near.p) HIP_TRY(hipMemcpy(n, c->prof_near.p, sizeof(n), hipMemcpyDeviceToHost));
   *far_cut_evals = (double)n[1];
+  return EXO_OK;
+}
+
+extern "C" int exo_profile_read_far_outer(exo_ctx* c, double* outer_evals) {
+  if (!c) return set_err(EXO_EINVAL, "ctx is NULL");
+  if (!outer_evals) return set_err(EXO_EINVAL, "outer_evals is NULL");
+  HIP_TRY(hipSetDevice(c->device));
+  for (auto& p : c->prof) HIP_TRY(hipEventSynchronize(p.b));
+  unsigned long long n[3] = {0, 0, 0};
+  if (c->prof_near.p) HIP_TRY(hipMemcpy(n, c->prof_near.p, sizeof(n), hipMemcpyDeviceToHost));
+  *outer_evals = (double)n[2];
   return EXO_OK;
 }
 
@@ -446,7 +457,7 @@ OpacityPlan exo::plan_opacity(int64_t n_lines, int nlay, int64_t ng, bool fp64, 
     P.rec64 = (size_t)P.nlc * n_lines * sizeof(LineRec64);
   } else {
     P.rec = (size_t)P.nlc * n_lines * sizeof(LineRec);
-    P.tier = (size_t)kMaxLayers * (sizeof(unsigned int) + sizeof(float) + sizeof(int));
+    P.tier = (size_t)kMaxLayers * (sizeof(unsigned int) + sizeof(float) + sizeof(int) + sizeof(float));
     if (tangent) P.rect = (size_t)P.nlc * n_lines * sizeof(LineRecT);
   }
   // partial sums (the FP32 sum always passes its far-line state through
@@ -499,11 +510,13 @@ int exo::species_opacity(exo_ctx* c, Workspace& ws, const Species& sp, const dou
   int rc;
   if ((rc = reserve_opacity(ws, P))) return rc;
   const int nlc = P.nlc;
-  // tier buffer: [kMaxLayers] gamma^2 maximum bits, then [kMaxLayers]
-  // squared reach; k_far_reach zeroes the bits of its chunk after use
+  // tier buffer: [kMaxLayers] gamma^2 maximum bits, then [kMaxLayers] each
+  // squared reach, t3 flag and squared outer reach; k_far_reach zeroes the
+  // bits of its chunk after use
   unsigned int* g2bits = fp64 ? nullptr : (unsigned int*)ws.tier.p;
   float* reach2 = fp64 ? nullptr : (float*)(g2bits + kMaxLayers);
   int* t3 = fp64 ? nullptr : (int*)(g2bits + 2 * kMaxLayers);
+  float* outer2 = fp64 ? nullptr : (float*)(g2bits + 3 * kMaxLayers);
   if (!fp64 && ws.tier_zeroed != ws.tier.p)
     HIP_TRY(hipMemsetAsync(g2bits, 0, (size_t)kMaxLayers * sizeof(unsigned int), st));
   ws.tier_zeroed = nullptr;
@@ -513,7 +526,7 @@ int exo::species_opacity(exo_ctx* c, Workspace& ws, const Species& sp, const dou
                                 fp64 ? nullptr : (LineRec*)ws.rec.p,
                                 (!fp64 && tangent) ? (LineRecT*)ws.rect.p : nullptr,
                                 fp64 ? (LineRec64*)ws.rec64.p : nullptr, g2bits, st));
-    if (!fp64) HIP_TRY(launch_far_reach((const LineRec*)ws.rec.p, sp.n, nl, tangent, g2bits, reach2, t3, st));
+    if (!fp64) HIP_TRY(launch_far_reach((const LineRec*)ws.rec.p, sp.n, nl, tangent, g2bits, reach2, t3, outer2, st));
     VoigtArgs A{};
     A.nu = d_nu;
     A.ng = ng;
@@ -524,6 +537,7 @@ int exo::species_opacity(exo_ctx* c, Workspace& ws, const Species& sp, const dou
     A.rec64 = (const LineRec64*)ws.rec64.p;
     A.far_reach2 = reach2;
     A.far_t3 = t3;
+    A.far_outer2 = outer2;
     A.nlay = nl;
     A.out_scale = (float)(1.0 / amp_scale);
     A.out_scale64 = 1.0 / amp_scale;

@@ -106,6 +106,15 @@ constexpr int kChunk = 32;
 // more near pairs against fewer FMAs on every far pair.  Where the Lorentz
 // widths are small (v ~ 0) the two reaches nearly coincide.
 //
+// Farther out the c_2 term itself falls below the same targets: beyond a
+// second, per-layer distance (the outer reach, searched the same way over
+// R .. 1e4 R with c_2 and t_2 added to the dropped terms) the value and the
+// tangent both stop at r^2, two FMAs less per pair.  The bound per pair is
+// the same in every tier, so the error of the sum does not grow.  With a
+// band a few tens of cm^-1 wide and Doppler widths ~0.01 cm^-1 most pairs
+// are outer ones; layers whose Lorentz widths are wide (high pressure) may
+// have none (outer reach FLT_MAX).
+//
 // The Doppler width is proportional to the line centre (Eq. thermal) and the
 // lines are sorted by centre, so the last line of a layer has the largest
 // beta^2.  The far lines of a wave are a prefix and a suffix of the sorted
@@ -114,6 +123,7 @@ constexpr int kChunk = 32;
 constexpr double kFarU = 2e-5;
 constexpr double kFarEpsV = 4.8e-9;
 constexpr double kFarEpsT = 1.42e-8;
+constexpr double kFarOuterSpan = 9.210340371976184;  // ln 1e4: outer reach <= 1e4 R
 
 // bound of u^p v^q over the far pairs of a layer (gr = g_max / R)
 __device__ inline double far_monomial(int p, int q, double U, double gr) {
@@ -127,32 +137,46 @@ __device__ inline double far_monomial(int p, int q, double U, double gr) {
   return m / den;
 }
 
-// t3: the tangent keeps its r^4 term (else it stops at r^3)
-__device__ inline bool far_bound_holds(double U, double gr, bool t3) {
+// Bound of the wing terms a tier drops: the value keeps c_0 .. c_(kv-1), the
+// tangent t_0 .. t_(kt-1) (kt = 8: no tangent).  A_k bounds |c_k r^k| (in
+// units of E0 r) by the monomials u^p v^q (u = beta^2 r, v = gamma^2 r) of
+// c_k; Av_k is the same with one more factor v.  Dropping t_k costs at most
+// k (A_k + Av_(k-1)): the T-derivative of the c_k term (degree k in u, v) and
+// the gamma^2-derivative of r in the c_(k-1) term.
+__device__ inline bool far_bound_holds(double U, double gr, int kv, int kt) {
   auto M = [&](int p, int q) { return far_monomial(p, q, U, gr); };
-  // A_k: sum of |coefficient| x monomial bound of c_k r^k; Av_k: the same times v
-  const double A3 = 105.0 * M(3, 0) + 60.0 * M(2, 1), A4 = 48.0 * M(2, 2) + 840.0 * M(3, 1);
-  const double A5 = 1680.0 * M(3, 2), A6 = 960.0 * M(3, 3);
-  const double Av2 = 15.0 * M(2, 1) + 4.0 * M(1, 2);
-  const double Av3 = 105.0 * M(3, 1) + 60.0 * M(2, 2), Av4 = 48.0 * M(2, 3) + 840.0 * M(3, 2);
-  const double Av5 = 1680.0 * M(3, 3), Av6 = 960.0 * M(3, 4);
-  const double ev = A3 + A4 + A5 + A6;
-  double et = 4.0 * A4 + 5.0 * A5 + 6.0 * A6 + 4.0 * Av3 + 5.0 * Av4 + 6.0 * Av5 + 7.0 * Av6;
-  if (!t3) et += 3.0 * A3 + 3.0 * Av2;
+  const double A[8] = {0.0,
+                       3.0 * M(1, 0),
+                       15.0 * M(2, 0) + 4.0 * M(1, 1),
+                       105.0 * M(3, 0) + 60.0 * M(2, 1),
+                       48.0 * M(2, 2) + 840.0 * M(3, 1),
+                       1680.0 * M(3, 2),
+                       960.0 * M(3, 3),
+                       0.0};
+  const double Av[7] = {0.0,  // t_0 is always kept
+                        3.0 * M(1, 1),
+                        15.0 * M(2, 1) + 4.0 * M(1, 2),
+                        105.0 * M(3, 1) + 60.0 * M(2, 2),
+                        48.0 * M(2, 3) + 840.0 * M(3, 2),
+                        1680.0 * M(3, 3),
+                        960.0 * M(3, 4)};
+  double ev = 0.0, et = 0.0;
+  for (int k = kv; k < 7; ++k) ev += A[k];
+  for (int k = kt; k < 8; ++k) et += (double)k * (A[k] + Av[k - 1]);
   return ev <= kFarEpsV && et <= kFarEpsT;
 }
 
 // Two-level search on ln R in [lo, hi] by the 64 lanes of a wave: the
-// smallest candidate (to ln(225)/4096) at which the bound holds; fails if
+// smallest candidate (to (hi - lo)/4096) at which the bound holds; fails if
 // it does not hold at hi.
-__device__ inline bool far_search(double bmax, double gmax, double lo, double hi, bool t3, int k,
+__device__ inline bool far_search(double bmax, double gmax, double lo, double hi, int kv, int kt, int k,
                                   double* x) {
   double a = lo, b = hi;
   bool found = false;
   for (int level = 0; level < 2; ++level) {
     const double xk = a + (b - a) * (double)(k + 1) * (1.0 / 64.0);
     const double R = exp(xk);
-    const unsigned long long ok = __ballot(far_bound_holds(bmax / R, gmax / R, t3));
+    const unsigned long long ok = __ballot(far_bound_holds(bmax / R, gmax / R, kv, kt));
     if (ok == 0ull) break;
     const int k1 = __builtin_ctzll(ok);
     const double bn = a + (b - a) * (double)(k1 + 1) * (1.0 / 64.0);
@@ -164,11 +188,16 @@ __device__ inline bool far_search(double bmax, double gmax, double lo, double hi
   return found;
 }
 
-// One 64-lane block per layer of the chunk.  t3[y] (tangent mode): 1 if
-// far pairs keep the tangent's r^4 term.
+// One 64-lane block per layer of the chunk.  reach2[y]: squared distance
+// beyond which a line is summed with the value polynomial cut after r^3;
+// t3[y] (tangent mode): 1 if those pairs keep the tangent's r^4 term;
+// outer2[y] (>= reach2[y]; FLT_MAX if none): squared distance beyond which
+// the value and the tangent both stop at r^2 (the value alone in forward
+// mode).
 __global__ __launch_bounds__(64) void k_far_reach(const LineRec* __restrict__ rec, int64_t n_lines,
                                                   int tangent, unsigned int* __restrict__ g2max_bits,
-                                                  float* __restrict__ reach2, int* __restrict__ t3) {
+                                                  float* __restrict__ reach2, int* __restrict__ t3,
+                                                  float* __restrict__ outer2) {
   const int y = blockIdx.x, k = threadIdx.x;
   // beta_max^2 from the threshold 2 * 111 beta^2, with margin for its rounding
   const double bmax = (double)rec[(int64_t)y * n_lines + n_lines - 1].thr * (1.001 / (2.0 * kHjertSwitch));
@@ -177,21 +206,27 @@ __global__ __launch_bounds__(64) void k_far_reach(const LineRec* __restrict__ re
   const double lo = log(2.0 * kHjertSwitch * bmax), hi = log(bmax / kFarU);
   double x = hi;
   int keep3 = 1;
-  // an unknown maximum (not a finite non-negative float) keeps the fixed-U reach
+  float ro = __FLT_MAX__;
+  // an unknown maximum (not a finite non-negative float) keeps the fixed-U
+  // reach and no outer zone
   if (bits <= 0x7f7fffffu && lo < hi) {
     const double gmax = (double)__uint_as_float(bits) * 1.001;
-    double x3, x2;
-    if (far_search(bmax, gmax, lo, hi, true, k, &x3)) x = x3;
-    if (tangent && far_search(bmax, gmax, lo, hi, false, k, &x2) && x2 <= x + 0.6931471805599453) {
+    double x3, x2, xo;
+    if (far_search(bmax, gmax, lo, hi, 3, 4, k, &x3)) x = x3;
+    if (tangent && far_search(bmax, gmax, lo, hi, 3, 3, k, &x2) && x2 <= x + 0.6931471805599453) {
       x = x2;
       keep3 = 0;
     }
+    if (far_search(bmax, gmax, x, x + kFarOuterSpan, 2, tangent ? 2 : 8, k, &xo))
+      ro = (float)(exp(xo) * (1.0 + 1e-6));
   }
   if (k == 0) {
     g2max_bits[y] = 0u;
     // rounded up so that the FP32 value does not undercut the bound
-    reach2[y] = (float)(exp(x) * (1.0 + 1e-6));
+    const float r = (float)(exp(x) * (1.0 + 1e-6));
+    reach2[y] = r;
     t3[y] = keep3;
+    outer2[y] = fmaxf(ro, r);
   }
 }
 
@@ -324,13 +359,17 @@ __device__ __forceinline__ void load_points(const VoigtArgs& A, int64_t tile0, i
 
 // Near lines [i0, i1) of wave w within [lb, le); the rest of [lb, le) is far.
 template <int G>
-__device__ __forceinline__ void near_range(const VoigtArgs& A, int64_t tile0, int w, int lb, int le, int& i0, int& i1) {
+__device__ __forceinline__ void tier_ranges(const VoigtArgs& A, int64_t tile0, int w, int lb, int le, int& o0,
+                                            int& i0, int& i1, int& o1) {
   const int64_t jw = tile0 + (int64_t)w * G * 64, jlast = A.ng - 1;
   const double lo = A.nu[jw < jlast ? jw : jlast];
   const double hi = A.nu[jw + G * 64 - 1 < jlast ? jw + G * 64 - 1 : jlast];
   const double reach = sqrt((double)A.far_reach2[blockIdx.y]);
-  i0 = __builtin_amdgcn_readfirstlane(search_sorted<false>(A.nu_c, lb, le, lo - reach));
+  const double outer = sqrt((double)A.far_outer2[blockIdx.y]);  // >= reach
+  o0 = __builtin_amdgcn_readfirstlane(search_sorted<false>(A.nu_c, lb, le, lo - outer));
+  i0 = __builtin_amdgcn_readfirstlane(search_sorted<false>(A.nu_c, o0, le, lo - reach));
   i1 = __builtin_amdgcn_readfirstlane(search_sorted<true>(A.nu_c, i0, le, hi + reach));
+  o1 = __builtin_amdgcn_readfirstlane(search_sorted<true>(A.nu_c, i1, le, hi + outer));
 }
 
 // Far lines [sb, se): truncated wing polynomial, no core branch.
@@ -340,8 +379,9 @@ __device__ __forceinline__ void near_range(const VoigtArgs& A, int64_t tile0, in
 // reach) this errs by ~1e-7 relative, like rounding the FP64 offset.  One
 // reciprocal serves two points: r0 = D1 / (D0 D1), r1 = D0 / (D0 D1) (D >= the
 // squared reach, so the product stays a normal FP32 number for any physical
-// width).  T3: the tangent keeps its r^4 term (false where the layer's
-// bound allows the tangent to stop at r^3).
+// width).  KT: terms the tangent keeps (4: up to r^4; 3: up to r^3 where the
+// layer's bound allows; 2: up to r^2, outer lines, where the value also stops
+// at r^2).  The forward sum ignores KT except for KT = 2.
 //
 // Each chunk of 64 far lines passes through a slice of LDS private to the
 // wave: lane i loads line i's value and tangent coefficients and gamma^2 with
@@ -384,7 +424,7 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <bool TAN, bool T3, int G>
+template <bool TAN, int KT, int G>
 __device__ __forceinline__ void far_lines(int sb, int se, const LineRec* __restrict__ R,
                                           const LineRecT* __restrict__ RT,
                                           const double* __restrict__ nuc, const double (&nuj)[G], double nuw,
@@ -430,11 +470,12 @@ __device__ __forceinline__ void far_lines(int sb, int se, const LineRec* __restr
       }
 #pragma unroll
       for (int g = 0; g < G; ++g) {
-        const float h = fmaf(fmaf(e.z, r[g], e.y), r[g], e.x);
+        const float h = KT == 2 ? fmaf(e.y, r[g], e.x) : fmaf(fmaf(e.z, r[g], e.y), r[g], e.x);
         blk[g] = fmaf(h, r[g], blk[g]);
         if (TAN) {
-          const float ht = T3 ? fmaf(fmaf(fmaf(t.w, r[g], t.z), r[g], t.y), r[g], t.x)
-                              : fmaf(fmaf(t.z, r[g], t.y), r[g], t.x);
+          const float ht = KT == 4   ? fmaf(fmaf(fmaf(t.w, r[g], t.z), r[g], t.y), r[g], t.x)
+                           : KT == 3 ? fmaf(fmaf(t.z, r[g], t.y), r[g], t.x)
+                                     : fmaf(t.y, r[g], t.x);
           tblk[g] = fmaf(ht, r[g], tblk[g]);
         }
       }
@@ -580,8 +621,8 @@ __device__ __forceinline__ void voigt_body(const VoigtArgs& A) {
   const int le = min(lb + (int)A.lines_per_split, (int)A.n_lines);
   const LineRec* __restrict__ R = A.rec + (int64_t)y * A.n_lines;
   const LineRecT* __restrict__ RT = TAN ? A.rect + (int64_t)y * A.n_lines : nullptr;
-  int i0, i1;
-  near_range<G>(A, tile0, w, lb, le, i0, i1);
+  int o0, i0, i1, o1;
+  tier_ranges<G>(A, tile0, w, lb, le, o0, i0, i1, o1);
   // base of the far tier's FP32 offsets: the wave's first point (uniform)
   const int64_t jw = tile0 + (int64_t)w * G * 64;
   const double nuw = A.nu[jw < A.ng ? jw : A.ng - 1];
@@ -591,10 +632,12 @@ __device__ __forceinline__ void voigt_body(const VoigtArgs& A) {
   for (int g = 0; g < G; ++g) s[g] = c[g] = ts[g] = tc[g] = 0.f;
 #pragma unroll 1
   for (int seg = 0; seg < 2; ++seg) {
-    const int sb = seg == 0 ? lb : i1;
-    const int se = seg == 0 ? i0 : le;
-    if (!TAN || A.far_t3[y]) far_lines<TAN, true, G>(sb, se, R, RT, A.nu_c, nuj, nuw, &stage[w].far, lane, s, c, ts, tc);
-    else far_lines<TAN, false, G>(sb, se, R, RT, A.nu_c, nuj, nuw, &stage[w].far, lane, s, c, ts, tc);
+    // outer lines [lb, o0) and [o1, le); far lines [o0, i0) and [i1, o1)
+    const int ob = seg == 0 ? lb : o1, oe = seg == 0 ? o0 : le;
+    const int sb = seg == 0 ? o0 : i1, se = seg == 0 ? i0 : o1;
+    far_lines<TAN, 2, G>(ob, oe, R, RT, A.nu_c, nuj, nuw, &stage[w].far, lane, s, c, ts, tc);
+    if (!TAN || A.far_t3[y]) far_lines<TAN, 4, G>(sb, se, R, RT, A.nu_c, nuj, nuw, &stage[w].far, lane, s, c, ts, tc);
+    else far_lines<TAN, 3, G>(sb, se, R, RT, A.nu_c, nuj, nuw, &stage[w].far, lane, s, c, ts, tc);
     if (seg == 0) near_lines<TAN, G>(i0, i1, R, RT, A.nu_c, nuj, &stage[w].near, lane, s, c, ts, tc);
   }
   if (A.near_pairs && lane == 0) {
@@ -602,7 +645,8 @@ __device__ __forceinline__ void voigt_body(const VoigtArgs& A) {
     if (npts > 0) {
       atomicAdd(A.near_pairs, (unsigned long long)(i1 - i0) * (unsigned long long)npts);
       if (TAN && !A.far_t3[y])
-        atomicAdd(A.near_pairs + 1, (unsigned long long)((le - lb) - (i1 - i0)) * (unsigned long long)npts);
+        atomicAdd(A.near_pairs + 1, (unsigned long long)((o1 - o0) - (i1 - i0)) * (unsigned long long)npts);
+      atomicAdd(A.near_pairs + 2, (unsigned long long)((le - lb) - (o1 - o0)) * (unsigned long long)npts);
     }
   }
 
@@ -758,9 +802,9 @@ hipError_t launch_line_records(const LinesDev& L, const double* T_lay, const dou
 }
 
 hipError_t launch_far_reach(const LineRec* rec, int64_t n_lines, int nlay, bool tangent,
-                            unsigned int* g2max_bits, float* reach2, int* t3, hipStream_t st) {
+                            unsigned int* g2max_bits, float* reach2, int* t3, float* outer2, hipStream_t st) {
   hipLaunchKernelGGL(k_far_reach, dim3((unsigned)nlay), dim3(64), 0, st, rec, n_lines, tangent ? 1 : 0, g2max_bits,
-                     reach2, t3);
+                     reach2, t3, outer2);
   return hipGetLastError();
 }
 

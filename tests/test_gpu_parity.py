@@ -15,7 +15,7 @@ import torch
 
 import synth
 from oracle import oracle as O
-from far_tier import far_reach2
+from far_tier import far_outer2, far_reach2
 
 pytestmark = pytest.mark.gpu
 
@@ -192,8 +192,9 @@ def test_cross_section_far_lines_only(exo):
 
 
 def _near_pairs_expected(ll, T, nu, wave_points=256, P=1.0):
-    """Pairs the near tier should take: lines within the layer's far reach of
-    the points a wave owns."""
+    """(pairs the near tier should take, outer pairs): lines within the
+    layer's far reach of the points a wave owns, and lines beyond its outer
+    reach from all of them."""
     kKB, kMU, kC = 1.380649e-16, 1.66053906660e-24, 2.99792458e10
     beta_last = math.sqrt(kKB * T / (ll.mass_amu * kMU)) * ll.nu_c[-1] / kC
     thr = float(np.float32(2.0 * 111.0 * beta_last * beta_last))
@@ -201,35 +202,46 @@ def _near_pairs_expected(ll, T, nu, wave_points=256, P=1.0):
     gam = ll.alpha_ref * (T / 296.0) ** (-ll.n_texp) * P
     gmax = float(np.max((gam * gam).astype(np.float32))) * 1.001
     reach = math.sqrt(far_reach2(bmax, gmax)[0])
-    total = 0
+    outer = math.sqrt(far_outer2(bmax, gmax))
+    total = n_out = 0
     for j0 in range(0, nu.size, wave_points):
         j1 = min(j0 + wave_points, nu.size) - 1
         lo, hi = nu[j0] - reach, nu[j1] + reach
         n_near = np.searchsorted(ll.nu_c, hi, side="right") - np.searchsorted(ll.nu_c, lo, side="left")
         total += int(n_near) * (j1 - j0 + 1)
-    return total
+        lo, hi = nu[j0] - outer, nu[j1] + outer
+        n_in = np.searchsorted(ll.nu_c, hi, side="right") - np.searchsorted(ll.nu_c, lo, side="left")
+        n_out += int(ll.n - n_in) * (j1 - j0 + 1)
+    return total, n_out
 
 
 @pytest.mark.parametrize("n_nu", [1000, 4097])
 def test_near_tier_pair_count(exo, n_nu):
-    """The kernel's near/far split equals the classification it is designed to
-    make (lines sorted by centre, reach from the largest Doppler width)."""
+    """The kernel's near / far / outer split equals the classification it is
+    designed to make (lines sorted by centre, reaches from the largest Doppler
+    and Lorentz widths)."""
     rng = np.random.default_rng(n_nu)
     ll = _lines(rng, rng.uniform(4330.0, 4370.0, 3000))
     nu = np.linspace(4340.0, 4360.0, n_nu)
     c = exo.Context(0)
     c.set_lines(0, ll)
     c.set_grid(nu)
+    n_outer = 0
     for T in (300.0, 2000.0):
         c.profile(True)
         c.cross_section(0, T, 1.0, "fp32")
         n, ms, evals = c.profile_read()
         near = c.profile_read_near()
+        outer = c.profile_read_far_outer()
         c.profile(False)
-        exp = _near_pairs_expected(ll, T, nu)
-        _say(f"  n_nu={n_nu} T={T}: near {near:.0f} expected {exp} of {evals:.0f}")
+        exp, exp_out = _near_pairs_expected(ll, T, nu)
+        _say(f"  n_nu={n_nu} T={T}: near {near:.0f} expected {exp}, outer {outer:.0f} expected {exp_out} "
+             f"of {evals:.0f}")
         assert evals == ll.n * n_nu
         assert near == exp
+        assert outer == exp_out
+        n_outer += outer
+    assert n_outer > 0
 
 
 # ------------------------------------------------------------------ emission
