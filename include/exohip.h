@@ -13,7 +13,9 @@
  *     w_2 for x^2 + a^2 >= 111 (Eq. asywofz); inside, the plain FP64 form
  *     takes the Algorithm-916 series (eta = 0.5, M = 27, Eq. algo916) and the
  *     FP32 form a rational approximation of w (Weideman 1994), continued to
- *     first order in a from the real axis for a < 1e-5;
+ *     first order in a from the real axis for a < 1e-5; the FP32 form drops,
+ *     for lines far from a group of grid points, the terms of w_2 that a
+ *     per-layer bound keeps below FP32 rounding (two distance tiers);
  *   - cross-section sum over lines (Eq. crosssec), layer optical depth
  *     (Sec. 3, Eq. dtau_line2) plus H2-H2 CIA (Sec. 2.4, Eq. taucont);
  *   - pure-absorption two-stream transfer F_n = T_n F_{n+1} + (1-T_n) S_n

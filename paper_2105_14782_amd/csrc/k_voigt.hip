@@ -84,7 +84,8 @@ constexpr int kChunk = 32;
 // and v = gamma^2 r, c_k r^k is a homogeneous polynomial of degree k in
 // (u, v): 1, 3u, 15u^2 - 4uv, 105u^3 - 60u^2 v, 48u^2 v^2 - 840u^3 v,
 // 1680u^3 v^2, -960u^3 v^3.  A far pair keeps k <= 2 of the value and k <= 3
-// of the tangent, and skips the core test.
+// of the tangent (k <= 1 of both beyond the outer reach), and skips the core
+// test.
 //
 // A line farther than `reach` from every grid point of a wave has, at each
 // of them, D >= reach^2 + gamma^2, so every monomial obeys
@@ -117,8 +118,8 @@ constexpr int kChunk = 32;
 //
 // The Doppler width is proportional to the line centre (Eq. thermal) and the
 // lines are sorted by centre, so the last line of a layer has the largest
-// beta^2.  The far lines of a wave are a prefix and a suffix of the sorted
-// list, found by binary search.
+// beta^2.  The far (and, within them, the outer) lines of a wave are a
+// prefix and a suffix of the sorted list, found by binary search.
 // ---------------------------------------------------------------------------
 constexpr double kFarU = 2e-5;
 constexpr double kFarEpsV = 4.8e-9;
@@ -357,7 +358,8 @@ __device__ __forceinline__ void load_points(const VoigtArgs& A, int64_t tile0, i
   }
 }
 
-// Near lines [i0, i1) of wave w within [lb, le); the rest of [lb, le) is far.
+// Line ranges of wave w within [lb, le): near [i0, i1), far [o0, i0) and
+// [i1, o1), outer [lb, o0) and [o1, le).
 template <int G>
 __device__ __forceinline__ void tier_ranges(const VoigtArgs& A, int64_t tile0, int w, int lb, int le, int& o0,
                                             int& i0, int& i1, int& o1) {
