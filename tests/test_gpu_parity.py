@@ -191,6 +191,35 @@ def test_cross_section_far_lines_only(exo):
         assert err < 2e-6
 
 
+@pytest.mark.parametrize("P", [1e-6, 1e-2, 1.0, 30.0, 300.0])
+def test_cross_section_outer_tier_pressures(exo, P):
+    """Lines spread over a band ten times wider than the grid: from low
+    pressure (most pairs beyond the outer reach, both polynomials cut after
+    r^2) to 300 bar (wide Lorentz widths, outer reach pushed out or absent),
+    the FP32 cross-section matches the exact profile to FP32 accuracy and the
+    kernel's outer-pair count matches the host statement of the rule."""
+    _say(f"cross_section outer tier P={P}")
+    rng = np.random.default_rng(int(1e3 * P) % 997 + 5)
+    ll = _lines(rng, rng.uniform(4200.0, 4500.0, 1500))
+    nu = np.linspace(4340.0, 4370.0, 3001)
+    c = exo.Context(0)
+    c.set_lines(0, ll)
+    c.set_grid(nu)
+    T = 1500.0
+    c.profile(True)
+    got = c.cross_section(0, T, P, "fp32").cpu().double().numpy()
+    outer = c.profile_read_far_outer()
+    c.profile(False)
+    _, exp_out = _near_pairs_expected(ll, T, nu, P=P)
+    ref = O.cross_section(ll, T, P, nu)
+    err = maxrel(got, ref)
+    _say(f"  outer pairs {outer:.0f} (expected {exp_out}) of {ll.n * nu.size}, max rel err {err:.2e}")
+    assert outer == exp_out
+    if P <= 1.0:
+        assert outer > 0.5 * ll.n * nu.size
+    assert err < 2e-6
+
+
 def _near_pairs_expected(ll, T, nu, wave_points=256, P=1.0):
     """(pairs the near tier should take, outer pairs): lines within the
     layer's far reach of the points a wave owns, and lines beyond its outer
