@@ -71,7 +71,10 @@ typedef enum {
   EXO_QR_POWER = 0, /* q_r(T) = (T/296)^k, qr_params = {k}, n_qr = 1      */
   EXO_QR_TABLE = 1  /* linear interpolation of Q on T nodes:
                        qr_params = {T_0..T_{n-1}, Q_0..Q_{n-1}}, n_qr = 2n,
-                       nodes ascending, n >= 2; q_r = Q(T)/Q(296)        */
+                       nodes ascending, n >= 2; q_r = Q(T)/Q(296);
+                       outside [T_0, T_{n-1}] the end value is held, and
+                       d ln q_r/dT is the derivative from the right (zero
+                       for T < T_0 and T >= T_{n-1}) (Sec. 2.3)           */
 } exo_qr_kind;
 
 typedef enum {

@@ -97,10 +97,11 @@ def voigt_profile(dnu, beta, gamma):
 # ---------------------------------------------------------------------------
 
 def qr_ratio(T, kind: int, params):
-    """q_r(T) = Q(T)/Q(T_ref).
+    """q_r(T) = Q(T)/Q(T_ref) (Sec. 2.3: Q interpolated on a grid of temperatures).
 
     kind 0: (T/T_ref)^k with params = [k].
-    kind 1: linear interpolation of a Q(T) table, params = [T_0..T_{n-1}, Q_0..Q_{n-1}].
+    kind 1: linear interpolation of a Q(T) table, params = [T_0..T_{n-1}, Q_0..Q_{n-1}];
+    outside [T_0, T_{n-1}] the end value is held (np.interp).
     """
     T = np.asarray(T, float)
     params = np.asarray(params, float)
@@ -112,6 +113,9 @@ def qr_ratio(T, kind: int, params):
 
 
 def dlog_qr_dT(T, kind: int, params):
+    """d ln q_r / dT of qr_ratio.  For the table, the derivative from the right:
+    the slope of the interval [T_i, T_{i+1}) holding T, and zero where the end
+    value is held (T < T_0 or T >= T_{n-1})."""
     T = np.asarray(T, float)
     params = np.asarray(params, float)
     if kind == 0:
@@ -120,6 +124,7 @@ def dlog_qr_dT(T, kind: int, params):
     tn, qn = params[:n], params[n:]
     i = np.clip(np.searchsorted(tn, T, side="right") - 1, 0, n - 2)
     slope = (qn[i + 1] - qn[i]) / (tn[i + 1] - tn[i])
+    slope = np.where((T >= tn[0]) & (T < tn[-1]), slope, 0.0)
     return slope / np.interp(T, tn, qn)
 
 

@@ -34,8 +34,9 @@ __device__ inline void qr_eval(int kind, const double* __restrict__ p, int nq, d
     }
     const double s = (qn[i + 1] - qn[i]) / (tn[i + 1] - tn[i]);
     if (slope) *slope = s;
-    // constant extrapolation outside the table, like np.interp
-    if (t <= tn[0]) { if (slope) *slope = 0.0; return qn[0]; }
+    // constant extrapolation outside the table, like np.interp; the slope is
+    // the derivative from the right (zero where the end value is held)
+    if (t < tn[0]) { if (slope) *slope = 0.0; return qn[0]; }
     if (t >= tn[n - 1]) { if (slope) *slope = 0.0; return qn[n - 1]; }
     return qn[i] + s * (t - tn[i]);
   };

@@ -408,3 +408,114 @@ def test_loss_gradient_by_central_differences():
         fd = (O.gaussian_loss(O.emission_flux(wl, wl.theta + e), data, sig)
               - O.gaussian_loss(O.emission_flux(wl, wl.theta - e), data, sig)) / (2 * h)
         assert g[k] == pytest.approx(fd, rel=1e-5, abs=1e-8 * abs(L))
+
+
+# ---------------------------------------------------------------- column, IP width, Q(T) table
+
+def test_column_factor_is_number_density_times_hydrostatic_thickness():
+    """Eq. dtau_line2: the molecules of species m above unit area in a layer are
+    n_m dz, with n_m = (X mu / M) P / (k_B T) (X a mass mixing ratio, mu the mean
+    molecular weight, M the molecule's mass) and the hydrostatic thickness
+    dz = H dP / P, H = k_B T / (mu m_u g) (Sec. 3).  T and mu cancel; the
+    route keeps them to show it.  Constants written out in cgs here."""
+    kB, m_u, bar = 1.380649e-16, 1.66053906660e-24, 1.0e6
+    cases = [(1e-3, 2.3e-4, 900.0, 0.0023, 18.0, 2.33, 10 ** 5.03),
+             (0.7, 0.05, 1300.0, 0.0058, 28.0, 2.33, 10 ** 5.03),
+             (80.0, 6.1, 2400.0, 1e-6, 44.0, 2.9, 2.2e3)]
+    for P, dP, T, X, M, mu, g in cases:
+        n_m = (X * mu / M) * (P * bar) / (kB * T)
+        H = kB * T / (mu * m_u * g)
+        dz = H * dP / P
+        assert float(O.column_factor(dP, X, M, g)) == pytest.approx(n_m * dz, rel=1e-13)
+    # vectorised over layers, as the emission model uses it
+    P = np.logspace(-8, 2, 100)
+    dP = O.layer_dP_bar(P)
+    col = O.column_factor(dP, 0.0023, 18.0, 10 ** 5.03)
+    np.testing.assert_allclose(col, (0.0023 * 2.33 / 18.0) * dP * bar / (2.33 * m_u * 10 ** 5.03), rtol=1e-13)
+
+
+def test_ip_width_is_c_over_R_at_half_maximum():
+    """Sec. 4.2: an instrument of resolving power R has a Gaussian profile whose
+    full width at half maximum is c/R in velocity.  Measured on the output of
+    instrumental() for a delta input (half-maximum crossings located by linear
+    interpolation on a grid 0.01 km/s apart), without calling ip_beta_kms."""
+    c_kms = 299792.458
+    for R in (1e5, 3e4):
+        dv = 0.01
+        n = 10001
+        nu = 4350.0 * np.exp(np.arange(n) * dv / c_kms)   # log-uniform: uniform in velocity
+        j0 = n // 2
+        G = np.zeros(n)
+        G[j0] = 1.0
+        half_reach = int(1.5 * (c_kms / R) / dv)              # 1.5 FWHM either side
+        idx = np.arange(j0 - half_reach, j0 + half_reach + 1)
+        F = O.instrumental(G, nu, idx, R)[0]
+        v = c_kms * np.log(nu[idx])
+        k = int(np.argmax(F))
+        assert idx[k] == j0
+        h = 0.5 * F[k]
+        i = k
+        while F[i] > h:
+            i += 1
+        vr = v[i - 1] + (h - F[i - 1]) * (v[i] - v[i - 1]) / (F[i] - F[i - 1])
+        i = k
+        while F[i] > h:
+            i -= 1
+        vl = v[i] + (h - F[i]) * (v[i + 1] - v[i]) / (F[i + 1] - F[i])
+        assert vr - vl == pytest.approx(c_kms / R, rel=2e-5)
+
+
+def _q_table(nodes, Q):
+    return np.concatenate([nodes, Q(nodes)])
+
+
+def test_partition_table_interpolation_and_derivative():
+    """Sec. 2.3: Q(T) tabulated on temperature nodes and interpolated linearly,
+    q_r = Q(T)/Q(296).  The table samples Q = 41 (T/296)^1.5: exact at the
+    nodes, the weighted mean of the two end values inside an interval, the end
+    value held outside the nodes; d ln q_r/dT against central differences of
+    ln q_r (inside intervals, below and above the nodes) and, at a node, the
+    one-sided difference from the right."""
+    tn = np.array([200.0, 296.0, 500.0, 800.0, 1200.0, 1700.0, 2400.0])
+    Q = lambda T: 41.0 * (np.asarray(T, float) / 296.0) ** 1.5
+    prm = _q_table(tn, Q)
+    np.testing.assert_allclose(O.qr_ratio(tn, 1, prm), (tn / 296.0) ** 1.5, rtol=1e-14)
+    for i in range(tn.size - 1):
+        for f in (0.25, 0.5, 0.9):
+            T = tn[i] + f * (tn[i + 1] - tn[i])
+            expect = ((1 - f) * Q(tn[i]) + f * Q(tn[i + 1])) / Q(296.0)
+            assert float(O.qr_ratio(T, 1, prm)) == pytest.approx(float(expect), rel=1e-13)
+    assert float(O.qr_ratio(150.0, 1, prm)) == pytest.approx(float(Q(200.0) / Q(296.0)), rel=1e-14)
+    assert float(O.qr_ratio(3000.0, 1, prm)) == pytest.approx(float(Q(2400.0) / Q(296.0)), rel=1e-14)
+    lq = lambda T: math.log(float(O.qr_ratio(T, 1, prm)))
+    h = 1e-3
+    for T in (150.0, 250.0, 400.0, 1000.0, 2000.0, 2600.0, 5000.0):
+        fd = (lq(T + h) - lq(T - h)) / (2 * h)
+        assert float(O.dlog_qr_dT(T, 1, prm)) == pytest.approx(fd, rel=1e-7, abs=1e-13), T
+    # at a node: q_r is linear on the interval to its right, so a forward
+    # difference of q_r (not of ln q_r) is exact up to rounding
+    q = lambda T: float(O.qr_ratio(T, 1, prm))
+    for T in (200.0, 500.0, 2400.0):
+        fd_right = (q(T + 1.0) - q(T)) / 1.0
+        assert float(O.dlog_qr_dT(T, 1, prm)) * q(T) == pytest.approx(fd_right, rel=1e-10, abs=1e-15), T
+    # a fine table converges to the power law and its log-derivative k/T
+    fine = np.linspace(150.0, 3000.0, 4001)
+    prm_f = _q_table(fine, Q)
+    T = np.array([233.3, 777.7, 1999.9])
+    np.testing.assert_allclose(O.qr_ratio(T, 1, prm_f), (T / 296.0) ** 1.5, rtol=2e-6)
+    np.testing.assert_allclose(O.dlog_qr_dT(T, 1, prm_f), 1.5 / T, rtol=1e-3)
+
+
+def test_strength_tangent_with_partition_table():
+    """d ln S/dT (Eq. Slog) with a tabulated q_r against central differences of
+    ln S, including temperatures outside the table where q_r is held."""
+    from dataclasses import replace
+    wl = synth.make_config(2, "tiny")
+    tn = np.array([300.0, 600.0, 1000.0, 1500.0, 2000.0])
+    ll = replace(wl.lines[0], qr_kind=1, qr_params=_q_table(tn, lambda T: 7.0 + 0.02 * np.asarray(T) ** 1.2))
+    h = 1e-3
+    for T in (250.0, 777.0, 1234.0, 2500.0):
+        st = O.line_state(ll, T, 0.3)
+        lp = np.log(O.line_state(ll, T + h, 0.3).S)
+        lm = np.log(O.line_state(ll, T - h, 0.3).S)
+        np.testing.assert_allclose(st.dlnS_dT, (lp - lm) / (2 * h), rtol=1e-6, atol=1e-12)

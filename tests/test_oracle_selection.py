@@ -11,6 +11,7 @@ import math
 from dataclasses import replace
 
 import numpy as np
+import pytest
 
 import synth
 from oracle import oracle as O
@@ -72,3 +73,29 @@ def test_stronger_lines_never_drop():
     assert np.all(k2 >= k1) and k2.sum() >= k1.sum()
     k3 = SEL.select_lines(replace(ll, S0=ll.S0 * 10.0), lx, atm, 1700.0)[0]
     assert np.all(k3 >= k1)
+
+
+def test_line_centre_depth_is_column_times_profile_at_centre():
+    """App. G: a line's optical depth at its own centre in layer n is the layer's
+    column (Eq. dtau_line2) times S V(0; beta, gamma_n).  V(0) here comes from
+    the oracle's Voigt profile (Re w by wofz) of that one line, evaluated at
+    its centre: the selection's closed form uses erfcx instead.  With a list of
+    strength temperatures, S is the largest S(T) over the list while the
+    widths stay at T_atm."""
+    ll, atm = _case(3, n=60)
+    lx, T_atm = math.log10(0.0023), 1700.0
+    P = atm.P_bar
+    col = O.column_factor(O.layer_dP_bar(P), 10.0 ** lx, ll.mass_amu, atm.g_cgs)
+    T_scan = [900.0, 1300.0, 1700.0]
+    d1 = SEL.line_centre_dtau(ll, lx, atm, T_atm, [T_atm])
+    d3 = SEL.line_centre_dtau(ll, lx, atm, T_atm, T_scan)
+    for l in (0, 17, 59):
+        one = replace(ll, nu_c=ll.nu_c[l:l + 1], S0=ll.S0[l:l + 1], E_low=ll.E_low[l:l + 1],
+                      alpha_ref=ll.alpha_ref[l:l + 1], n_texp=ll.n_texp[l:l + 1])
+        S = lambda T: float(O.line_strength(one.S0, one.E_low, one.nu_c, T,
+                                            O.qr_ratio(T, one.qr_kind, one.qr_params))[0])
+        boost = max(S(T) for T in T_scan) / S(T_atm)
+        for n in (0, 40, 77, 99):
+            sig = float(O.cross_section(one, T_atm, P[n], one.nu_c)[0])
+            assert d1[n, l] == pytest.approx(col[n] * sig, rel=1e-12)
+            assert d3[n, l] == pytest.approx(col[n] * sig * boost, rel=1e-12)
