@@ -12,11 +12,14 @@
  *     host array it needs).
  *   - A dispatcher thread admits the head of the queue as soon as a stream
  *     slot is free AND a contiguous region of the device memory budget large
- *     enough for the request's workspace is free (first fit).  The budget is
- *     one device allocation made at creation; nothing is allocated while
- *     serving.  Admitted requests run concurrently on separate HIP streams
- *     (default priority) and overlap on the device; a finished request frees
- *     its slot and region, which admits the next.
+ *     enough for the request's workspace is free (first fit).  While the
+ *     head waits for memory, later requests (up to 64 places behind it) that
+ *     fit may go first, at most 8 of them per waiting head; after that the
+ *     head is admitted before any other.  The budget is one device
+ *     allocation made at creation; nothing is allocated while serving.
+ *     Admitted requests run concurrently on separate HIP streams (default
+ *     priority) and overlap on the device; a finished request frees its slot
+ *     and region, which admits the next.
  *   - Every request runs exactly the kernels and launch shapes it would run
  *     alone, so its result is bitwise identical alone and in the mix.
  *   - The context's line lists and grid must not be changed while a server
@@ -36,6 +39,8 @@ typedef struct exo_server exo_server;
 typedef struct {
   int64_t submitted, admitted, completed, failed, rejected;
   int64_t queued, in_flight;
+  int64_t peak_in_flight; /* most requests on the device at once          */
+  int64_t bypasses;       /* admissions ahead of a head waiting for memory */
   double mem_budget_bytes, mem_in_use_bytes, mem_peak_bytes;
 } exo_server_counters;
 
@@ -51,15 +56,20 @@ int exo_server_destroy(exo_server* srv);
  * host arrays are copied; flux_dev (device, caller-owned, [out_len] float for
  * EXO_FP32_KAHAN or double for EXO_FP64) must stay valid until the request
  * has been waited for.  *ticket identifies the request.
+ * arrival_s: the request's arrival time in seconds on CLOCK_MONOTONIC (the
+ * clock of Python's time.monotonic()); latency and queue time are measured
+ * from it.  arrival_s <= 0, or a time later than the call, means the time of
+ * the call.
  * Errors: validation errors of exo_emission_flux (nothing queued);
  * EXO_ENOMEM if the request's workspace can never fit the budget. */
 int exo_server_submit(exo_server* srv, const exo_atmos* atm, const exo_response* resp,
-                      int precision, void* flux_dev, int64_t* ticket);
+                      int precision, void* flux_dev, double arrival_s, int64_t* ticket);
 
 /* Block until request `ticket` has finished (timeout_s < 0: no limit).
  * Returns the request's own status (EXO_OK or its error) or EXO_EINVAL for
- * an unknown ticket / timeout.  Optional outputs, in seconds since submit:
- * latency (until the GPU finished it) and queue time (until admission).
+ * an unknown ticket / timeout.  Optional outputs, in seconds since the
+ * request's arrival: latency (until the GPU finished it) and queue time
+ * (until admission).
  * A ticket can be waited for once. */
 int exo_server_wait(exo_server* srv, int64_t ticket, double timeout_s, double* latency_s,
                     double* queue_s);

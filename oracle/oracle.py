@@ -55,7 +55,17 @@ BAR = 1.0e6                        # dyn cm^-2
 C_KMS = 2.99792458e5               # km s^-1
 SQRT_PI = math.sqrt(math.pi)
 
-N_THREADS = int(os.environ.get("ORACLE_THREADS", os.cpu_count() or 1))
+def _default_threads():
+    """Threads for the chunked sums: the CPUs this process may run on, at most
+    16 (a one-GPU host's share of its CPUs)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+N_THREADS = int(os.environ.get("ORACLE_THREADS", _default_threads()))
 
 
 def _pool_map(fn, items):
@@ -204,17 +214,19 @@ def _xs_chunk(args):
     return sig, dsig
 
 
-def cross_section(ll, T: float, P_bar: float, nu, want_dT: bool = False):
+def cross_section(ll, T: float, P_bar: float, nu, want_dT: bool = False, parallel: bool = True):
     """sigma(nu_j) = sum_l S_l V(nu_j - nu_l; beta_l, gamma_l)  [cm^2 / molecule].
 
-    With want_dT also returns d sigma / dT at fixed P.
+    With want_dT also returns d sigma / dT at fixed P.  The lines go in chunks
+    (threads over chunks unless parallel is False); the chunk sums are added
+    in chunk order either way.
     """
     nu = np.asarray(nu, float)
     st = line_state(ll, T, P_bar)
     nu_c = np.asarray(ll.nu_c, float)
     chunk = max(1, min(_LINE_CHUNK, int(2e6 // max(nu.size, 1))))
     tasks = [(nu, nu_c, st, lo, min(lo + chunk, ll.n), want_dT) for lo in range(0, ll.n, chunk)]
-    parts = _pool_map(_xs_chunk, tasks)
+    parts = _pool_map(_xs_chunk, tasks) if parallel else [_xs_chunk(t) for t in tasks]
     sig = np.sum(np.stack([p[0] for p in parts]), axis=0)
     if not want_dT:
         return sig
@@ -455,7 +467,7 @@ class Columns:
 
 def _xs_layer(args):
     ll, T, P, nu, want = args
-    return cross_section(ll, T, P, nu, want_dT=want)
+    return cross_section(ll, T, P, nu, want_dT=want, parallel=False)
 
 
 def optical_depths(wl, theta, nu_idx=None, want_dT=False) -> Columns:
@@ -476,14 +488,16 @@ def optical_depths(wl, theta, nu_idx=None, want_dT=False) -> Columns:
         raise ValueError("the MODIT opacity is evaluated on the whole grid, without tangents")
     for m, ll in enumerate(wl.lines):
         col = column_factor(dP, 10.0 ** logx[m], ll.mass_amu, atm.g_cgs)
-        for n in range(NL):
-            if modit:
-                from .modit import modit_cross_section
+        if modit:
+            from .modit import modit_cross_section
+            for n in range(NL):
                 # the truncated transform rings slightly below zero next to
                 # narrow lines; an optical depth is not negative
                 tau[m, n] = col[n] * np.maximum(modit_cross_section(ll, T[n], P[n], nu, atm.modit_dln_gamma), 0.0)
-                continue
-            r = cross_section(ll, T[n], P[n], nu, want_dT=want_dT)
+            continue
+        # one cross-section per layer, the layers spread over threads
+        res = _pool_map(_xs_layer, [(ll, T[n], P[n], nu, want_dT) for n in range(NL)])
+        for n, r in enumerate(res):
             if want_dT:
                 tau[m, n] = col[n] * r[0]
                 dtau[m, n] = col[n] * r[1]

@@ -14,6 +14,10 @@ namespace exo {
 // Layers per atmosphere (per-call parameter blocks are staged through a
 // fixed pinned buffer).
 constexpr int kMaxLayers = 4096;
+// FP32 far-tier table of a workspace: per layer the gamma^2 maximum bits,
+// squared reach, t3 flag and squared outer reach, then the strength maximum
+// (8 B) and output scale (4 B) of an adaptive cross-section scale.
+constexpr size_t kTierBytes = (size_t)kMaxLayers * 16 + 16;
 
 int set_err(int code, const char* fmt, ...);
 bool fail_alloc_hook();
@@ -118,10 +122,12 @@ size_t estimate_workspace(const exo_ctx* c, const exo_atmos* a, const exo_respon
                           bool vjp);
 int voigt_launch_profiled(exo_ctx* c, const VoigtArgs& A, bool fp64, bool tan, hipStream_t st);
 // d_T == nullptr: one layer at (T_one, P_one), passed to the kernels by value.
+// adaptive_scale (FP32, one layer at (T_one, P_one)): amp_scale is replaced
+// by a power of two chosen on the device from the largest line strength.
 int species_opacity(exo_ctx* c, Workspace& ws, const Species& sp, const double* d_T,
                     const double* d_P, const double* d_col, int nlay, double amp_scale, bool fp64,
                     bool tangent, const double* d_nu, int64_t ng, void* out, float* out_t,
-                    hipStream_t st, double T_one = 0.0, double P_one = 0.0);
+                    hipStream_t st, double T_one = 0.0, double P_one = 0.0, bool adaptive_scale = false);
 // MODIT cross-sections (d_col == NULL) or optical depths col_n sigma clamped
 // at zero, of nlay layers, from the lines with nu_lo <= nu_c <= nu_hi.
 int modit_opacity(exo_ctx* c, Workspace& ws, const Species& sp, const double* d_T, const double* d_P,

@@ -35,6 +35,7 @@ struct VoigtArgs {
   int ksplit;
   int nlay;
   float out_scale;
+  const float* out_scale_dev;  // if set, the output scale is read from here (adaptive cross-section scale)
   double out_scale64;
   float* out;
   float* out_t;
@@ -159,15 +160,19 @@ struct RespDev {
 // T_lay == nullptr: one layer at (T_one, P_one).
 // g2max_bits (FP32 records only, else nullptr): [nlay] running maximum of
 // gamma^2 over the lines as FP32 bit patterns, raised by atomicMax.
+// amax (FP32 single-layer records only, else nullptr): a zeroed word that
+// receives the largest S(T) of the call; the records then carry the adaptive
+// power-of-two amplitude scale it implies and write its inverse to *oscale.
 hipError_t launch_line_records(const LinesDev& L, const double* T_lay, const double* P_lay,
                                const double* col_lay, double T_one, double P_one, double amp_scale,
-                               int layer0, int nlay,
-                               LineRec* rec, LineRecT* rect, LineRec64* rec64,
-                               unsigned int* g2max_bits, hipStream_t st);
+                               const unsigned long long* amax, float* oscale, int layer0, int nlay,
+                               LineRec* rec, LineRecT* rect, LineRec64* rec64, unsigned int* g2max_bits,
+                               hipStream_t st);
 // Squared far-tier and outer reaches of each layer from its records and
-// g2max_bits, which it resets to zero for the next chunk.
+// g2max_bits, which it resets to zero for the next chunk (and *amax, if given).
 hipError_t launch_far_reach(const LineRec* rec, int64_t n_lines, int nlay, bool tangent,
-                            unsigned int* g2max_bits, float* reach2, int* t3, float* outer2, hipStream_t st);
+                            unsigned int* g2max_bits, float* reach2, int* t3, float* outer2,
+                            unsigned long long* amax, hipStream_t st);
 hipError_t launch_voigt(const VoigtArgs& A, bool fp64, bool tangent, hipStream_t st);
 // Fills the coefficient table of the core branch's rational approximation on
 // the current device (once per process and device; synchronises the device).

@@ -461,7 +461,7 @@ OpacityPlan exo::plan_opacity(int64_t n_lines, int nlay, int64_t ng, bool fp64, 
     P.rec64 = (size_t)P.nlc * n_lines * sizeof(LineRec64);
   } else {
     P.rec = (size_t)P.nlc * n_lines * sizeof(LineRec);
-    P.tier = (size_t)kMaxLayers * (sizeof(unsigned int) + sizeof(float) + sizeof(int) + sizeof(float));
+    P.tier = kTierBytes;
     if (tangent) P.rect = (size_t)P.nlc * n_lines * sizeof(LineRecT);
   }
   // partial sums (the FP32 sum always passes its far-line state through
@@ -508,29 +508,33 @@ int exo::reserve_opacity(Workspace& ws, const OpacityPlan& P) {
 int exo::species_opacity(exo_ctx* c, Workspace& ws, const Species& sp, const double* d_T,
                          const double* d_P, const double* d_col, int nlay, double amp_scale,
                          bool fp64, bool tangent, const double* d_nu, int64_t ng, void* out,
-                         float* out_t, hipStream_t st, double T_one, double P_one) {
+                         float* out_t, hipStream_t st, double T_one, double P_one, bool adaptive_scale) {
   const LinesDev L = lines_dev(sp);
   const OpacityPlan P = plan_opacity(sp.n, nlay, ng, fp64, tangent);
   int rc;
   if ((rc = reserve_opacity(ws, P))) return rc;
   const int nlc = P.nlc;
   // tier buffer: [kMaxLayers] gamma^2 maximum bits, then [kMaxLayers] each
-  // squared reach, t3 flag and squared outer reach; k_far_reach zeroes the
-  // bits of its chunk after use
+  // squared reach, t3 flag and squared outer reach, then the strength
+  // maximum and the output scale of an adaptive cross-section scale;
+  // k_far_reach zeroes the maxima of its chunk after use
   unsigned int* g2bits = fp64 ? nullptr : (unsigned int*)ws.tier.p;
   float* reach2 = fp64 ? nullptr : (float*)(g2bits + kMaxLayers);
   int* t3 = fp64 ? nullptr : (int*)(g2bits + 2 * kMaxLayers);
   float* outer2 = fp64 ? nullptr : (float*)(g2bits + 3 * kMaxLayers);
-  if (!fp64 && ws.tier_zeroed != ws.tier.p)
-    HIP_TRY(hipMemsetAsync(g2bits, 0, (size_t)kMaxLayers * sizeof(unsigned int), st));
+  const bool adaptive = adaptive_scale && !fp64 && d_T == nullptr && nlay == 1;
+  unsigned long long* amax = adaptive ? (unsigned long long*)(g2bits + 4 * kMaxLayers) : nullptr;
+  float* oscale = adaptive ? (float*)(g2bits + 4 * kMaxLayers + 2) : nullptr;
+  if (!fp64 && ws.tier_zeroed != ws.tier.p) HIP_TRY(hipMemsetAsync(ws.tier.p, 0, kTierBytes, st));
   ws.tier_zeroed = nullptr;
   for (int l0 = 0; l0 < nlay; l0 += nlc) {
     const int nl = std::min(nlc, nlay - l0);
-    HIP_TRY(launch_line_records(L, d_T, d_P, d_col, T_one, P_one, amp_scale, l0, nl,
+    HIP_TRY(launch_line_records(L, d_T, d_P, d_col, T_one, P_one, amp_scale, amax, oscale, l0, nl,
                                 fp64 ? nullptr : (LineRec*)ws.rec.p,
                                 (!fp64 && tangent) ? (LineRecT*)ws.rect.p : nullptr,
                                 fp64 ? (LineRec64*)ws.rec64.p : nullptr, g2bits, st));
-    if (!fp64) HIP_TRY(launch_far_reach((const LineRec*)ws.rec.p, sp.n, nl, tangent, g2bits, reach2, t3, outer2, st));
+    if (!fp64)
+      HIP_TRY(launch_far_reach((const LineRec*)ws.rec.p, sp.n, nl, tangent, g2bits, reach2, t3, outer2, amax, st));
     VoigtArgs A{};
     A.nu = d_nu;
     A.ng = ng;
@@ -544,6 +548,7 @@ int exo::species_opacity(exo_ctx* c, Workspace& ws, const Species& sp, const dou
     A.far_outer2 = outer2;
     A.nlay = nl;
     A.out_scale = (float)(1.0 / amp_scale);
+    A.out_scale_dev = oscale;
     A.out_scale64 = 1.0 / amp_scale;
     A.ld_out = ng;
     if (fp64) A.out64 = (double*)out + (int64_t)l0 * ng;
@@ -799,13 +804,14 @@ extern "C" int exo_cross_section(exo_ctx* c, int s, double T, double P, int prec
   std::lock_guard<std::mutex> g(c->mu);
   Workspace& ws = c->ws;
   const bool fp64 = precision == EXO_FP64;
-  // FP32 records carry the amplitude times 2^64 so that the small strengths
-  // of single-molecule cross-sections stay far from the FP32 subnormal range.
-  const double scale = fp64 ? 1.0 : std::ldexp(1.0, 64);
+  // FP32 records carry the amplitude times a power of two chosen on the
+  // device from the call's largest line strength, so that single-molecule
+  // strengths (1e-30 .. 1e8 cm/molecule) stay far from both ends of the
+  // FP32 range.
   // (T, P) go to the record kernel by value: no staging copy on this path
   return with_ws(ws, st, [&] {
-    return species_opacity(c, ws, c->sp[s], nullptr, nullptr, nullptr, 1, scale, fp64, false,
-                           (const double*)c->d_nu.p, c->n_nu, sigma, nullptr, st, T, P);
+    return species_opacity(c, ws, c->sp[s], nullptr, nullptr, nullptr, 1, 1.0, fp64, false,
+                           (const double*)c->d_nu.p, c->n_nu, sigma, nullptr, st, T, P, !fp64);
   });
 }
 

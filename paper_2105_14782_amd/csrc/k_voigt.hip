@@ -11,15 +11,46 @@ namespace exo {
 // Largest FP32 line amplitude (see k_line_records).
 constexpr double kAmpMax = 1e25;
 
+// Adaptive amplitude scale of a single-layer FP32 cross-section: a power of
+// two (exact) that brings the call's largest line strength to [2^80, 2^81),
+// far below kAmpMax (so no line is clipped) while lines 1e60 times weaker
+// than the strongest still sit above FP32's subnormal range.  The exponent is
+// clamped so that its inverse, the output scale, is a normal FP32 number.
+constexpr int kAmpExp = 80;
+
+__device__ inline double amp_scale_of(unsigned long long bits) {
+  const double m = __longlong_as_double((long long)bits);
+  if (!(m > 0.0) || !isfinite(m)) return 18446744073709551616.0;  // no strength: 2^64
+  const int e = min(126, max(-126, kAmpExp - ilogb(m)));
+  return ldexp(1.0, e);
+}
+
+// Largest S(T) over the lines at (T, P), raised into *amax as its FP64 bit
+// pattern (non-negative doubles order like their bit patterns).  *amax is
+// zero on entry; k_far_reach clears it after the records have used it.
+__global__ __launch_bounds__(256) void k_amp_max(LinesDev L, double T, double P,
+                                                 unsigned long long* __restrict__ amax) {
+  const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double S = 0.0;
+  if (l < L.n) S = line_state(L, l, T, P).S;
+#pragma unroll
+  for (int k = 32; k > 0; k >>= 1) S = fmax(S, __shfl_xor(S, k, 64));
+  if ((threadIdx.x & 63) == 0 && S > 0.0) atomicMax(amax, (unsigned long long)__double_as_longlong(S));
+}
+
 // grid: x over lines, y over layers of the chunk.  col == nullptr: column
 // factor 1 (single-layer cross-section).  T_lay == nullptr: one layer at
 // (T_one, P_one), passed by value.  FP32 records also raise g2max_bits[y] to
-// the layer's largest gamma^2 (one atomic per wave).
+// the layer's largest gamma^2 (one atomic per wave).  amax != nullptr: the
+// amplitude scale is amp_scale_of(*amax) instead of amp_scale, and its
+// inverse goes to *oscale for the Voigt sum's output.
 __global__ __launch_bounds__(256) void k_line_records(LinesDev L, const double* __restrict__ T_lay,
                                                       const double* __restrict__ P_lay,
                                                       const double* __restrict__ col_lay,
                                                       double T_one, double P_one,
                                                       double amp_scale, int layer0,
+                                                      const unsigned long long* __restrict__ amax,
+                                                      float* __restrict__ oscale,
                                                       LineRec* __restrict__ rec,
                                                       LineRecT* __restrict__ rect,
                                                       LineRec64* __restrict__ rec64,
@@ -28,6 +59,10 @@ __global__ __launch_bounds__(256) void k_line_records(LinesDev L, const double* 
   const bool in = l < L.n;
   const int y = blockIdx.y;
   const int n = layer0 + y;
+  if (amax) {
+    amp_scale = amp_scale_of(*amax);
+    if (oscale && l == 0 && y == 0) *oscale = (float)(1.0 / amp_scale);
+  }
   const double T = T_lay ? T_lay[n] : T_one, P = T_lay ? P_lay[n] : P_one;
   const double col = col_lay ? col_lay[n] : 1.0;
   const int64_t o = (int64_t)y * L.n + l;
@@ -198,8 +233,11 @@ __device__ inline bool far_search(double bmax, double gmax, double lo, double hi
 __global__ __launch_bounds__(64) void k_far_reach(const LineRec* __restrict__ rec, int64_t n_lines,
                                                   int tangent, unsigned int* __restrict__ g2max_bits,
                                                   float* __restrict__ reach2, int* __restrict__ t3,
-                                                  float* __restrict__ outer2) {
+                                                  float* __restrict__ outer2,
+                                                  unsigned long long* __restrict__ amax) {
   const int y = blockIdx.x, k = threadIdx.x;
+  // the records are written: clear the strength maximum for the next call
+  if (amax && y == 0 && k == 0) *amax = 0ull;
   // beta_max^2 from the threshold 2 * 111 beta^2, with margin for its rounding
   const double bmax = (double)rec[(int64_t)y * n_lines + n_lines - 1].thr * (1.001 / (2.0 * kHjertSwitch));
   const unsigned int bits = g2max_bits[y];
@@ -658,8 +696,9 @@ __device__ __forceinline__ void voigt_body(const VoigtArgs& A) {
     if (j >= A.ng) continue;
     if (A.ksplit == 1) {
       const int64_t o = (int64_t)y * A.ld_out + j;
-      A.out[o] = (s[g] + c[g]) * A.out_scale;
-      if (TAN) A.out_t[o] = (ts[g] + tc[g]) * A.out_scale;
+      const float os = A.out_scale_dev ? *A.out_scale_dev : A.out_scale;
+      A.out[o] = (s[g] + c[g]) * os;
+      if (TAN) A.out_t[o] = (ts[g] + tc[g]) * os;
     } else {
       const int64_t p = ((int64_t)blockIdx.z * A.nlay + y) * A.ng + j;
       A.part[p] = make_float2(s[g], c[g]);
@@ -706,8 +745,9 @@ __global__ __launch_bounds__(256) void k_voigt_combine(VoigtArgs A) {
     }
   }
   const int64_t o = (int64_t)y * A.ld_out + j;
-  A.out[o] = (s + c) * A.out_scale;
-  if (TAN) A.out_t[o] = (ts + tc) * A.out_scale;
+  const float os = A.out_scale_dev ? *A.out_scale_dev : A.out_scale;
+  A.out[o] = (s + c) * os;
+  if (TAN) A.out_t[o] = (ts + tc) * os;
 }
 
 // ---------------------------------------------------------------------------
@@ -795,18 +835,26 @@ __global__ __launch_bounds__(256) void k_hjert_f64(int64_t n, const double* __re
 // ---------------------------------------------------------------------------
 hipError_t launch_line_records(const LinesDev& L, const double* T_lay, const double* P_lay,
                                const double* col_lay, double T_one, double P_one, double amp_scale,
-                               int layer0, int nlay, LineRec* rec, LineRecT* rect, LineRec64* rec64,
-                               unsigned int* g2max_bits, hipStream_t st) {
+                               const unsigned long long* amax, float* oscale, int layer0, int nlay,
+                               LineRec* rec, LineRecT* rect, LineRec64* rec64, unsigned int* g2max_bits,
+                               hipStream_t st) {
   dim3 grid((unsigned)((L.n + 255) / 256), (unsigned)nlay);
+  if (amax) {
+    // the scale needs the largest strength of the call: one layer at (T_one, P_one)
+    if (T_lay || nlay != 1 || rec64) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_amp_max, dim3((unsigned)((L.n + 255) / 256)), dim3(256), 0, st, L, T_one, P_one,
+                       const_cast<unsigned long long*>(amax));
+  }
   hipLaunchKernelGGL(k_line_records, grid, dim3(256), 0, st, L, T_lay, P_lay, col_lay, T_one, P_one,
-                     amp_scale, layer0, rec, rect, rec64, rec64 ? nullptr : g2max_bits);
+                     amp_scale, layer0, amax, oscale, rec, rect, rec64, rec64 ? nullptr : g2max_bits);
   return hipGetLastError();
 }
 
 hipError_t launch_far_reach(const LineRec* rec, int64_t n_lines, int nlay, bool tangent,
-                            unsigned int* g2max_bits, float* reach2, int* t3, float* outer2, hipStream_t st) {
+                            unsigned int* g2max_bits, float* reach2, int* t3, float* outer2,
+                            unsigned long long* amax, hipStream_t st) {
   hipLaunchKernelGGL(k_far_reach, dim3((unsigned)nlay), dim3(64), 0, st, rec, n_lines, tangent ? 1 : 0, g2max_bits,
-                     reach2, t3, outer2);
+                     reach2, t3, outer2, amax);
   return hipGetLastError();
 }
 

@@ -2,8 +2,11 @@
 // C ABI in include/exohip_serve.h.
 #include <hip/hip_runtime.h>
 
+#include <time.h>
+
 #include <chrono>
 #include <condition_variable>
+#include <cmath>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -16,9 +19,22 @@
 #include "exo_host.h"
 
 using namespace exo;
-using Clock = std::chrono::steady_clock;
 
 namespace {
+
+// Seconds on CLOCK_MONOTONIC: the clock callers state arrival times in.
+double mono_now() {
+  timespec ts;
+  clock_gettime(CLOCK_MONOTONIC, &ts);
+  return (double)ts.tv_sec + 1e-9 * (double)ts.tv_nsec;
+}
+
+// A request waiting for memory at the head of the queue lets at most this
+// many later requests that fit be admitted before it; then admission waits
+// for it (no starvation of large requests).
+constexpr int kMaxBypass = 8;
+// How far past a waiting head the dispatcher looks for a request that fits.
+constexpr size_t kBypassWindow = 64;
 
 struct Request {
   int64_t id = 0;
@@ -32,7 +48,8 @@ struct Request {
   size_t bytes = 0;
   size_t region = 0;
   int slot = -1;
-  Clock::time_point t_submit, t_admit, t_done;
+  int bypassed = 0;   // later requests admitted while this one waited at the head
+  double t_arrival = 0, t_admit = 0, t_done = 0;   // CLOCK_MONOTONIC seconds
   int status = EXO_OK;
   std::string msg;
   bool done = false;
@@ -102,6 +119,7 @@ struct exo_server {
   std::vector<Request*> finished;                   // reported by stream callbacks
   int64_t next_id = 1;
   int64_t submitted = 0, admitted = 0, completed = 0, failed = 0, rejected = 0, in_flight = 0;
+  int64_t peak_in_flight = 0, bypasses = 0;
   bool stop = false;
   std::thread dispatcher;
 };
@@ -119,7 +137,7 @@ void on_stream_done(void* p) {
   CallbackArg* a = static_cast<CallbackArg*>(p);
   {
     std::lock_guard<std::mutex> g(a->srv->mu);
-    a->req->t_done = Clock::now();
+    a->req->t_done = mono_now();
     a->srv->finished.push_back(a->req);
   }
   a->srv->cv.notify_all();
@@ -156,24 +174,37 @@ void run_dispatcher(exo_server* s) {
     s->finished.clear();
     if (retired) s->done_cv.notify_all();
     if (s->stop && s->queue.empty() && s->in_flight == 0) break;
-    // admit in arrival order while a slot and a memory region are free
+    // admit in arrival order while a slot and a memory region are free; a
+    // head that waits for memory lets up to kMaxBypass later requests that
+    // fit go first (looking kBypassWindow requests ahead)
     bool admitted_any = false;
     while (!s->queue.empty()) {
       const int si = free_slot(s);
       if (si < 0) break;
-      std::shared_ptr<Request> r = s->queue.front();
       size_t off;
-      if (!s->regions.alloc(r->bytes, &off)) break;  // wait for memory
-      s->queue.pop_front();
+      auto pick = s->queue.begin();
+      if (!s->regions.alloc((*pick)->bytes, &off)) {
+        Request* head = pick->get();
+        if (head->bypassed >= kMaxBypass) break;  // wait for memory
+        const auto end = s->queue.size() > kBypassWindow ? s->queue.begin() + kBypassWindow : s->queue.end();
+        for (++pick; pick != end; ++pick)
+          if (s->regions.alloc((*pick)->bytes, &off)) break;
+        if (pick == end) break;  // nothing fits: wait for memory
+        ++head->bypassed;
+        ++s->bypasses;
+      }
+      std::shared_ptr<Request> r = *pick;
+      s->queue.erase(pick);
       r->region = off;
       r->slot = si;
-      r->t_admit = Clock::now();
+      r->t_admit = mono_now();
       Slot& sl = *s->slots[si];
       sl.busy = true;
       s->in_use += r->bytes;
       if (s->in_use > s->peak) s->peak = s->in_use;
       ++s->admitted;
       ++s->in_flight;
+      if (s->in_flight > s->peak_in_flight) s->peak_in_flight = s->in_flight;
       admitted_any = true;
       lk.unlock();
       sl.ws.bind_arena(s->arena + off, r->bytes);
@@ -259,10 +290,11 @@ extern "C" size_t exo_workspace_bytes(exo_ctx* ctx, const exo_atmos* a, const ex
 }
 
 extern "C" int exo_server_submit(exo_server* s, const exo_atmos* a, const exo_response* r,
-                                 int precision, void* flux, int64_t* ticket) {
+                                 int precision, void* flux, double arrival_s, int64_t* ticket) {
   if (!s || !a || !ticket) return set_err(EXO_EINVAL, "NULL argument");
   if (!flux) return set_err(EXO_EINVAL, "flux_dev is NULL");
   if (precision != EXO_FP32_KAHAN && precision != EXO_FP64) return set_err(EXO_EINVAL, "bad precision");
+  if (!std::isfinite(arrival_s)) return set_err(EXO_EINVAL, "arrival time must be finite");
   int64_t gb, gl;
   int rc;
   if ((rc = validate_atmos(s->ctx, a, &gb, &gl))) return rc;
@@ -296,7 +328,8 @@ extern "C" int exo_server_submit(exo_server* s, const exo_atmos* a, const exo_re
   }
   q->precision = precision;
   q->flux = flux;
-  q->t_submit = Clock::now();
+  const double now = mono_now();
+  q->t_arrival = arrival_s > 0 && arrival_s <= now ? arrival_s : now;
   {
     std::lock_guard<std::mutex> g(s->mu);
     if (s->stop) return set_err(EXO_EINVAL, "server is shutting down");
@@ -322,8 +355,8 @@ extern "C" int exo_server_wait(exo_server* s, int64_t ticket, double timeout_s, 
   else if (!s->done_cv.wait_for(lk, std::chrono::duration<double>(timeout_s), ready))
     return set_err(EXO_EINVAL, "timeout waiting for ticket %lld", (long long)ticket);
   s->live.erase(it);
-  if (latency_s) *latency_s = std::chrono::duration<double>(r->t_done - r->t_submit).count();
-  if (queue_s) *queue_s = std::chrono::duration<double>(r->t_admit - r->t_submit).count();
+  if (latency_s) *latency_s = r->t_done - r->t_arrival;
+  if (queue_s) *queue_s = r->t_admit - r->t_arrival;
   if (r->status != EXO_OK) return set_err(r->status, "%s", r->msg.c_str());
   return EXO_OK;
 }
@@ -338,6 +371,8 @@ extern "C" int exo_server_stats(exo_server* s, exo_server_counters* o) {
   o->rejected = s->rejected;
   o->queued = (int64_t)s->queue.size();
   o->in_flight = s->in_flight;
+  o->peak_in_flight = s->peak_in_flight;
+  o->bypasses = s->bypasses;
   o->mem_budget_bytes = (double)s->cap;
   o->mem_in_use_bytes = (double)s->in_use;
   o->mem_peak_bytes = (double)s->peak;

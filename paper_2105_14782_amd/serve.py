@@ -22,7 +22,8 @@ from .api import Atmos, Context, Response, _prec
 
 class ExoServerCounters(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in
-                ("submitted", "admitted", "completed", "failed", "rejected", "queued", "in_flight")] + \
+                ("submitted", "admitted", "completed", "failed", "rejected", "queued", "in_flight",
+                 "peak_in_flight", "bypasses")] + \
                [(n, ctypes.c_double) for n in ("mem_budget_bytes", "mem_in_use_bytes", "mem_peak_bytes")]
 
 
@@ -33,7 +34,7 @@ def _bind(lib):
     sig = {
         "exo_server_create": ([V, I, ctypes.c_size_t, ctypes.POINTER(V)], I),
         "exo_server_destroy": ([V], I),
-        "exo_server_submit": ([V, ctypes.POINTER(L.ExoAtmos), ctypes.POINTER(L.ExoResponse), I, V,
+        "exo_server_submit": ([V, ctypes.POINTER(L.ExoAtmos), ctypes.POINTER(L.ExoResponse), I, V, D,
                                ctypes.POINTER(I64)], I),
         "exo_server_wait": ([V, I64, D, ctypes.POINTER(D), ctypes.POINTER(D)], I),
         "exo_server_stats": ([V, ctypes.POINTER(ExoServerCounters)], I),
@@ -84,7 +85,10 @@ class Server:
         return int(self._lib.exo_workspace_bytes(self.ctx.handle, ctypes.byref(a),
                                                  ctypes.byref(r) if r is not None else None, _prec(precision)))
 
-    def submit(self, atmos: Atmos, response: Optional[Response] = None, precision="fp32") -> int:
+    def submit(self, atmos: Atmos, response: Optional[Response] = None, precision="fp32",
+               arrival_s: float = 0.0) -> int:
+        """Queue one spectrum; arrival_s (time.monotonic() seconds, 0: now) is
+        the instant latency and queue time are measured from."""
         p = _prec(precision)
         dt = torch.float64 if p == L.EXO_FP64 else torch.float32
         n = int(response.out_len) if response is not None else (int(atmos.grid_len) or self.ctx.n_nu)
@@ -93,7 +97,8 @@ class Server:
         r = response.to_c() if response is not None else None
         t = ctypes.c_int64()
         L.check(self._lib.exo_server_submit(self._h, ctypes.byref(a), ctypes.byref(r) if r is not None else None,
-                                            p, ctypes.c_void_p(out.data_ptr()), ctypes.byref(t)))
+                                            p, ctypes.c_void_p(out.data_ptr()), float(arrival_s),
+                                            ctypes.byref(t)))
         with self._lock:
             self._out[t.value] = out
         return t.value
@@ -115,26 +120,27 @@ class Server:
 def run_stream(server: Server, requests: List[tuple], arrival_s: Optional[np.ndarray] = None,
                precision="fp32") -> dict:
     """Submit (atmos, response) pairs at the given arrival times (seconds from
-    start; None = all at once) and wait for all.  Returns latencies, results
-    and throughput."""
+    start; None = all at once) and wait for all.  Each request's latency is
+    measured from its scheduled arrival, so a submitter that falls behind
+    the schedule adds to it.  Returns latencies, results and throughput."""
     n = len(requests)
     tickets = [None] * n
-    t0 = time.perf_counter()
+    t0 = time.monotonic()
 
     def submitter():
         for i, (a, r) in enumerate(requests):
-            if arrival_s is not None:
-                delay = t0 + float(arrival_s[i]) - time.perf_counter()
-                if delay > 0:
-                    time.sleep(delay)
-            tickets[i] = server.submit(a, r, precision)
+            due = t0 + (float(arrival_s[i]) if arrival_s is not None else 0.0)
+            delay = due - time.monotonic()
+            if delay > 0:
+                time.sleep(delay)
+            tickets[i] = server.submit(a, r, precision, arrival_s=due)
 
     th = threading.Thread(target=submitter)
     th.start()
     th.join()
     results = [server.wait(t) for t in tickets]
     torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
+    wall = time.monotonic() - t0
     lat = np.array([r.latency_s for r in results])
     return {"results": results, "latency_s": lat, "wall_s": wall,
             "spectra_per_s": n / wall,

@@ -114,7 +114,7 @@ def _lines_config2(rng, n_lines, nu_lo, nu_hi, mass, qr_power):
                     np.array([qr_power]))
 
 
-_SIZES = ("tiny", "small", "medium", "full")
+_SIZES = ("tiny", "small", "reduced", "medium", "full")
 
 
 def make_config(k: int, size: str = "full", seed: Optional[int] = None) -> Workload:
@@ -123,14 +123,16 @@ def make_config(k: int, size: str = "full", seed: Optional[int] = None) -> Workl
     full   : the configuration as specified (1..3); 4 = config-2 atmosphere.
     medium : config-2 shape with fewer lines, still many tiles (parity runs).
     small  : several tiles plus ragged tails, oracle finishes in seconds.
+    reduced: (configs 2 and 4) 1e3 lines per species, 2,000 points, 100
+             layers: the size of the full-gradient oracle comparison.
     tiny   : a handful of lines/points for CPU-only oracle pins.
     """
     if size not in _SIZES:
         raise ValueError(size)
     rng = np.random.default_rng(CONFIG_SEEDS[k] if seed is None else seed)
     if k == 1:
-        n_lines, n_nu = {"tiny": (7, 50), "small": (1000, 4000), "medium": (1000, 4000),
-                         "full": (1000, 4000)}[size]
+        n_lines, n_nu = {"tiny": (7, 50), "small": (1000, 4000), "reduced": (1000, 4000),
+                         "medium": (1000, 4000), "full": (1000, 4000)}[size]
         nu_c = np.sort(rng.uniform(4340.0, 4360.0, n_lines))
         S0 = 10.0 ** rng.uniform(-25.0, -20.0, n_lines)
         gam = rng.uniform(0.01, 0.1, n_lines)
@@ -144,6 +146,7 @@ def make_config(k: int, size: str = "full", seed: Optional[int] = None) -> Workl
         n_lines, n_nu, n_lay, margin = {
             "tiny": (9, 1201, 12, 60),
             "small": (401, 1537, 100, 160),
+            "reduced": (1000, 2000, 100, 100),
             "medium": (20011, 20000, 100, 600),
             "full": (100000, 20000, 100, 600),
         }[size]
@@ -166,6 +169,7 @@ def make_config(k: int, size: str = "full", seed: Optional[int] = None) -> Workl
         n_lines, n_nu, n_lay = {
             "tiny": (11, 300, 5),
             "small": (3001, 2500, 10),
+            "reduced": (3001, 2500, 10),
             "medium": (1_000_000, 100_000, 100),
             "full": (10_000_000, 100_000, 100),
         }[size]

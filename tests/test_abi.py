@@ -82,7 +82,7 @@ def _c_layout(tmp_path, struct, fields):
     if shutil.which("gcc") is None:
         pytest.skip("gcc not found")
     src = tmp_path / "layout.c"
-    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "exohip.h"', "int main(void) {",
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "exohip_serve.h"', "int main(void) {",
              f'  printf("%zu\\n", sizeof({struct}));']
     lines += [f'  printf("%zu\\n", offsetof({struct}, {f}));' for f in fields]
     lines += ["  return 0;", "}"]
@@ -94,9 +94,16 @@ def _c_layout(tmp_path, struct, fields):
     return int(out[0]), [int(v) for v in out[1:]]
 
 
-@pytest.mark.parametrize("struct,ctype", [("exo_atmos", L.ExoAtmos), ("exo_response", L.ExoResponse)])
+def _server_counters():
+    from paper_2105_14782_amd import serve
+    return serve.ExoServerCounters
+
+
+@pytest.mark.parametrize("struct,ctype", [("exo_atmos", L.ExoAtmos), ("exo_response", L.ExoResponse),
+                                          ("exo_server_counters", None)])
 def test_ctypes_structs_match_the_header(tmp_path, struct, ctype):
     """The binding's ctypes mirrors have the C layout field by field."""
+    ctype = ctype or _server_counters()
     names = [f[0] for f in ctype._fields_]
     size, offsets = _c_layout(tmp_path, struct, names)
     assert ctypes.sizeof(ctype) == size

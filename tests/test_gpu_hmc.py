@@ -65,7 +65,8 @@ def test_loss_grad_against_oracle(exo, case):
     scale = np.maximum(np.abs(g_ref), 1e-6 * np.abs(g_ref).max())
     assert np.all(np.abs(g - g_ref) / scale < 1e-3), (g, g_ref)
     errl = np.abs(gl - gl_ref) / np.maximum(np.abs(gl_ref), 1e-6 * np.abs(gl_ref).max())
-    assert errl.max() < 5e-3
+    _say(f"  per-layer gradient max rel err {errl.max():.2e}")
+    assert errl.max() < 1e-3
     # the same gradient as flux_vjp with the cotangent formed from the same F
     cot = ((F.double() - d.double()) / s.double() ** 2).float().contiguous()
     g2, _, _ = c.flux_vjp(atm, resp, cot)

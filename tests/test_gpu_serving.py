@@ -96,3 +96,70 @@ def test_memory_admission_bounds_and_rejects(setup):
     assert st["completed"] == len(fits)
     assert st["rejected"] == len(too_big)
     assert st["mem_peak_bytes"] <= 64 << 20
+
+
+def _warm(api, ctx, nu, lists, reqs):
+    from paper_2105_14782_amd import serve
+    srv = serve.Server(ctx, n_streams=4, mem_budget_bytes=4 << 30)
+    serve.run_stream(srv, [_req_args(api, nu, lists, q) for q in reqs])
+    srv.close()
+
+
+def test_requests_overlap_on_the_device(setup):
+    """A fixed set of 12 requests: served four at a time they are on the
+    device together (peak in-flight >= 2) and finish in less wall time than
+    the sum of their times served one at a time."""
+    import time
+    api, ctx, lists, nu, reqs = setup
+    from paper_2105_14782_amd import serve
+    _warm(api, ctx, nu, lists, reqs[:12])
+    args = [_req_args(api, nu, lists, q) for q in reqs[:12]]
+    alone = serve.Server(ctx, n_streams=1, mem_budget_bytes=4 << 30)
+    solo = []
+    for a, r in args:
+        t = time.monotonic()
+        alone.wait(alone.submit(a, r))
+        solo.append(time.monotonic() - t)
+    alone.close()
+    mix = serve.Server(ctx, n_streams=4, mem_budget_bytes=4 << 30)
+    out = serve.run_stream(mix, args)
+    st = mix.stats()
+    mix.close()
+    print(f"  sum of solo times {1e3 * sum(solo):.1f} ms, mixed wall {1e3 * out['wall_s']:.1f} ms, "
+          f"peak in flight {st['peak_in_flight']}", flush=True)
+    assert st["peak_in_flight"] >= 2
+    assert out["wall_s"] < sum(solo)
+
+
+def test_small_requests_bypass_a_head_waiting_for_memory(setup):
+    """While a large request waits for memory at the head of the queue,
+    smaller requests that fit are admitted ahead of it, at most 8 of them; the
+    rest wait for it.  Every result is still the one the request gives alone."""
+    import time
+    from dataclasses import replace
+    api, ctx, lists, nu, reqs = setup
+    from paper_2105_14782_amd import serve
+    big = replace(reqs[0], grid_begin=2000, grid_len=150000, n_layers=200)
+    A = _req_args(api, nu, lists, big)
+    H = _req_args(api, nu, lists, replace(big, theta=reqs[1].theta))
+    small = [_req_args(api, nu, lists, replace(q, grid_len=2000, n_layers=20)) for q in reqs[2:14]]
+    probe = serve.Server(ctx, n_streams=1, mem_budget_bytes=1 << 20)
+    wa = max(probe.workspace_bytes(*A), probe.workspace_bytes(*H))
+    ws = max(probe.workspace_bytes(*s) for s in small)
+    probe.close()
+    budget = wa + wa // 2
+    assert 3 * ws < wa // 2, (ws, wa)   # three small requests fit beside the first large one
+    ref = [ctx.emission_flux(*x).cpu() for x in [A, H] + small]
+    srv = serve.Server(ctx, n_streams=4, mem_budget_bytes=budget)
+    t0 = time.monotonic()    # one arrival instant for all: queue times order the admissions
+    tickets = [srv.submit(a, r, arrival_s=t0) for a, r in [A, H] + small]
+    res = [srv.wait(t) for t in tickets]
+    st = srv.stats()
+    srv.close()
+    ahead = sum(r.queue_s < res[1].queue_s for r in res[2:])
+    print(f"  bypasses {st['bypasses']}, small requests admitted before the waiting head {ahead}",
+          flush=True)
+    assert 1 <= st["bypasses"] <= 8
+    assert ahead == st["bypasses"]
+    for k, (r, f) in enumerate(zip(res, ref)):
+        assert torch.equal(r.flux.cpu(), f), k
