@@ -146,6 +146,24 @@ int exo_set_grid(exo_ctx* ctx, int64_t n_nu, const double* nu);
 int exo_cross_section(exo_ctx* ctx, int s, double T_K, double P_bar, int precision,
                       void* sigma_dev, void* stream);
 
+/* exo_cross_section for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, kernels and result (bitwise) as
+ * exo_cross_section; no hipMalloc, hipFree, memset or event is issued.  Its
+ * scratch (line records, the far-tier table and split partial sums) is not
+ * the context's workspace but a fixed 128 MiB array per GPU, held from the
+ * first exo_create on that GPU until the process ends.  Every call on a GPU
+ * shares that GPU's array and it keeps the last call's contents (each call
+ * clears what must start at zero, with a kernel): calls that overlap on one
+ * GPU (other streams, threads or contexts) race, and the caller must
+ * serialise them.
+ * Errors: as exo_cross_section, and EXO_ENOMEM (nothing launched) when the
+ * call would need more than 128 MiB of scratch: 64 B (FP32) or 32 B (FP64)
+ * per line, 64 KiB, and 8 B per grid point and line split (the splits bring
+ * the workgroups of one launch to about 8192). */
+int exo_cross_section_noalloc(exo_ctx* ctx, int s, double T_K, double P_bar, int precision,
+                              void* sigma_dev, void* stream);
+
 /* The same cross-section by MODIT (Sec. 2.1.2), the paper's method for many
  * lines: a lineshape density on the log-uniform grid (q = R0 ln nu, every
  * line split over the neighbouring grid points and log-spaced Lorentz-width

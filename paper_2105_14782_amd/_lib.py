@@ -90,6 +90,7 @@ def load_library(path: str = LIB_PATH):
         "exo_set_lines": ([V, I, I64, _c_dp, _c_dp, _c_dp, _c_dp, _c_dp, _c_dp, D, I, _c_dp, I], I),
         "exo_set_grid": ([V, I64, _c_dp], I),
         "exo_cross_section": ([V, I, D, D, I, V, V], I),
+        "exo_cross_section_noalloc": ([V, I, D, D, I, V, V], I),
         "exo_emission_flux": ([V, ctypes.POINTER(ExoAtmos), ctypes.POINTER(ExoResponse), I, V, V], I),
         "exo_flux_vjp": ([V, ctypes.POINTER(ExoAtmos), ctypes.POINTER(ExoResponse), I, V, _c_dp, _c_dp, V, V], I),
         "exo_broaden": ([V, I64, I64, ctypes.POINTER(ExoResponse), V, V, V], I),

@@ -163,6 +163,18 @@ class Context:
                                             ctypes.c_void_p(out.data_ptr()), _stream(stream)))
         return out
 
+    def cross_section_noalloc(self, slot: int, T: float, P_bar: float, out: torch.Tensor, precision="fp32",
+                              stream=None):
+        """cross_section into a caller-owned tensor, with no device allocation
+        by the library (its scratch is a fixed per-device array shared by all
+        such calls on the GPU: overlapping calls race)."""
+        p = _prec(precision)
+        dt = torch.float64 if p == L.EXO_FP64 else torch.float32
+        assert out.dtype == dt and out.is_contiguous() and out.numel() == self.n_nu
+        L.check(self._lib.exo_cross_section_noalloc(self._h, int(slot), float(T), float(P_bar), p,
+                                                    ctypes.c_void_p(out.data_ptr()), _stream(stream)))
+        return out
+
     def cross_section_modit(self, slot: int, T: float, P_bar: float, precision="fp32", dln_gamma=0.1,
                             out=None, stream=None):
         """MODIT cross-section (Sec. 2.1.2) on the context's log-uniform grid."""

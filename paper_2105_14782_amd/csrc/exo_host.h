@@ -46,6 +46,9 @@ struct Workspace {
   // Arena mode (serving): buffers are carved from [arena, arena + arena_cap)
   // instead of being allocated; no allocation happens while serving.
   char* arena = nullptr;
+  // No device work that allocates or records a memset: scratch is cleared by
+  // kernels and the Voigt launches are not profiled (events).
+  bool no_alloc = false;
   size_t arena_cap = 0, arena_used = 0;
   int reserve(DevBuf& b, size_t bytes);
   void bind_arena(char* base, size_t cap);

@@ -174,6 +174,8 @@ hipError_t launch_far_reach(const LineRec* rec, int64_t n_lines, int nlay, bool 
                             unsigned int* g2max_bits, float* reach2, int* t3, float* outer2,
                             unsigned long long* amax, hipStream_t st);
 hipError_t launch_voigt(const VoigtArgs& A, bool fp64, bool tangent, hipStream_t st);
+// Zeroes bytes (a multiple of 4) at p with a kernel (no memset node).
+hipError_t launch_zero_words(void* p, size_t bytes, hipStream_t st);
 // Fills the coefficient table of the core branch's rational approximation on
 // the current device (once per process and device; synchronises the device).
 hipError_t ensure_weideman();

@@ -169,6 +169,38 @@ int Workspace::stage_params(const double* host, size_t n, double* dev, hipStream
 }
 
 // ---------------------------------------------------------------------------
+// Scratch of the cross-section that allocates nothing
+// ---------------------------------------------------------------------------
+// exo_cross_section_noalloc keeps its line records, far-tier table and split
+// partial sums in this fixed array, one copy per device for the life of the
+// process.  In host code `scratch` names a host-side stand-in, not device
+// memory: its device address on each device comes from hipGetSymbolAddress
+// (at exo_create, with that device current) and only that address is used.
+static constexpr size_t kNoAllocScratchBytes = size_t(128) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+static std::mutex g_scratch_mu;
+static std::vector<void*> g_scratch_dev;   // [device] address of `scratch`
+
+// With `device` current: look up and keep the device's scratch address.
+static int bind_scratch(int device) {
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if ((int)g_scratch_dev.size() <= device) g_scratch_dev.resize(device + 1, nullptr);
+  if (g_scratch_dev[device]) return EXO_OK;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !p)
+    return set_err(EXO_EDEVICE, "hipGetSymbolAddress(scratch) failed on device %d: %s", device,
+                   hipGetErrorString(e));
+  g_scratch_dev[device] = p;
+  return EXO_OK;
+}
+
+static void* scratch_of(int device) {
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  return device < (int)g_scratch_dev.size() ? g_scratch_dev[device] : nullptr;
+}
+
+// ---------------------------------------------------------------------------
 // Context
 // ---------------------------------------------------------------------------
 extern "C" int exo_create(int device, exo_ctx** out) {
@@ -179,6 +211,8 @@ extern "C" int exo_create(int device, exo_ctx** out) {
   if (device < 0 || device >= n) return set_err(EXO_EINVAL, "device %d out of range (%d devices)", device, n);
   HIP_TRY(hipSetDevice(device));
   HIP_TRY(ensure_weideman());
+  const int rc = bind_scratch(device);
+  if (rc) return rc;
   exo_ctx* c = new exo_ctx();
   c->device = device;
   *out = c;
@@ -525,7 +559,10 @@ int exo::species_opacity(exo_ctx* c, Workspace& ws, const Species& sp, const dou
   const bool adaptive = adaptive_scale && !fp64 && d_T == nullptr && nlay == 1;
   unsigned long long* amax = adaptive ? (unsigned long long*)(g2bits + 4 * kMaxLayers) : nullptr;
   float* oscale = adaptive ? (float*)(g2bits + 4 * kMaxLayers + 2) : nullptr;
-  if (!fp64 && ws.tier_zeroed != ws.tier.p) HIP_TRY(hipMemsetAsync(ws.tier.p, 0, kTierBytes, st));
+  if (!fp64 && ws.tier_zeroed != ws.tier.p) {
+    if (ws.no_alloc) HIP_TRY(launch_zero_words(ws.tier.p, kTierBytes, st));
+    else HIP_TRY(hipMemsetAsync(ws.tier.p, 0, kTierBytes, st));
+  }
   ws.tier_zeroed = nullptr;
   for (int l0 = 0; l0 < nlay; l0 += nlc) {
     const int nl = std::min(nlc, nlay - l0);
@@ -565,7 +602,7 @@ int exo::species_opacity(exo_ctx* c, Workspace& ws, const Species& sp, const dou
       A.part_t = (float2*)ws.part_t.p;
       A.part64 = (double*)ws.part.p;
     }
-    if ((rc = voigt_launch_profiled(c, A, fp64, tangent, st))) return rc;
+    if ((rc = voigt_launch_profiled(ws.no_alloc ? nullptr : c, A, fp64, tangent, st))) return rc;
   }
   if (!fp64) ws.tier_zeroed = ws.tier.p;
   return EXO_OK;
@@ -813,6 +850,39 @@ extern "C" int exo_cross_section(exo_ctx* c, int s, double T, double P, int prec
     return species_opacity(c, ws, c->sp[s], nullptr, nullptr, nullptr, 1, 1.0, fp64, false,
                            (const double*)c->d_nu.p, c->n_nu, sigma, nullptr, st, T, P, !fp64);
   });
+}
+
+// Bytes of scratch a plan carves (256-byte aligned pieces).
+static size_t plan_bytes(const OpacityPlan& P) {
+  size_t t = 0;
+  for (size_t b : {P.rec, P.rect, P.rec64, P.tier, P.part, P.part_t}) t += (b + 255) & ~size_t(255);
+  return t;
+}
+
+extern "C" int exo_cross_section_noalloc(exo_ctx* c, int s, double T, double P, int precision,
+                                         void* sigma, void* stream) {
+  if (!c) return set_err(EXO_EINVAL, "ctx is NULL");
+  if (s < 0 || s >= EXO_MAX_SPECIES || !c->sp[s].set) return set_err(EXO_ENOTSET, "species %d not set", s);
+  if (c->n_nu < 2) return set_err(EXO_ENOTSET, "grid not set");
+  if (!(T > 0) || !std::isfinite(T) || !(P >= 0) || !std::isfinite(P))
+    return set_err(EXO_EINVAL, "need T > 0 and P >= 0");
+  if (precision != EXO_FP32_KAHAN && precision != EXO_FP64) return set_err(EXO_EINVAL, "bad precision");
+  if (!sigma) return set_err(EXO_EINVAL, "sigma_dev is NULL");
+  char* base = (char*)scratch_of(c->device);
+  if (!base) return set_err(EXO_EDEVICE, "no scratch address on device %d", c->device);
+  const bool fp64 = precision == EXO_FP64;
+  const Species& sp = c->sp[s];
+  const size_t need = plan_bytes(plan_opacity(sp.n, 1, c->n_nu, fp64, false));
+  if (need > kNoAllocScratchBytes)
+    return set_err(EXO_ENOMEM, "this cross-section needs %zu bytes of scratch; the no-allocation scratch holds %zu",
+                   need, kNoAllocScratchBytes);
+  HIP_TRY(hipSetDevice(c->device));
+  std::lock_guard<std::mutex> g(c->mu);
+  Workspace ws;   // carved from the scratch: reserves allocate nothing
+  ws.no_alloc = true;
+  ws.bind_arena(base, kNoAllocScratchBytes);
+  return species_opacity(c, ws, sp, nullptr, nullptr, nullptr, 1, 1.0, fp64, false, (const double*)c->d_nu.p,
+                         c->n_nu, sigma, nullptr, (hipStream_t)stream, T, P, !fp64);
 }
 
 // ---------------------------------------------------------------------------

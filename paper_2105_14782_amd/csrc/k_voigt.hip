@@ -858,6 +858,18 @@ hipError_t launch_far_reach(const LineRec* rec, int64_t n_lines, int nlay, bool 
   return hipGetLastError();
 }
 
+__global__ __launch_bounds__(256) void k_zero_words(unsigned int* __restrict__ p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+
+hipError_t launch_zero_words(void* p, size_t bytes, hipStream_t st) {
+  const int64_t n = (int64_t)(bytes / sizeof(unsigned int));
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zero_words, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, (unsigned int*)p, n);
+  return hipGetLastError();
+}
+
 hipError_t launch_voigt(const VoigtArgs& A, bool fp64, bool tangent, hipStream_t st) {
   if (fp64) {
     dim3 grid((unsigned)((A.ng + 255) / 256), (unsigned)A.nlay, (unsigned)A.ksplit);
