@@ -54,8 +54,11 @@ def parse():
     ap.add_argument("--modit-emission-only", action="store_true",
                     help="only the config-3 emission with MODIT opacities (for profiling)")
     ap.add_argument("--cpu-points", type=int, default=256)
-    ap.add_argument("--serve-requests", type=int, default=48,
+    ap.add_argument("--serve-requests", type=int, default=1000,
                     help="requests of the Poisson serving run (0: skip)")
+    ap.add_argument("--serve-capacity-requests", type=int, default=200,
+                    help="requests of the closed-loop capacity run that sets the arrival rate")
+    ap.add_argument("--no-config3", action="store_true", help="skip the full config-3 direct-sum spectrum")
     ap.add_argument("--serve-load", type=float, nargs="+", default=[0.9],
                     help="arrival rates of the serving runs as fractions of the measured capacity")
     ap.add_argument("--serving-only", action="store_true", help="only the serving runs")
@@ -65,6 +68,8 @@ def parse():
                     help="write the traffic summary from two --pmc runs of --counters and exit")
     ap.add_argument("--summarize-valu", metavar="VALU_CSV",
                     help="write the VALU-issue summary from a --pmc run of --counters and exit")
+    ap.add_argument("--summarize-flops", metavar="FLOPS_CSV",
+                    help="write the hardware FLOP summary from a --pmc run (FLOP_COUNTERS) of --counters and exit")
     ap.add_argument("--summarize-stats", metavar="STATS_CSV",
                     help="write the kernel-time summary from a rocprofv3 --stats run and exit")
     ap.add_argument("--summarize-modit-stats", metavar="STATS_CSV",
@@ -76,9 +81,26 @@ def parse():
     return ap.parse_args()
 
 
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
 def cpu_baseline(wl, theta, n_points):
-    """The FP64 oracle on a bounded sample: F0 at n_points grid points, all lines and layers."""
-    threads = min(16, os.cpu_count() or 1)
+    """The FP64 oracle on a bounded sample: F0 at n_points grid points, all
+    lines and layers, on every CPU this process may use (at most 16, a
+    one-GPU host's share)."""
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = os.cpu_count() or 1
+    threads = max(1, min(16, usable))
     os.environ["ORACLE_THREADS"] = str(threads)
     from oracle import oracle as O
     O.N_THREADS = threads
@@ -89,6 +111,8 @@ def cpu_baseline(wl, theta, n_points):
     dt = time.perf_counter() - t0
     evals = sum(l.n for l in wl.lines) * wl.atmos.P_bar.size * n_points
     return {"value": evals / dt, "unit": "Voigt evals/s", "cores": threads, "kind": "oracle",
+            "nproc": os.cpu_count(), "usable_cpus": usable, "cpu_model": _cpu_model(),
+            "evals_per_s_per_core": evals / dt / threads,
             "sample": f"F0 at {n_points} random grid points x all {sum(l.n for l in wl.lines)} lines "
                       f"x {wl.atmos.P_bar.size} layers (FP64 scipy wofz + exact E3), {dt:.1f} s"}
 
@@ -106,10 +130,10 @@ def voigt_source_hash():
     return h.hexdigest()
 
 
-def recorded_traffic():
-    """HBM bytes per tangent Voigt launch from the committed counter summary,
-    or None when the kernel sources changed since the counters were taken."""
-    path = os.path.join(ROOT, TRAFFIC_PROFILE)
+def _profile_values(rel_path):
+    """The "- key: value" lines of a committed counter summary, or None when
+    the kernel sources changed since its counters were taken."""
+    path = os.path.join(ROOT, rel_path)
     if not os.path.exists(path):
         return None
     kv = {}
@@ -119,7 +143,24 @@ def recorded_traffic():
             kv[k.strip()] = v.strip().strip("`")
     if kv.get("kernel_source_sha256") != voigt_source_hash():
         return None
-    return float(kv["traffic_bytes_per_launch"])
+    return kv
+
+
+def recorded_traffic():
+    """HBM bytes per tangent Voigt launch from the committed counter summary
+    (None if stale)."""
+    kv = _profile_values(TRAFFIC_PROFILE)
+    return None if kv is None else float(kv["traffic_bytes_per_launch"])
+
+
+def recorded_counter_flops():
+    """FP32 and FP64 operations per tangent Voigt launch counted by the
+    hardware (64 lanes x (ADD + MUL + TRANS + 2 FMA) wave instructions), from
+    the committed counter summary (None if stale)."""
+    kv = _profile_values(FLOPS_PROFILE)
+    if kv is None:
+        return None
+    return float(kv["fp32_flop_per_launch"]), float(kv["fp64_flop_per_launch"])
 
 
 def summarize_counters(fetch_csv, write_csv, out_path):
@@ -176,6 +217,9 @@ def summarize_counters(fetch_csv, write_csv, out_path):
 
 
 VALU_PROFILE = "profiles/voigt_tangent_config2_valu.md"
+FLOPS_PROFILE = "profiles/voigt_tangent_config2_flops.md"
+FLOP_COUNTERS = ("SQ_INSTS_VALU_ADD_F32 SQ_INSTS_VALU_MUL_F32 SQ_INSTS_VALU_FMA_F32 SQ_INSTS_VALU_TRANS_F32 "
+                 "SQ_INSTS_VALU_ADD_F64 SQ_INSTS_VALU_MUL_F64 SQ_INSTS_VALU_FMA_F64 SQ_INSTS_VALU_TRANS_F64")
 STATS_PROFILE = "profiles/voigt_config2_kernel_stats.md"
 MODIT_EMISSION_PROFILE = "profiles/modit_emission_config3_kernel_stats.md"
 MODIT_PROFILE = "profiles/modit_config3_kernel_stats.md"
@@ -222,6 +266,54 @@ def summarize_valu(csv_path, out_path):
         "issue VALU work on (nearly) every cycle; above 1, some counted instructions (moves,",
         "masks, lane operations) hold the SIMD for fewer than 4 cycles.  The kernel is bound",
         "by VALU issue, not by memory: the lever is the instruction count per pair.",
+    ]
+    open(out_path, "w").write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def summarize_flops(csv_path, out_path):
+    """Hardware FP32/FP64 operation counts of the tangent Voigt launches from
+    one rocprofv3 --pmc run of `bench.py --counters` (FLOP_COUNTERS): each
+    counter counts wave instructions, so operations = 64 lanes x (ADD + MUL +
+    TRANS + 2 FMA), whatever the execution mask (masked-off lanes count)."""
+    import csv
+    acc = {}
+    for r in csv.DictReader(open(csv_path)):
+        if "k_voigt_f32<true" in r["Kernel_Name"]:
+            acc.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    m = {k: float(np.mean(v)) for k, v in acc.items()}
+    n = len(next(iter(acc.values())))
+    f32 = 64.0 * (m["SQ_INSTS_VALU_ADD_F32"] + m["SQ_INSTS_VALU_MUL_F32"] + m["SQ_INSTS_VALU_TRANS_F32"]
+                  + 2.0 * m["SQ_INSTS_VALU_FMA_F32"])
+    f64 = 64.0 * (m["SQ_INSTS_VALU_ADD_F64"] + m["SQ_INSTS_VALU_MUL_F64"] + m["SQ_INSTS_VALU_TRANS_F64"]
+                  + 2.0 * m["SQ_INSTS_VALU_FMA_F64"])
+    pairs = 1e5 * 2e4 * 100
+    groups = pairs / 64.0
+    lines = [
+        "# Hardware FP32/FP64 operations of the tangent-mode Voigt sum (config-2 emission, one species per launch)", "",
+        "Command (repository root, one MI355X):", "", "```",
+        f"rocprofv3 --pmc {FLOP_COUNTERS} --output-format csv -d gpurun_out/pmc_flops -o run -- "
+        "python3 bench.py --counters --warmup 1",
+        "python3 bench.py --summarize-flops gpurun_out/pmc_flops/run_counter_collection.csv", "```", "",
+        f"Launches measured: {n} (1e5 lines x 20,000 points x 100 layers = 2e11 pairs each).", "",
+        "Wave instructions per 64 pairs (per launch / 3.125e9):", "",
+    ]
+    for k in FLOP_COUNTERS.split():
+        lines.append(f"- {k}: {m[k]:.4e} per launch = {m[k] / groups:.3f} per 64 pairs")
+    lines += [
+        "",
+        "Operations = 64 x (ADD + MUL + TRANS + 2 FMA) wave instructions (FMA = 2, masked lanes included):", "",
+        f"- fp32_flop_per_launch: {f32:.4e}",
+        f"- fp64_flop_per_launch: {f64:.4e}",
+        f"- fp32_flop_per_pair: {f32 / pairs:.3f}",
+        f"- fp64_flop_per_pair: {f64 / pairs:.3f}",
+        f"- kernel_source_sha256: `{voigt_source_hash()}`", "",
+        "bench.py divides these per-launch counts by the launch time it measures with HIP events",
+        "(`roofline.counter_tflops`), beside the algorithmic count (`roofline.achieved`, tier-aware",
+        "model FLOPs per pair).  The hardware count is the larger: it includes the reciprocal",
+        "sharing (one reciprocal and three multiplications per two far points), the FP64 offset",
+        "and core-branch work, compares and selects counted as FP32 operations, and lanes",
+        "masked off in the core branch.",
     ]
     open(out_path, "w").write("\n".join(lines) + "\n")
     print("\n".join(lines))
@@ -279,7 +371,7 @@ def summarize_stats(csv_path, out_path, modit=False):
     print("\n".join(lines))
 
 
-def modit_bench(reps=5):
+def modit_bench(wl=None, reps=5):
     """MODIT (Sec. 2.1.2) against the direct sum on the throughput workload
     (config 3: lines U(4340, 4796.44) cm^-1, 100,000-point grid at R0 = 1e6),
     one layer at T = 1300 K, P = 1 bar, as the paper benchmarks opacity time
@@ -289,7 +381,7 @@ def modit_bench(reps=5):
     import synth
     from dataclasses import replace
     from paper_2105_14782_amd import api
-    wl = synth.make_config(3, "full")
+    wl = wl if wl is not None else synth.make_config(3, "full")
     full = wl.lines[0]
     ctx = api.Context(0)
     ctx.set_grid(wl.nu)
@@ -320,10 +412,6 @@ def modit_bench(reps=5):
         run["direct_fp32_ms"] = 1e3 * timed(lambda: ctx.cross_section(0, T, P, "fp32"), 1 if stride == 1 else 3)
         run["direct_over_modit_fp32"] = run["direct_fp32_ms"] / run["modit_fp32_ms"]
         run["direct_fp32_evals_per_s"] = sub.n * wl.nu.size / (1e-3 * run["direct_fp32_ms"])
-        if stride == 1:
-            # the plain FP64 form on the whole config-3 list (1e12 evaluations)
-            run["direct_fp64_ms"] = 1e3 * timed(lambda: ctx.cross_section(0, T, P, "fp64"), 1)
-            run["direct_fp32_over_fp64"] = run["direct_fp64_ms"] / run["direct_fp32_ms"]
         # weak-line pre-selection (App. G) of the same list on the config-3 atmosphere:
         # isothermal 1700 K, strengths scanned over 500-1700 K, margin 2 layers
         run["select_ms"] = 1e3 * timed(lambda: ctx.select_lines(0, math.log10(0.0023), atm, 1700.0, T_scan, 2),
@@ -331,7 +419,7 @@ def modit_bench(reps=5):
         run["select_kept"] = ctx.select_lines(0, math.log10(0.0023), atm, 1700.0, T_scan, 2)[1]
         out["runs"].append(run)
     ctx.close()
-    out["emission"] = modit_emission_bench(reps)
+    out["emission"] = modit_emission_bench(wl, reps)
     out["emission"]["direct_single_layer_fp32_ms"] = out["runs"][-1]["direct_fp32_ms"]
     return out
 
@@ -364,13 +452,16 @@ def config1_bench(reps=50):
     return out
 
 
-def config3_direct_bench():
-    """One FP32 forward spectrum (F0, no response) of the whole config-3
-    workload by the direct sum: 1e7 lines x 100,000 points x 100 layers."""
+def config3_direct_bench(wl=None, fp64_layer=True):
+    """The throughput workload by the direct sum: one FP32 forward spectrum
+    (F0, no response) of all of config 3 (1e7 lines x 100,000 points x 100
+    layers = 1e14 pair evaluations), with the Voigt kernel's share and its
+    per-tier pair fractions; then one layer (1300 K, 1 bar) of the same list
+    in FP32 and in the plain FP64 form (1e12 evaluations each)."""
     import torch
     import synth
     from paper_2105_14782_amd import api
-    wl = synth.make_config(3, "full")
+    wl = wl if wl is not None else synth.make_config(3, "full")
     ctx = api.Context(0)
     ctx.set_lines(0, wl.lines[0])
     ctx.set_grid(wl.nu)
@@ -383,14 +474,34 @@ def config3_direct_bench():
     dt = time.perf_counter() - t
     nl, kms, evals = ctx.profile_read()
     near = ctx.profile_read_near()
-    ctx.close()
+    cut = ctx.profile_read_far_cut()
+    outer = ctx.profile_read_far_outer()
+    ctx.profile(False)
     total = wl.lines[0].n * wl.nu.size * wl.atmos.P_bar.size
-    return {"workload": "config-3 direct-sum FP32 spectrum: 1e7 lines, 100,000 points, 100 layers",
-            "s": dt, "evals": total, "evals_per_s": total / dt, "voigt_kernel_ms": kms,
-            "near_fraction": near / max(evals, 1.0)}
+    out = {"workload": "config-3 direct-sum FP32 spectrum: 1e7 lines, 100,000 points, 100 layers",
+           "s": dt, "evals": total, "evals_per_s": total / dt, "voigt_kernel_ms": kms,
+           "voigt_launches": nl, "voigt_share": 1e-3 * kms / dt,
+           "near_fraction": near / max(evals, 1.0), "far_cut_fraction": cut / max(evals, 1.0),
+           "outer_fraction": outer / max(evals, 1.0),
+           "far_fraction": (evals - near - cut - outer) / max(evals, 1.0)}
+    if fp64_layer:
+        T, P = 1300.0, 1.0
+        ts = {}
+        for prec in ("fp32", "fp64"):
+            ctx.cross_section(0, T, P, prec)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            ctx.cross_section(0, T, P, prec)
+            torch.cuda.synchronize()
+            ts[prec] = time.perf_counter() - t
+        out["one_layer"] = {"T_K": T, "P_bar": P, "evals": wl.lines[0].n * wl.nu.size,
+                            "fp32_ms": 1e3 * ts["fp32"], "fp64_plain_ms": 1e3 * ts["fp64"],
+                            "fp32_over_fp64_plain": ts["fp64"] / ts["fp32"]}
+    ctx.close()
+    return out
 
 
-def modit_emission_bench(reps=5):
+def modit_emission_bench(wl=None, reps=5):
     """The whole config-3 emission spectrum (all 1e7 lines, 100 layers, no
     response) with MODIT opacities, FP32 and FP64; the direct sum would take
     100 single-layer sums of all lines."""
@@ -398,7 +509,7 @@ def modit_emission_bench(reps=5):
     import synth
     from dataclasses import replace
     from paper_2105_14782_amd import api
-    wl = synth.make_config(3, "full")
+    wl = wl if wl is not None else synth.make_config(3, "full")
     ctx = api.Context(0)
     ctx.set_lines(0, wl.lines[0])
     ctx.set_grid(wl.nu)
@@ -419,13 +530,15 @@ def modit_emission_bench(reps=5):
 SERVE_MARGIN = 260   # output margin (points) at R0 = 1e6: rotation + RV + 6-sigma IP reach < 200
 
 
-def serving_bench(n_req, loads=(0.9,), n_streams=4, budget=48 << 30):
+def serving_bench(n_req, loads=(0.9,), n_streams=4, budget=48 << 30, n_cap=200):
     """Continuous batching on a stream shaped like the serving configuration:
     16 resident lists (1e3-1e6 lines, 3900-5100 cm^-1), windows of 2e3-1e5
     points on an R0 = 1e6 grid, 50-200 layers, HMC-like parameter walk.
-    Capacity is measured closed-loop first; then Poisson arrivals at each
-    load x capacity give the latency distribution (arrival -> spectrum on
-    device).  The top-level latency fields are those of the first load."""
+    Capacity is measured closed-loop first (n_cap requests submitted at
+    once); then n_req Poisson arrivals at each load x capacity give the
+    latency distribution, from each request's scheduled arrival to its
+    spectrum on the device.  The top-level latency fields are those of the
+    first load."""
     import torch
     import synth
     from paper_2105_14782_amd import api, serve
@@ -449,8 +562,10 @@ def serving_bench(n_req, loads=(0.9,), n_streams=4, budget=48 << 30):
     warm = args(synth.serving_requests(n_streams, 0.0, nu_master=nu, seed=7))
     srv = serve.Server(ctx, n_streams=n_streams, mem_budget_bytes=budget)
     serve.run_stream(srv, warm)
-    closed = args(synth.serving_requests(max(8, n_req // 2), 0.0, nu_master=nu, seed=11))
+    closed = args(synth.serving_requests(n_cap, 0.0, nu_master=nu, seed=11))
     cap = serve.run_stream(srv, closed)
+    print(f"serving: capacity {cap['spectra_per_s']:.2f} spectra/s over {n_cap} requests", file=sys.stderr,
+          flush=True)
     evals = lambda reqs: sum((lists[a.species[0]].n + lists[a.species[1]].n) * a.grid_len * len(a.P_bar)
                              for a, _ in reqs)
     runs = []
@@ -458,18 +573,25 @@ def serving_bench(n_req, loads=(0.9,), n_streams=4, budget=48 << 30):
         rate = rho * cap["spectra_per_s"]
         reqs = synth.serving_requests(n_req, rate, nu_master=nu)
         arr = np.array([q.arrival_s for q in reqs])
+        st0 = srv.stats()
         res = serve.run_stream(srv, args(reqs), arr)
+        st1 = srv.stats()
+        lat = res["latency_s"]
         runs.append({"load": rho, "arrival_rate_hz": rate, "spectra_per_s": res["spectra_per_s"],
-                     "p50_ms": res["p50_ms"], "p99_ms": res["p99_ms"]})
+                     "p50_ms": res["p50_ms"], "p99_ms": res["p99_ms"],
+                     "p90_ms": float(np.percentile(lat, 90) * 1e3), "max_ms": float(lat.max() * 1e3),
+                     "bypasses": st1["bypasses"] - st0["bypasses"]})
         print(f"serving: load {rho}: p50 {res['p50_ms']:.0f} ms, p99 {res['p99_ms']:.0f} ms", file=sys.stderr, flush=True)
     st = srv.stats()
     srv.close()
     ctx.close()
     first = runs[0]
-    return {"requests": n_req, "streams": n_streams, "capacity_spectra_per_s": cap["spectra_per_s"],
+    return {"requests": n_req, "capacity_requests": n_cap, "streams": n_streams,
+            "capacity_spectra_per_s": cap["spectra_per_s"],
             "capacity_evals_per_s": evals(closed) / cap["wall_s"],
             "arrival_rate_hz": first["arrival_rate_hz"], "spectra_per_s": first["spectra_per_s"],
-            "p50_ms": first["p50_ms"], "p99_ms": first["p99_ms"], "loads": runs,
+            "p50_ms": first["p50_ms"], "p99_ms": first["p99_ms"], "latency_from": "scheduled arrival",
+            "loads": runs, "peak_in_flight": st["peak_in_flight"],
             "mem_peak_gb": st["mem_peak_bytes"] / 2 ** 30, "mem_budget_gb": st["mem_budget_bytes"] / 2 ** 30}
 
 
@@ -480,6 +602,9 @@ def main():
         return
     if args.summarize_valu:
         summarize_valu(args.summarize_valu, os.path.join(ROOT, VALU_PROFILE))
+        return
+    if args.summarize_flops:
+        summarize_flops(args.summarize_flops, os.path.join(ROOT, FLOPS_PROFILE))
         return
     if args.summarize_stats:
         summarize_stats(args.summarize_stats, os.path.join(ROOT, STATS_PROFILE))
@@ -505,7 +630,8 @@ def main():
         print(json.dumps({"config3_direct": config3_direct_bench()}), flush=True)
         return
     if args.serving_only:
-        print(json.dumps({"serving": serving_bench(args.serve_requests, args.serve_load)}), flush=True)
+        print(json.dumps({"serving": serving_bench(args.serve_requests, args.serve_load,
+                                                   n_cap=args.serve_capacity_requests)}), flush=True)
         return
     import torch
     import synth
@@ -603,6 +729,9 @@ def main():
     flops_per_launch = (FLOPS_PER_EVAL_NEAR * knear + FLOPS_PER_EVAL_FAR * (kevals - knear - kcut - kout)
                         + FLOPS_PER_EVAL_FAR_CUT * kcut + FLOPS_PER_EVAL_OUTER * kout) / max(nl, 1)
     achieved = flops_per_launch / (avg_launch_ms * 1e-3) / 1e12
+    hw = recorded_counter_flops()
+    counter_tflops = None if hw is None else hw[0] / (avg_launch_ms * 1e-3) / 1e12
+    counter_tflops64 = None if hw is None else hw[1] / (avg_launch_ms * 1e-3) / 1e12
     out = {
         "metric": METRIC,
         "value": evals / (ms * 1e-3),
@@ -630,6 +759,14 @@ def main():
         "leapfrog_loss_grad": {"ms_per_call": tloss * 1e3, "evals_per_s": evals / tloss},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS, "traffic": recorded_traffic(),
+                     "model_tflops": achieved,
+                     "counter_tflops": counter_tflops, "counter_fp64_tflops": counter_tflops64,
+                     "counter_frac": None if counter_tflops is None else counter_tflops / PEAK_FP32_TFLOPS,
+                     "non_packed_peak": PEAK_FP32_TFLOPS / 2,
+                     "evals_counted": "every (line, grid point, layer) pair is evaluated, but by tier: the "
+                                      "full wing polynomial (near tier, core pairs by the rational w), the "
+                                      "polynomial cut after r^3 (far) or after r^2 (outer), each cut below "
+                                      "FP32 rounding of that pair; see the *_fraction fields",
                      "kernel": "k_voigt_f32<tangent>", "avg_launch_ms": avg_launch_ms,
                      "launches": nl, "evals_per_launch": kevals / max(nl, 1),
                      "near_fraction": knear / max(kevals, 1.0),
@@ -641,9 +778,15 @@ def main():
     }
     ctx.close()
     if args.serve_requests > 0:
-        out["serving"] = serving_bench(args.serve_requests, args.serve_load)
+        out["serving"] = serving_bench(args.serve_requests, args.serve_load, n_cap=args.serve_capacity_requests)
+    wl3 = None
+    if not args.no_config3 or not args.no_modit:
+        wl3 = synth.make_config(3, "full")
+    if not args.no_config3:
+        out["config3"] = config3_direct_bench(wl3)
+        print(f"config3: direct FP32 spectrum {out['config3']['s']:.2f} s", file=sys.stderr, flush=True)
     if not args.no_modit:
-        out["modit"] = modit_bench()
+        out["modit"] = modit_bench(wl3)
     out["config1"] = config1_bench()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, theta, args.cpu_points)
