@@ -700,6 +700,7 @@ def main():
 
     t32 = time_fwd("fp32", max(3, args.steps))
     t64 = time_fwd("fp64", args.fp64_reps)
+    t64t = time_fwd("fp64_tiled", max(3, args.fp64_reps))
 
     # one leapfrog step of the sampler: Gaussian likelihood and its gradient in one pass
     Fd = ctx.emission_flux(atm, resp, "fp32")
@@ -754,7 +755,12 @@ def main():
         "p99_ms": float(np.percentile(lat, 99)),
         "forward_fp32": {"spectra_per_s": 1.0 / t32, "evals_per_s": evals / t32},
         "forward_fp64_plain": {"spectra_per_s": 1.0 / t64, "evals_per_s": evals / t64},
+        "forward_fp64_tiled": {"spectra_per_s": 1.0 / t64t, "evals_per_s": evals / t64t,
+                               "form": "the FP32 form's tiling, staging, near/far split and core branch in "
+                                       "FP64, full asymptotic polynomial on every wing pair"},
         "fp32_over_fp64_spectra": t64 / t32,
+        "fp32_over_fp64_plain_spectra": t64 / t32,
+        "fp32_over_fp64_tiled_spectra": t64t / t32,
         "flux_jvp": {"ms_per_call": tjvp * 1e3, "evals_per_s": evals / tjvp},
         "leapfrog_loss_grad": {"ms_per_call": tloss * 1e3, "evals_per_s": evals / tloss},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",

@@ -64,7 +64,14 @@ typedef enum {
   EXO_FP32_KAHAN = 0,
   /* The plain FP64 form: the paper's hjert written out in double precision
    * per (line, grid point) with IEEE divisions; plain FP64 accumulation. */
-  EXO_FP64 = 1
+  EXO_FP64 = 1,
+  /* The FP32 form's algorithm in double precision: the same thread
+   * mapping, per-wave record staging, near/far split and core branch (the
+   * rational approximation of w), with the full asymptotic polynomial on
+   * every wing pair and plain FP64 accumulation.  For measuring the cost of
+   * precision alone.  Forward only (exo_cross_section, exo_emission_flux);
+   * outputs are double. */
+  EXO_FP64_TILED = 2
 } exo_precision;
 
 typedef enum {
@@ -140,7 +147,8 @@ int exo_set_grid(exo_ctx* ctx, int64_t n_nu, const double* nu);
 /* Single-layer cross-section of species s at (T_K, P_bar) on the whole grid
  * (Eq. crosssec summed over lines):
  *   sigma(nu_j) = sum_l S_l(T) V(nu_j - nu_l; beta_l(T), gamma_l(T, P)).
- * sigma_dev: device, [n_nu] float (EXO_FP32_KAHAN) or double (EXO_FP64).
+ * sigma_dev: device, [n_nu] float (EXO_FP32_KAHAN) or double (EXO_FP64,
+ * EXO_FP64_TILED).
  * Errors: EXO_ENOTSET, EXO_EINVAL (T <= 0, P < 0, bad precision),
  * EXO_ENOMEM, EXO_EDEVICE. */
 int exo_cross_section(exo_ctx* ctx, int s, double T_K, double P_bar, int precision,
@@ -157,6 +165,7 @@ int exo_cross_section(exo_ctx* ctx, int s, double T_K, double P_bar, int precisi
  * clears what must start at zero, with a kernel): calls that overlap on one
  * GPU (other streams, threads or contexts) race, and the caller must
  * serialise them.
+ * precision: EXO_FP32_KAHAN or EXO_FP64.
  * Errors: as exo_cross_section, and EXO_ENOMEM (nothing launched) when the
  * call would need more than 128 MiB of scratch: 64 B (FP32) or 32 B (FP64)
  * per line, 64 KiB, and 8 B per grid point and line split (the splits bring
@@ -225,7 +234,7 @@ typedef struct {
 /* Emission spectrum F = k_G * k_R * F0 (Eq. model without the photometric
  * normalisation), or F0 on the whole model grid when `resp` is NULL.
  * flux_dev: device [out_len] (or [model grid length]) float for
- * EXO_FP32_KAHAN, double for EXO_FP64.
+ * EXO_FP32_KAHAN, double for EXO_FP64 and EXO_FP64_TILED.
  * Errors: EXO_ENOTSET, EXO_EINVAL, EXO_ENOMEM, EXO_EDEVICE. */
 int exo_emission_flux(exo_ctx* ctx, const exo_atmos* atm, const exo_response* resp,
                       int precision, void* flux_dev, void* stream);

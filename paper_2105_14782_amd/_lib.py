@@ -13,7 +13,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("EXO_LIB_PATH") or os.path.join(_HERE, "libexohip.so")
 
 EXO_OK, EXO_EINVAL, EXO_ENOMEM, EXO_ENOTSET, EXO_EDEVICE = 0, -1, -2, -3, -4
-EXO_FP32_KAHAN, EXO_FP64 = 0, 1
+EXO_FP32_KAHAN, EXO_FP64, EXO_FP64_TILED = 0, 1, 2
 EXO_QR_POWER, EXO_QR_TABLE = 0, 1
 EXO_FB_PLANCK_BOTTOM, EXO_FB_ZERO = 0, 1
 EXO_OPACITY_LPF, EXO_OPACITY_MODIT = 0, 1

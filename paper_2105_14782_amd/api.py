@@ -15,7 +15,7 @@ import torch
 
 from . import _lib as L
 
-PRECISIONS = {"fp32": L.EXO_FP32_KAHAN, "fp64": L.EXO_FP64}
+PRECISIONS = {"fp32": L.EXO_FP32_KAHAN, "fp64": L.EXO_FP64, "fp64_tiled": L.EXO_FP64_TILED}
 
 
 def _prec(p) -> int:
@@ -155,7 +155,7 @@ class Context:
     # -- evaluation ---------------------------------------------------------
     def cross_section(self, slot: int, T: float, P_bar: float, precision="fp32", out=None, stream=None):
         p = _prec(precision)
-        dt = torch.float64 if p == L.EXO_FP64 else torch.float32
+        dt = torch.float32 if p == L.EXO_FP32_KAHAN else torch.float64
         if out is None:
             out = torch.empty(self.n_nu, dtype=dt, device=f"cuda:{self.device}")
         assert out.dtype == dt and out.is_contiguous() and out.numel() == self.n_nu
@@ -169,7 +169,7 @@ class Context:
         by the library (its scratch is a fixed per-device array shared by all
         such calls on the GPU: overlapping calls race)."""
         p = _prec(precision)
-        dt = torch.float64 if p == L.EXO_FP64 else torch.float32
+        dt = torch.float32 if p == L.EXO_FP32_KAHAN else torch.float64
         assert out.dtype == dt and out.is_contiguous() and out.numel() == self.n_nu
         L.check(self._lib.exo_cross_section_noalloc(self._h, int(slot), float(T), float(P_bar), p,
                                                     ctypes.c_void_p(out.data_ptr()), _stream(stream)))
@@ -179,7 +179,7 @@ class Context:
                             out=None, stream=None):
         """MODIT cross-section (Sec. 2.1.2) on the context's log-uniform grid."""
         p = _prec(precision)
-        dt = torch.float64 if p == L.EXO_FP64 else torch.float32
+        dt = torch.float32 if p == L.EXO_FP32_KAHAN else torch.float64
         if out is None:
             out = torch.empty(self.n_nu, dtype=dt, device=f"cuda:{self.device}")
         assert out.dtype == dt and out.is_contiguous() and out.numel() == self.n_nu
@@ -210,7 +210,7 @@ class Context:
     def emission_flux(self, atmos: Atmos, response: Optional[Response] = None, precision="fp32",
                       out=None, stream=None):
         p = _prec(precision)
-        dt = torch.float64 if p == L.EXO_FP64 else torch.float32
+        dt = torch.float32 if p == L.EXO_FP32_KAHAN else torch.float64
         n = self._out_len(atmos, response)
         if out is None:
             out = torch.empty(n, dtype=dt, device=f"cuda:{self.device}")

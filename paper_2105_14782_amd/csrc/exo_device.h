@@ -67,6 +67,18 @@ struct LineRec64 {
   double A, beta, gam, erfcxa;
 };
 
+// Tiled FP64 form: the fields of LineRec in double precision, with the full
+// wing polynomial (no tier truncation).
+struct LineRec64T {
+  double e[7];    // wing polynomial, amplitude included
+  double gam2;    // gamma^2
+  double thr;     // 2 beta^2 * 111: core branch iff D < thr
+  double winv;    // 1 / (sqrt2 beta)
+  double a;       // gamma / (sqrt2 beta)
+  double acore;   // amplitude / (sqrt(2 pi) beta)
+};
+static_assert(sizeof(LineRec64T) == 96, "LineRec64T layout");
+
 // ---------------------------------------------------------------------------
 // Record construction (FP64) from the line state at one layer.
 //   A      amplitude (cross-section: S(T) [* column factor] [* scale])
@@ -127,6 +139,26 @@ __device__ inline void make_line_record(double A, double beta, double gam, doubl
     for (int k = 0; k < 5; ++k) t.pad[k] = 0.f;
     *RT = t;
   }
+}
+
+// The same record in FP64 for the tiled FP64 form (forward only).
+__device__ inline void make_line_record64t(double A, double beta, double gam, LineRec64T* R) {
+  const double b = beta * beta, g = gam * gam;
+  const double E0 = A * gam / kPi;
+  LineRec64T r;
+  r.e[0] = E0;
+  r.e[1] = E0 * (3.0 * b);
+  r.e[2] = E0 * (15.0 * b * b - 4.0 * b * g);
+  r.e[3] = E0 * (105.0 * b * b * b - 60.0 * b * b * g);
+  r.e[4] = E0 * (48.0 * b * b * g * g - 840.0 * b * b * b * g);
+  r.e[5] = E0 * (1680.0 * b * b * b * g * g);
+  r.e[6] = E0 * (-960.0 * b * b * b * g * g * g);
+  r.gam2 = g;
+  r.thr = 2.0 * kHjertSwitch * b;
+  r.winv = 1.0 / (kSqrt2 * beta);
+  r.a = gam * r.winv;
+  r.acore = A * r.winv / kSqrtPi;
+  *R = r;
 }
 
 // ---------------------------------------------------------------------------

@@ -116,21 +116,26 @@ struct OpacityPlan {
   size_t rec, rect, rec64, part, part_t;
   size_t tier;  // FP32 far tier: per layer of a chunk, the gamma^2 maximum bits and the squared reach
 };
-OpacityPlan plan_opacity(int64_t n_lines, int nlay, int64_t ng, bool fp64, bool tangent);
+// tiled64 (with fp64): the tiled FP64 form's records and splits.
+OpacityPlan plan_opacity(int64_t n_lines, int nlay, int64_t ng, bool fp64, bool tangent, bool tiled64 = false);
 // component-wise largest plan over the species of an atmosphere
-OpacityPlan plan_opacity_all(const exo_ctx* c, const exo_atmos* a, int64_t gl, bool fp64, bool tangent);
+OpacityPlan plan_opacity_all(const exo_ctx* c, const exo_atmos* a, int64_t gl, bool fp64, bool tangent,
+                             bool tiled64 = false);
 int reserve_opacity(Workspace& ws, const OpacityPlan& P);
 // Upper bound of the workspace bytes one evaluation reserves (arena sizing).
 size_t estimate_workspace(const exo_ctx* c, const exo_atmos* a, const exo_response* r, bool fp64,
                           bool vjp);
-int voigt_launch_profiled(exo_ctx* c, const VoigtArgs& A, bool fp64, bool tan, hipStream_t st);
+int voigt_launch_profiled(exo_ctx* c, const VoigtArgs& A, bool fp64, bool tan, hipStream_t st,
+                          bool tiled = false);
 // d_T == nullptr: one layer at (T_one, P_one), passed to the kernels by value.
 // adaptive_scale (FP32, one layer at (T_one, P_one)): amp_scale is replaced
 // by a power of two chosen on the device from the largest line strength.
+// tiled64 (with fp64): the tiled FP64 form instead of the plain one.
 int species_opacity(exo_ctx* c, Workspace& ws, const Species& sp, const double* d_T,
                     const double* d_P, const double* d_col, int nlay, double amp_scale, bool fp64,
                     bool tangent, const double* d_nu, int64_t ng, void* out, float* out_t,
-                    hipStream_t st, double T_one = 0.0, double P_one = 0.0, bool adaptive_scale = false);
+                    hipStream_t st, double T_one = 0.0, double P_one = 0.0, bool adaptive_scale = false,
+                    bool tiled64 = false);
 // MODIT cross-sections (d_col == NULL) or optical depths col_n sigma clamped
 // at zero, of nlay layers, from the lines with nu_lo <= nu_c <= nu_hi.
 int modit_opacity(exo_ctx* c, Workspace& ws, const Species& sp, const double* d_T, const double* d_P,
@@ -140,7 +145,7 @@ size_t modit_workspace(const Species& sp, double nu_lo, double nu_hi, int64_t ng
 int validate_atmos(const exo_ctx* c, const exo_atmos* a, int64_t* gb, int64_t* gl);
 int prepare_response(const exo_ctx* c, const exo_response* r, int64_t gl, RespDev* R);
 int forward_core(exo_ctx* c, Workspace& ws, const exo_atmos* a, int64_t gb, int64_t gl, bool fp64,
-                 bool tangent, hipStream_t st);
+                 bool tangent, hipStream_t st, bool tiled64 = false);
 int apply_response(Workspace& ws, RespDev& R, const double* F0, void* out, bool out64, hipStream_t st);
 int emission_impl(exo_ctx* c, Workspace& ws, const exo_atmos* a, const exo_response* r,
                   int precision, void* flux, hipStream_t st);

@@ -422,7 +422,7 @@ extern "C" int exo_profile_read(exo_ctx* c, int64_t* nl, double* ms, double* eva
   return EXO_OK;
 }
 
-int exo::voigt_launch_profiled(exo_ctx* c, const VoigtArgs& A, bool fp64, bool tan, hipStream_t st) {
+int exo::voigt_launch_profiled(exo_ctx* c, const VoigtArgs& A, bool fp64, bool tan, hipStream_t st, bool tiled) {
   ProfRec pr{};
   const bool prof = c && c->profile;
   if (prof) {
@@ -432,7 +432,7 @@ int exo::voigt_launch_profiled(exo_ctx* c, const VoigtArgs& A, bool fp64, bool t
   }
   VoigtArgs Ap = A;
   if (prof && !fp64) Ap.near_pairs = (unsigned long long*)c->prof_near.p;
-  HIP_TRY(launch_voigt(Ap, fp64, tan, st));
+  HIP_TRY(launch_voigt(Ap, fp64, tan, st, tiled));
   if (prof) {
     HIP_TRY(hipEventRecord(pr.b, st));
     pr.evals = (double)A.n_lines * (double)A.ng * (double)A.nlay;
@@ -473,9 +473,10 @@ static constexpr size_t kRecBudget = size_t(4) << 30;
 // SIMD): a wave's near lines and core pairs fall in one split, so finer
 // splits even out the workgroups' run times (config 2: 5 splits instead of 2,
 // 2.8 % faster per step; 16384 the same, 4096 half the gain).
-static void split_plan(int64_t ng, int nl, int64_t n_lines, bool fp64, int64_t* ks_out,
+static void split_plan(int64_t ng, int nl, int64_t n_lines, bool one_point, int64_t* ks_out,
                        int64_t* lps_out) {
-  const int64_t G = fp64 ? 1 : kVoigtG;
+  // one_point: the plain FP64 form (one grid point per thread)
+  const int64_t G = one_point ? 1 : kVoigtG;
   const int64_t tiles = (ng + 256 * G - 1) / (256 * G);
   const int64_t blocks = tiles * nl;
   int64_t ks = 1;
@@ -486,13 +487,16 @@ static void split_plan(int64_t ng, int nl, int64_t n_lines, bool fp64, int64_t* 
   *lps_out = lps;
 }
 
-OpacityPlan exo::plan_opacity(int64_t n_lines, int nlay, int64_t ng, bool fp64, bool tangent) {
+OpacityPlan exo::plan_opacity(int64_t n_lines, int nlay, int64_t ng, bool fp64, bool tangent, bool tiled64) {
   OpacityPlan P{};
-  const size_t per_layer = (size_t)n_lines * (fp64 ? sizeof(LineRec64)
+  tiled64 = tiled64 && fp64;
+  const size_t rec64_size = tiled64 ? sizeof(LineRec64T) : sizeof(LineRec64);
+  const size_t per_layer = (size_t)n_lines * (fp64 ? rec64_size
                                                    : sizeof(LineRec) + (tangent ? sizeof(LineRecT) : 0));
   P.nlc = (int)std::max<size_t>(1, std::min<size_t>((size_t)nlay, kRecBudget / per_layer));
   if (fp64) {
-    P.rec64 = (size_t)P.nlc * n_lines * sizeof(LineRec64);
+    // the tiled FP64 records share the plain form's buffer
+    P.rec64 = (size_t)P.nlc * n_lines * rec64_size;
   } else {
     P.rec = (size_t)P.nlc * n_lines * sizeof(LineRec);
     P.tier = kTierBytes;
@@ -503,7 +507,7 @@ OpacityPlan exo::plan_opacity(int64_t n_lines, int nlay, int64_t ng, bool fp64, 
   for (int nl : {P.nlc, nlay % P.nlc}) {
     if (nl <= 0) continue;
     int64_t ks, lps;
-    split_plan(ng, nl, n_lines, fp64, &ks, &lps);
+    split_plan(ng, nl, n_lines, fp64 && !tiled64, &ks, &lps);
     if (ks > 1 || !fp64) {
       const size_t pb = (size_t)ks * nl * ng * (fp64 ? sizeof(double) : sizeof(float2));
       P.part = std::max(P.part, pb);
@@ -514,10 +518,10 @@ OpacityPlan exo::plan_opacity(int64_t n_lines, int nlay, int64_t ng, bool fp64, 
 }
 
 OpacityPlan exo::plan_opacity_all(const exo_ctx* c, const exo_atmos* a, int64_t gl, bool fp64,
-                                  bool tangent) {
+                                  bool tangent, bool tiled64) {
   OpacityPlan P{};
   for (int m = 0; m < a->n_species; ++m) {
-    const OpacityPlan Q = plan_opacity(c->sp[a->species[m]].n, a->n_layers, gl, fp64, tangent);
+    const OpacityPlan Q = plan_opacity(c->sp[a->species[m]].n, a->n_layers, gl, fp64, tangent, tiled64);
     P.rec = std::max(P.rec, Q.rec);
     P.rect = std::max(P.rect, Q.rect);
     P.rec64 = std::max(P.rec64, Q.rec64);
@@ -542,9 +546,12 @@ int exo::reserve_opacity(Workspace& ws, const OpacityPlan& P) {
 int exo::species_opacity(exo_ctx* c, Workspace& ws, const Species& sp, const double* d_T,
                          const double* d_P, const double* d_col, int nlay, double amp_scale,
                          bool fp64, bool tangent, const double* d_nu, int64_t ng, void* out,
-                         float* out_t, hipStream_t st, double T_one, double P_one, bool adaptive_scale) {
+                         float* out_t, hipStream_t st, double T_one, double P_one, bool adaptive_scale,
+                         bool tiled64) {
   const LinesDev L = lines_dev(sp);
-  const OpacityPlan P = plan_opacity(sp.n, nlay, ng, fp64, tangent);
+  tiled64 = tiled64 && fp64;
+  if (tiled64 && tangent) return set_err(EXO_EINVAL, "the tiled FP64 form has no tangents");
+  const OpacityPlan P = plan_opacity(sp.n, nlay, ng, fp64, tangent, tiled64);
   int rc;
   if ((rc = reserve_opacity(ws, P))) return rc;
   const int nlc = P.nlc;
@@ -569,7 +576,8 @@ int exo::species_opacity(exo_ctx* c, Workspace& ws, const Species& sp, const dou
     HIP_TRY(launch_line_records(L, d_T, d_P, d_col, T_one, P_one, amp_scale, amax, oscale, l0, nl,
                                 fp64 ? nullptr : (LineRec*)ws.rec.p,
                                 (!fp64 && tangent) ? (LineRecT*)ws.rect.p : nullptr,
-                                fp64 ? (LineRec64*)ws.rec64.p : nullptr, g2bits, st));
+                                (fp64 && !tiled64) ? (LineRec64*)ws.rec64.p : nullptr, g2bits, st,
+                                tiled64 ? (LineRec64T*)ws.rec64.p : nullptr));
     if (!fp64)
       HIP_TRY(launch_far_reach((const LineRec*)ws.rec.p, sp.n, nl, tangent, g2bits, reach2, t3, outer2, amax, st));
     VoigtArgs A{};
@@ -579,7 +587,8 @@ int exo::species_opacity(exo_ctx* c, Workspace& ws, const Species& sp, const dou
     A.n_lines = sp.n;
     A.rec = (const LineRec*)ws.rec.p;
     A.rect = (const LineRecT*)ws.rect.p;
-    A.rec64 = (const LineRec64*)ws.rec64.p;
+    A.rec64 = tiled64 ? nullptr : (const LineRec64*)ws.rec64.p;
+    A.rec64t = tiled64 ? (const LineRec64T*)ws.rec64.p : nullptr;
     A.far_reach2 = reach2;
     A.far_t3 = t3;
     A.far_outer2 = outer2;
@@ -594,7 +603,7 @@ int exo::species_opacity(exo_ctx* c, Workspace& ws, const Species& sp, const dou
       A.out_t = tangent ? out_t + (int64_t)l0 * ng : nullptr;
     }
     int64_t ks, lps;
-    split_plan(ng, nl, sp.n, fp64, &ks, &lps);
+    split_plan(ng, nl, sp.n, fp64 && !tiled64, &ks, &lps);
     A.lines_per_split = lps;
     A.ksplit = (int)ks;
     if (ks > 1 || !fp64) {
@@ -602,7 +611,7 @@ int exo::species_opacity(exo_ctx* c, Workspace& ws, const Species& sp, const dou
       A.part_t = (float2*)ws.part_t.p;
       A.part64 = (double*)ws.part.p;
     }
-    if ((rc = voigt_launch_profiled(ws.no_alloc ? nullptr : c, A, fp64, tangent, st))) return rc;
+    if ((rc = voigt_launch_profiled(ws.no_alloc ? nullptr : c, A, fp64, tangent, st, tiled64))) return rc;
   }
   if (!fp64) ws.tier_zeroed = ws.tier.p;
   return EXO_OK;
@@ -834,13 +843,15 @@ extern "C" int exo_cross_section(exo_ctx* c, int s, double T, double P, int prec
   if (c->n_nu < 2) return set_err(EXO_ENOTSET, "grid not set");
   if (!(T > 0) || !std::isfinite(T) || !(P >= 0) || !std::isfinite(P))
     return set_err(EXO_EINVAL, "need T > 0 and P >= 0");
-  if (precision != EXO_FP32_KAHAN && precision != EXO_FP64) return set_err(EXO_EINVAL, "bad precision");
+  if (precision != EXO_FP32_KAHAN && precision != EXO_FP64 && precision != EXO_FP64_TILED)
+    return set_err(EXO_EINVAL, "bad precision");
   if (!sigma) return set_err(EXO_EINVAL, "sigma_dev is NULL");
   HIP_TRY(hipSetDevice(c->device));
   hipStream_t st = (hipStream_t)stream;
   std::lock_guard<std::mutex> g(c->mu);
   Workspace& ws = c->ws;
-  const bool fp64 = precision == EXO_FP64;
+  const bool fp64 = precision != EXO_FP32_KAHAN;
+  const bool tiled64 = precision == EXO_FP64_TILED;
   // FP32 records carry the amplitude times a power of two chosen on the
   // device from the call's largest line strength, so that single-molecule
   // strengths (1e-30 .. 1e8 cm/molecule) stay far from both ends of the
@@ -848,7 +859,7 @@ extern "C" int exo_cross_section(exo_ctx* c, int s, double T, double P, int prec
   // (T, P) go to the record kernel by value: no staging copy on this path
   return with_ws(ws, st, [&] {
     return species_opacity(c, ws, c->sp[s], nullptr, nullptr, nullptr, 1, 1.0, fp64, false,
-                           (const double*)c->d_nu.p, c->n_nu, sigma, nullptr, st, T, P, !fp64);
+                           (const double*)c->d_nu.p, c->n_nu, sigma, nullptr, st, T, P, !fp64, tiled64);
   });
 }
 
@@ -971,7 +982,7 @@ int exo::prepare_response(const exo_ctx* c, const exo_response* r, int64_t gl, R
 
 // Forward model into ws.tau (and ws.taut), then F0 into ws.F0.
 int exo::forward_core(exo_ctx* c, Workspace& ws, const exo_atmos* a, int64_t gb, int64_t gl,
-                      bool fp64, bool tangent, hipStream_t st) {
+                      bool fp64, bool tangent, hipStream_t st, bool tiled64) {
   const int NL = a->n_layers, M = a->n_species;
   int rc;
   // parameter block: P, then the layer temperatures when the atmosphere gives them
@@ -1017,7 +1028,7 @@ int exo::forward_core(exo_ctx* c, Workspace& ws, const exo_atmos* a, int64_t gb,
   const bool modit = a->opacity == EXO_OPACITY_MODIT;
   if (modit && tangent) return set_err(EXO_EINVAL, "the MODIT opacity has no tangents");
   // every species' buffers fit in the largest plan, reserved once up front
-  if (!modit && (rc = reserve_opacity(ws, plan_opacity_all(c, a, gl, fp64, tangent)))) return rc;
+  if (!modit && (rc = reserve_opacity(ws, plan_opacity_all(c, a, gl, fp64, tangent, tiled64)))) return rc;
   const double* d_nu = (const double*)c->d_nu.p + gb;
   for (int m = 0; m < M; ++m) {
     const Species& sp = c->sp[a->species[m]];
@@ -1028,7 +1039,7 @@ int exo::forward_core(exo_ctx* c, Workspace& ws, const exo_atmos* a, int64_t gb,
                          c->h_nu[gb], c->h_nu[gb + gl - 1], gl, out, st);
     else
       rc = species_opacity(c, ws, sp, A.T, A.P, A.col + (size_t)m * NL, NL, 1.0, fp64, tangent, d_nu, gl,
-                           out, out_t, st);
+                           out, out_t, st, 0.0, 0.0, false, tiled64);
     if (rc) return rc;
   }
   if ((rc = ws.reserve(ws.F0, (size_t)gl * sizeof(double)))) return rc;
@@ -1108,12 +1119,13 @@ int exo::emission_impl(exo_ctx* c, Workspace& ws, const exo_atmos* a, const exo_
   int64_t gb, gl;
   int rc;
   if ((rc = validate_atmos(c, a, &gb, &gl))) return rc;
-  if (precision != EXO_FP32_KAHAN && precision != EXO_FP64) return set_err(EXO_EINVAL, "bad precision");
+  if (precision != EXO_FP32_KAHAN && precision != EXO_FP64 && precision != EXO_FP64_TILED)
+    return set_err(EXO_EINVAL, "bad precision");
   if (!flux) return set_err(EXO_EINVAL, "flux_dev is NULL");
   RespDev R{};
   if (r && (rc = prepare_response(c, r, gl, &R))) return rc;
-  const bool fp64 = precision == EXO_FP64;
-  if ((rc = forward_core(c, ws, a, gb, gl, fp64, false, st))) return rc;
+  const bool fp64 = precision != EXO_FP32_KAHAN;
+  if ((rc = forward_core(c, ws, a, gb, gl, fp64, false, st, precision == EXO_FP64_TILED))) return rc;
   if (r) return apply_response(ws, R, (const double*)ws.F0.p, flux, fp64, st);
   HIP_TRY(launch_cast_copy((const double*)ws.F0.p, flux, fp64, gl, st));
   return EXO_OK;

@@ -54,7 +54,8 @@ __global__ __launch_bounds__(256) void k_line_records(LinesDev L, const double* 
                                                       LineRec* __restrict__ rec,
                                                       LineRecT* __restrict__ rect,
                                                       LineRec64* __restrict__ rec64,
-                                                      unsigned int* __restrict__ g2max_bits) {
+                                                      unsigned int* __restrict__ g2max_bits,
+                                                      LineRec64T* __restrict__ rec64t) {
   const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool in = l < L.n;
   const int y = blockIdx.y;
@@ -66,6 +67,12 @@ __global__ __launch_bounds__(256) void k_line_records(LinesDev L, const double* 
   const double T = T_lay ? T_lay[n] : T_one, P = T_lay ? P_lay[n] : P_one;
   const double col = col_lay ? col_lay[n] : 1.0;
   const int64_t o = (int64_t)y * L.n + l;
+  if (rec64t) {
+    if (!in) return;
+    const LineState s = line_state(L, l, T, P);
+    make_line_record64t(s.S * col * amp_scale, s.beta, s.gam, rec64t + o);
+    return;
+  }
   if (rec64) {
     if (!in) return;
     const LineState s = line_state(L, l, T, P);
@@ -751,6 +758,124 @@ __global__ __launch_bounds__(256) void k_voigt_combine(VoigtArgs A) {
 }
 
 // ---------------------------------------------------------------------------
+// The tiled FP64 form: the FP32 sum's thread mapping, per-wave record
+// staging and core branch (core_w) in double precision, with the full
+// asymptotic polynomial on every wing pair (no far/outer truncation) and
+// plain FP64 accumulation.  Next to the FP32 sum it isolates the cost of
+// precision; next to the plain FP64 form, the cost of the paper's per-pair
+// evaluation.  Lines farther than the core reach sqrt(222) beta_max from
+// every point of a wave cannot have a core pair there: a prefix and a
+// suffix of the sorted list, summed without the core test.  Forward only.
+// ---------------------------------------------------------------------------
+constexpr int kChunk64 = 32;
+struct Stage64 {
+  double e[7][kChunk64];  // wing coefficients, one row per power of r
+  double gam2[kChunk64];
+  double nu[kChunk64];
+  double thr[kChunk64];
+  double winv[kChunk64];
+  double a[kChunk64];
+  double acore[kChunk64];
+};
+
+// 1/D in FP64: the hardware reciprocal and two Newton steps (each doubles
+// the number of correct bits of the ~23-bit estimate).
+__device__ __forceinline__ double rcp64(double D) {
+  double inv = __builtin_amdgcn_rcp(D);
+  inv = fma(inv, fma(-D, inv, 1.0), inv);
+  return fma(inv, fma(-D, inv, 1.0), inv);
+}
+
+template <bool NEAR, int G>
+__device__ __forceinline__ void lines64(int sb, int se, const LineRec64T* __restrict__ R,
+                                        const double* __restrict__ nuc, const double (&nuj)[G],
+                                        Stage64* __restrict__ st, int lane, double (&acc)[G]) {
+  for (int l0 = sb; l0 < se; l0 += kChunk64) {
+    const int l1 = min(l0 + kChunk64, se);
+    const int li = l0 + (lane & 31);
+    if (li < l1) {
+      const LineRec64T& q = R[li];
+      if (lane < 32) {
+#pragma unroll
+        for (int k = 0; k < 7; ++k) st->e[k][lane] = q.e[k];
+        st->gam2[lane] = q.gam2;
+      } else {
+        const int h = lane & 31;
+        st->nu[h] = nuc[li];
+        st->thr[h] = q.thr;
+        st->winv[h] = q.winv;
+        st->a[h] = q.a;
+        st->acore[h] = q.acore;
+      }
+    }
+    wave_lds_sync();
+    const int n = l1 - l0;
+#pragma unroll 1
+    for (int i = 0; i < n; ++i) {
+      double e[7];
+#pragma unroll
+      for (int k = 0; k < 7; ++k) e[k] = st->e[k][i];
+      const double g2 = st->gam2[i], nul = st->nu[i];
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        const double d = nuj[g] - nul;
+        const double D = fma(d, d, g2);
+        if (NEAR && D < st->thr[i]) {
+          double H, L;
+          core_w(d * st->winv[i], st->a[i], &H, &L);
+          acc[g] = fma(st->acore[i], H, acc[g]);
+        } else {
+          const double r = rcp64(D);
+          double h = fma(e[6], r, e[5]);
+          h = fma(h, r, e[4]);
+          h = fma(h, r, e[3]);
+          h = fma(h, r, e[2]);
+          h = fma(h, r, e[1]);
+          h = fma(h, r, e[0]);
+          acc[g] = fma(h, r, acc[g]);
+        }
+      }
+    }
+    wave_lds_sync();
+  }
+}
+
+template <int G>
+__global__ __launch_bounds__(256) void k_voigt_f64t(VoigtArgs A) {
+  const int y = blockIdx.y;
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  __shared__ Stage64 stage[4];
+  const int64_t tile0 = (int64_t)blockIdx.x * (256 * G);
+  double nuj[G];
+  load_points<G>(A, tile0, w, lane, nuj);
+  const int lb = (int)blockIdx.z * (int)A.lines_per_split;
+  const int le = min(lb + (int)A.lines_per_split, (int)A.n_lines);
+  const LineRec64T* __restrict__ R = A.rec64t + (int64_t)y * A.n_lines;
+  // the last line (largest centre) has the largest Doppler width, hence the
+  // largest core threshold of the layer
+  const double reach = sqrt(R[A.n_lines - 1].thr) * (1.0 + 1e-12);
+  const int64_t jw = tile0 + (int64_t)w * G * 64, jlast = A.ng - 1;
+  const double lo = A.nu[jw < jlast ? jw : jlast];
+  const double hi = A.nu[jw + G * 64 - 1 < jlast ? jw + G * 64 - 1 : jlast];
+  const int i0 = __builtin_amdgcn_readfirstlane(search_sorted<false>(A.nu_c, lb, le, lo - reach));
+  const int i1 = __builtin_amdgcn_readfirstlane(search_sorted<true>(A.nu_c, i0, le, hi + reach));
+  double acc[G];
+#pragma unroll
+  for (int g = 0; g < G; ++g) acc[g] = 0.0;
+  lines64<false, G>(lb, i0, R, A.nu_c, nuj, &stage[w], lane, acc);
+  lines64<true, G>(i0, i1, R, A.nu_c, nuj, &stage[w], lane, acc);
+  lines64<false, G>(i1, le, R, A.nu_c, nuj, &stage[w], lane, acc);
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+    const int64_t j = tile0 + (int64_t)(w * G + g) * 64 + lane;
+    if (j >= A.ng) continue;
+    if (A.ksplit == 1) A.out64[(int64_t)y * A.ld_out + j] = acc[g] * A.out_scale64;
+    else A.part64[((int64_t)blockIdx.z * A.nlay + y) * A.ng + j] = acc[g];
+  }
+}
+
+// ---------------------------------------------------------------------------
 // The plain FP64 form: per pair x = dnu/(sqrt2 beta), a = gamma/(sqrt2 beta),
 // H from hjert_f64, contribution A/(sqrt(2 pi) beta) H; plain accumulation.
 // Same thread-to-grid mapping as the FP32 kernel (G = 1).
@@ -837,16 +962,17 @@ hipError_t launch_line_records(const LinesDev& L, const double* T_lay, const dou
                                const double* col_lay, double T_one, double P_one, double amp_scale,
                                const unsigned long long* amax, float* oscale, int layer0, int nlay,
                                LineRec* rec, LineRecT* rect, LineRec64* rec64, unsigned int* g2max_bits,
-                               hipStream_t st) {
+                               hipStream_t st, LineRec64T* rec64t) {
   dim3 grid((unsigned)((L.n + 255) / 256), (unsigned)nlay);
   if (amax) {
     // the scale needs the largest strength of the call: one layer at (T_one, P_one)
-    if (T_lay || nlay != 1 || rec64) return hipErrorInvalidValue;
+    if (T_lay || nlay != 1 || rec64 || rec64t) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_amp_max, dim3((unsigned)((L.n + 255) / 256)), dim3(256), 0, st, L, T_one, P_one,
                        const_cast<unsigned long long*>(amax));
   }
   hipLaunchKernelGGL(k_line_records, grid, dim3(256), 0, st, L, T_lay, P_lay, col_lay, T_one, P_one,
-                     amp_scale, layer0, amax, oscale, rec, rect, rec64, rec64 ? nullptr : g2max_bits);
+                     amp_scale, layer0, amax, oscale, rec, rect, rec64, (rec64 || rec64t) ? nullptr : g2max_bits,
+                     rec64t);
   return hipGetLastError();
 }
 
@@ -870,7 +996,18 @@ hipError_t launch_zero_words(void* p, size_t bytes, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_voigt(const VoigtArgs& A, bool fp64, bool tangent, hipStream_t st) {
+hipError_t launch_voigt(const VoigtArgs& A, bool fp64, bool tangent, hipStream_t st, bool tiled) {
+  if (fp64 && tiled) {
+    if (tangent) return hipErrorInvalidValue;
+    constexpr int G = kVoigtG;
+    dim3 grid((unsigned)((A.ng + 256 * G - 1) / (256 * G)), (unsigned)A.nlay, (unsigned)A.ksplit);
+    hipLaunchKernelGGL((k_voigt_f64t<G>), grid, dim3(256), 0, st, A);
+    if (A.ksplit > 1) {
+      dim3 g2((unsigned)((A.ng + 255) / 256), (unsigned)A.nlay);
+      hipLaunchKernelGGL(k_voigt_combine64, g2, dim3(256), 0, st, A);
+    }
+    return hipGetLastError();
+  }
   if (fp64) {
     dim3 grid((unsigned)((A.ng + 255) / 256), (unsigned)A.nlay, (unsigned)A.ksplit);
     hipLaunchKernelGGL(k_voigt_f64, grid, dim3(256), 0, st, A);

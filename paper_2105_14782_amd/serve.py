@@ -90,7 +90,7 @@ class Server:
         """Queue one spectrum; arrival_s (time.monotonic() seconds, 0: now) is
         the instant latency and queue time are measured from."""
         p = _prec(precision)
-        dt = torch.float64 if p == L.EXO_FP64 else torch.float32
+        dt = torch.float32 if p == L.EXO_FP32_KAHAN else torch.float64
         n = int(response.out_len) if response is not None else (int(atmos.grid_len) or self.ctx.n_nu)
         out = torch.empty(n, dtype=dt, device=f"cuda:{self.ctx.device}")
         a, keep = atmos.to_c()

@@ -108,7 +108,7 @@ def _ctx_with(exo, wl, grid=None):
     return c
 
 
-@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+@pytest.mark.parametrize("prec", ["fp32", "fp64", "fp64_tiled"])
 def test_cross_section_config1(exo, prec):
     _say(f"cross_section config1 {prec}")
     wl = synth.make_config(1, "full")
@@ -132,7 +132,7 @@ def test_cross_section_ragged_shapes(exo, n_lines, n_nu):
     c.set_grid(nu)
     for T, P in [(800.0, 0.01), (1500.0, 3.0)]:
         ref = O.cross_section(ll, T, P, nu)
-        for prec, tol in [("fp32", RTOL_FLUX), ("fp64", 1e-5)]:
+        for prec, tol in [("fp32", RTOL_FLUX), ("fp64", 1e-5), ("fp64_tiled", 1e-5)]:
             got = c.cross_section(3, T, P, prec).cpu().double().numpy()
             assert maxrel(got, ref) < tol, (prec, T, P)
 
@@ -152,6 +152,8 @@ def test_cross_section_degenerate_widths(exo):
         ref = O.cross_section(ll, T, P, nu)
         got = c.cross_section(0, T, P, "fp32").cpu().double().numpy()
         assert maxrel(got, ref) < RTOL_FLUX, (T, P)
+        got = c.cross_section(0, T, P, "fp64_tiled").cpu().numpy()
+        assert maxrel(got, ref) < 1e-5, ("fp64_tiled", T, P)
 
 
 def test_cross_section_is_deterministic(exo):
@@ -279,7 +281,7 @@ def _atmos(exo, wl, theta=None, **kw):
     return exo.Atmos.from_workload(wl.atmos, list(range(len(wl.lines))), theta, **kw)
 
 
-@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+@pytest.mark.parametrize("prec", ["fp32", "fp64", "fp64_tiled"])
 def test_emission_small_with_response(exo, prec):
     _say(f"emission small {prec}")
     wl = synth.make_config(2, "small")
@@ -321,7 +323,7 @@ def test_emission_full_config2_sampled(exo):
     idx = np.sort(rng.choice(np.arange(1, wl.nu.size - 1), 62, replace=False))
     idx = np.concatenate([[0], idx, [wl.nu.size - 1]])
     ref = O.emission_F0(wl, wl.theta_star, nu_idx=idx)
-    for prec, tol in [("fp32", RTOL_FLUX), ("fp64", 1e-5)]:
+    for prec, tol in [("fp32", RTOL_FLUX), ("fp64", 1e-5), ("fp64_tiled", 1e-5)]:
         F0 = c.emission_flux(_atmos(exo, wl), None, prec).cpu().double().numpy()
         err = maxrel(F0[idx], ref)
         _say(f"  {prec} max rel err {err:.3e} over {idx.size} points")
