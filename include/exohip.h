@@ -241,8 +241,11 @@ int exo_emission_flux(exo_ctx* ctx, const exo_atmos* atm, const exo_response* re
 
 /* Vector-Jacobian product of the emission spectrum (the paper provides
  * forward-mode JVPs, App. D; this is the reverse-mode counterpart).
+ *   precision EXO_FP32_KAHAN, or EXO_FP64 / EXO_FP64_TILED: both run the
+ *             tiled FP64 form, which has a tangent mode (the plain FP64 form
+ *             has none), for the forward pass and the gradient
  *   cot_dev   device [out_len] (or model grid length when resp == NULL),
- *             dL/dF, float (EXO_FP32_KAHAN) or double (EXO_FP64)
+ *             dL/dF, float (EXO_FP32_KAHAN) or double (FP64)
  *   grad_host host [2 + n_species + 2] doubles, written on return:
  *             {dL/dT0, dL/dalpha, dL/dlog10X_1..S, dL/dRV, dL/dvsini}
  *             (RV, vsini entries are 0 when resp == NULL; T0, alpha
@@ -250,7 +253,8 @@ int exo_emission_flux(exo_ctx* ctx, const exo_atmos* atm, const exo_response* re
  *             dL_dT_layers)
  *   dL_dT_layers host [n_layers] or NULL: dL/dT_n of every layer
  *   flux_dev  device or NULL: if given, the forward spectrum F is written
- *             there as by exo_emission_flux (one pass gives F and gradient)
+ *             there as by exo_emission_flux (one pass gives F and gradient;
+ *             float or double as cot_dev)
  * The forward model is re-evaluated internally.  Blocks until the gradient
  * is on the host.  Errors as exo_emission_flux. */
 int exo_flux_vjp(exo_ctx* ctx, const exo_atmos* atm, const exo_response* resp,

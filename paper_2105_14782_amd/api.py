@@ -222,18 +222,21 @@ class Context:
         return out
 
     def flux_vjp(self, atmos: Atmos, response: Optional[Response], cot: torch.Tensor,
-                 want_layers: bool = False, want_flux: bool = False, stream=None):
-        """(grad[2 + M + 2], dL/dT_n or None, F or None) for cotangent dL/dF."""
+                 want_layers: bool = False, want_flux: bool = False, stream=None, precision="fp32"):
+        """(grad[2 + M + 2], dL/dT_n or None, F or None) for cotangent dL/dF
+        (float32 for "fp32", float64 for the FP64 forms)."""
+        p = _prec(precision)
+        dt = torch.float32 if p == L.EXO_FP32_KAHAN else torch.float64
         n = self._out_len(atmos, response)
-        assert cot.dtype == torch.float32 and cot.is_contiguous() and cot.numel() == n
+        assert cot.dtype == dt and cot.is_contiguous() and cot.numel() == n
         m = len(atmos.species)
         grad = np.zeros(4 + m)
         layers = np.zeros(len(atmos.P_bar)) if want_layers else None
-        flux = torch.empty(n, dtype=torch.float32, device=cot.device) if want_flux else None
+        flux = torch.empty(n, dtype=dt, device=cot.device) if want_flux else None
         a, keep = atmos.to_c()
         r = response.to_c() if response is not None else None
         L.check(self._lib.exo_flux_vjp(
-            self._h, ctypes.byref(a), ctypes.byref(r) if r is not None else None, L.EXO_FP32_KAHAN,
+            self._h, ctypes.byref(a), ctypes.byref(r) if r is not None else None, p,
             ctypes.c_void_p(cot.data_ptr()), L.dptr(grad), L.dptr(layers),
             ctypes.c_void_p(flux.data_ptr()) if flux is not None else None, _stream(stream)))
         return grad, layers, flux

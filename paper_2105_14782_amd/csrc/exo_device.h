@@ -67,8 +67,8 @@ struct LineRec64 {
   double A, beta, gam, erfcxa;
 };
 
-// Tiled FP64 form: the fields of LineRec in double precision, with the full
-// wing polynomial (no tier truncation).
+// Tiled FP64 form: the fields of LineRec (and LineRecT) in double precision,
+// with the full wing polynomial (no tier truncation).
 struct LineRec64T {
   double e[7];    // wing polynomial, amplitude included
   double gam2;    // gamma^2
@@ -78,6 +78,55 @@ struct LineRec64T {
   double acore;   // amplitude / (sqrt(2 pi) beta)
 };
 static_assert(sizeof(LineRec64T) == 96, "LineRec64T layout");
+
+struct LineRec64TT {
+  double t[8];    // wing: d f/dT = r * sum_k t_k r^k
+  double kA;      // d ln(acore)/dT
+  double kw;      // d ln(winv)/dT
+  double da;      // da/dT
+  double pad;
+};
+static_assert(sizeof(LineRec64TT) == 96, "LineRec64TT layout");
+
+// Temperature tangent of the record (FP64): the wing polynomial's T-derivative
+// coefficients tk[0..7] and the core-branch factors d ln(acore)/dT,
+// d ln(winv)/dT, da/dT, from the amplitude, widths and their T-derivatives.
+__device__ inline void record_tangent(double A, double beta, double gam, double dlnA, double dbeta,
+                                      double dgam, double (&tk)[8], double* kA, double* kw, double* da) {
+  const double b = beta * beta, g = gam * gam;
+  const double E0 = A * gam / kPi;
+  double c[7];
+  c[0] = 1.0;
+  c[1] = 3.0 * b;
+  c[2] = 15.0 * b * b - 4.0 * b * g;
+  c[3] = 105.0 * b * b * b - 60.0 * b * b * g;
+  c[4] = 48.0 * b * b * g * g - 840.0 * b * b * b * g;
+  c[5] = 1680.0 * b * b * b * g * g;
+  c[6] = -960.0 * b * b * b * g * g * g;
+  // db/dT, dg/dT
+  const double db = 2.0 * beta * dbeta, dg = 2.0 * gam * dgam;
+  // dc_k/dT = dc_k/db * db + dc_k/dg * dg
+  double dc[7];
+  dc[0] = 0.0;
+  dc[1] = 3.0 * db;
+  dc[2] = (30.0 * b - 4.0 * g) * db - 4.0 * b * dg;
+  dc[3] = (315.0 * b * b - 120.0 * b * g) * db - 60.0 * b * b * dg;
+  dc[4] = (96.0 * b * g * g - 2520.0 * b * b * g) * db + (96.0 * b * b * g - 840.0 * b * b * b) * dg;
+  dc[5] = 5040.0 * b * b * g * g * db + 3360.0 * b * b * b * g * dg;
+  dc[6] = -2880.0 * b * b * g * g * g * db - 2880.0 * b * b * b * g * g * dg;
+  // E0 = A gam / pi  ->  dE0 = E0 (dlnA) + A dgam / pi
+  const double dE0 = E0 * dlnA + A * dgam / kPi;
+  // f = sum_k e_k r^{k+1}, r = 1/(s + g):  df/dT = sum_k e'_k r^{k+1} - g' sum_k (k+1) e_k r^{k+2}
+  for (int k = 0; k < 8; ++k) tk[k] = 0.0;
+  for (int k = 0; k < 7; ++k) {
+    tk[k] += dE0 * c[k] + E0 * dc[k];
+    tk[k + 1] += -dg * (double)(k + 1) * E0 * c[k];
+  }
+  const double winv = 1.0 / (kSqrt2 * beta);
+  *kA = dlnA - dbeta / beta;
+  *kw = -dbeta / beta;
+  *da = winv * (dgam - gam * dbeta / beta);
+}
 
 // ---------------------------------------------------------------------------
 // Record construction (FP64) from the line state at one layer.
@@ -110,39 +159,29 @@ __device__ inline void make_line_record(double A, double beta, double gam, doubl
   for (int k = 0; k < 4; ++k) r.pad[k] = 0.f;
   *R = r;
   if (RT) {
-    // db/dT, dg/dT
-    const double db = 2.0 * beta * dbeta, dg = 2.0 * gam * dgam;
-    // dc_k/dT = dc_k/db * db + dc_k/dg * dg
-    double dc[7];
-    dc[0] = 0.0;
-    dc[1] = 3.0 * db;
-    dc[2] = (30.0 * b - 4.0 * g) * db - 4.0 * b * dg;
-    dc[3] = (315.0 * b * b - 120.0 * b * g) * db - 60.0 * b * b * dg;
-    dc[4] = (96.0 * b * g * g - 2520.0 * b * b * g) * db + (96.0 * b * b * g - 840.0 * b * b * b) * dg;
-    dc[5] = 5040.0 * b * b * g * g * db + 3360.0 * b * b * b * g * dg;
-    dc[6] = -2880.0 * b * b * g * g * g * db - 2880.0 * b * b * b * g * g * dg;
-    // E0 = A gam / pi  ->  dE0 = E0 (dlnA) + A dgam / pi
-    const double dE0 = E0 * dlnA + A * dgam / kPi;
-    // f = sum_k e_k r^{k+1}, r = 1/(s + g):  df/dT = sum_k e'_k r^{k+1} - g' sum_k (k+1) e_k r^{k+2}
     LineRecT t;
-    double tk[8];
-    for (int k = 0; k < 8; ++k) tk[k] = 0.0;
-    for (int k = 0; k < 7; ++k) {
-      tk[k] += dE0 * c[k] + E0 * dc[k];
-      tk[k + 1] += -dg * (double)(k + 1) * E0 * c[k];
-    }
+    double tk[8], kA, kw, da;
+    record_tangent(A, beta, gam, dlnA, dbeta, dgam, tk, &kA, &kw, &da);
 #pragma unroll
     for (int k = 0; k < 8; ++k) t.t[k] = (float)tk[k];
-    t.kA = (float)(dlnA - dbeta / beta);
-    t.kw = (float)(-dbeta / beta);
-    t.da = (float)(winv * (dgam - gam * dbeta / beta));
+    t.kA = (float)kA;
+    t.kw = (float)kw;
+    t.da = (float)da;
     for (int k = 0; k < 5; ++k) t.pad[k] = 0.f;
     *RT = t;
   }
 }
 
-// The same record in FP64 for the tiled FP64 form (forward only).
-__device__ inline void make_line_record64t(double A, double beta, double gam, LineRec64T* R) {
+// The same records in FP64 for the tiled FP64 form; RT (tangent mode) may be
+// nullptr.
+__device__ inline void make_line_record64t(double A, double beta, double gam, double dlnA, double dbeta,
+                                           double dgam, LineRec64T* R, LineRec64TT* RT) {
+  if (RT) {
+    LineRec64TT t;
+    record_tangent(A, beta, gam, dlnA, dbeta, dgam, t.t, &t.kA, &t.kw, &t.da);
+    t.pad = 0.0;
+    *RT = t;
+  }
   const double b = beta * beta, g = gam * gam;
   const double E0 = A * gam / kPi;
   LineRec64T r;

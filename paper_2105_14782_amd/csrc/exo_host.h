@@ -133,7 +133,7 @@ int voigt_launch_profiled(exo_ctx* c, const VoigtArgs& A, bool fp64, bool tan, h
 // tiled64 (with fp64): the tiled FP64 form instead of the plain one.
 int species_opacity(exo_ctx* c, Workspace& ws, const Species& sp, const double* d_T,
                     const double* d_P, const double* d_col, int nlay, double amp_scale, bool fp64,
-                    bool tangent, const double* d_nu, int64_t ng, void* out, float* out_t,
+                    bool tangent, const double* d_nu, int64_t ng, void* out, void* out_t,
                     hipStream_t st, double T_one = 0.0, double P_one = 0.0, bool adaptive_scale = false,
                     bool tiled64 = false);
 // MODIT cross-sections (d_col == NULL) or optical depths col_n sigma clamped

@@ -32,6 +32,7 @@ struct VoigtArgs {
   const LineRecT* rect;
   const LineRec64* rec64;
   const LineRec64T* rec64t;  // tiled FP64 form
+  const LineRec64TT* rect64t;  // tiled FP64 form, tangent mode
   int64_t lines_per_split;
   int ksplit;
   int nlay;
@@ -41,10 +42,12 @@ struct VoigtArgs {
   float* out;
   float* out_t;
   double* out64;
+  double* out_t64;   // tiled FP64 tangent output (or nullptr)
   int64_t ld_out;
   float2* part;
   float2* part_t;
   double* part64;
+  double* part_t64;
   const float* far_reach2;         // [nlay] squared far-tier reach of each layer (cm^-2)
   const int* far_t3;               // [nlay] tangent mode: 1 if far pairs keep the tangent's r^4 term
   const float* far_outer2;         // [nlay] squared outer reach (>= far_reach2; FLT_MAX: none)
@@ -165,18 +168,20 @@ struct RespDev {
 // receives the largest S(T) of the call; the records then carry the adaptive
 // power-of-two amplitude scale it implies and write its inverse to *oscale.
 // rec64t (tiled FP64 form, else nullptr): FP64 records with the full wing
-// polynomial; rec, rect, rec64 and g2max_bits are then unused.
+// polynomial, and their tangents in rect64t (tangent mode, else nullptr);
+// rec, rect, rec64 and g2max_bits are then unused.
 hipError_t launch_line_records(const LinesDev& L, const double* T_lay, const double* P_lay,
                                const double* col_lay, double T_one, double P_one, double amp_scale,
                                const unsigned long long* amax, float* oscale, int layer0, int nlay,
                                LineRec* rec, LineRecT* rect, LineRec64* rec64, unsigned int* g2max_bits,
-                               hipStream_t st, LineRec64T* rec64t = nullptr);
+                               hipStream_t st, LineRec64T* rec64t = nullptr, LineRec64TT* rect64t = nullptr);
 // Squared far-tier and outer reaches of each layer from its records and
 // g2max_bits, which it resets to zero for the next chunk (and *amax, if given).
 hipError_t launch_far_reach(const LineRec* rec, int64_t n_lines, int nlay, bool tangent,
                             unsigned int* g2max_bits, float* reach2, int* t3, float* outer2,
                             unsigned long long* amax, hipStream_t st);
-// fp64 && tiled: the tiled FP64 form (A.rec64t), forward only.
+// fp64 && tiled: the tiled FP64 form (A.rec64t; tangent mode with A.rect64t,
+// A.out_t64 and A.part_t64).
 hipError_t launch_voigt(const VoigtArgs& A, bool fp64, bool tangent, hipStream_t st, bool tiled = false);
 // Zeroes bytes (a multiple of 4) at p with a kernel (no memset node).
 hipError_t launch_zero_words(void* p, size_t bytes, hipStream_t st);

@@ -490,13 +490,16 @@ static void split_plan(int64_t ng, int nl, int64_t n_lines, bool one_point, int6
 OpacityPlan exo::plan_opacity(int64_t n_lines, int nlay, int64_t ng, bool fp64, bool tangent, bool tiled64) {
   OpacityPlan P{};
   tiled64 = tiled64 && fp64;
+  tangent = tangent && (!fp64 || tiled64);   // the plain FP64 form has no tangent mode
   const size_t rec64_size = tiled64 ? sizeof(LineRec64T) : sizeof(LineRec64);
-  const size_t per_layer = (size_t)n_lines * (fp64 ? rec64_size
-                                                   : sizeof(LineRec) + (tangent ? sizeof(LineRecT) : 0));
+  const size_t per_layer =
+      (size_t)n_lines * (fp64 ? rec64_size + (tangent ? sizeof(LineRec64TT) : 0)
+                              : sizeof(LineRec) + (tangent ? sizeof(LineRecT) : 0));
   P.nlc = (int)std::max<size_t>(1, std::min<size_t>((size_t)nlay, kRecBudget / per_layer));
   if (fp64) {
-    // the tiled FP64 records share the plain form's buffer
+    // the tiled FP64 records share the plain form's buffers
     P.rec64 = (size_t)P.nlc * n_lines * rec64_size;
+    if (tangent) P.rect = (size_t)P.nlc * n_lines * sizeof(LineRec64TT);
   } else {
     P.rec = (size_t)P.nlc * n_lines * sizeof(LineRec);
     P.tier = kTierBytes;
@@ -511,7 +514,7 @@ OpacityPlan exo::plan_opacity(int64_t n_lines, int nlay, int64_t ng, bool fp64, 
     if (ks > 1 || !fp64) {
       const size_t pb = (size_t)ks * nl * ng * (fp64 ? sizeof(double) : sizeof(float2));
       P.part = std::max(P.part, pb);
-      if (!fp64 && tangent) P.part_t = std::max(P.part_t, pb);
+      if (tangent) P.part_t = std::max(P.part_t, pb);
     }
   }
   return P;
@@ -546,11 +549,11 @@ int exo::reserve_opacity(Workspace& ws, const OpacityPlan& P) {
 int exo::species_opacity(exo_ctx* c, Workspace& ws, const Species& sp, const double* d_T,
                          const double* d_P, const double* d_col, int nlay, double amp_scale,
                          bool fp64, bool tangent, const double* d_nu, int64_t ng, void* out,
-                         float* out_t, hipStream_t st, double T_one, double P_one, bool adaptive_scale,
+                         void* out_t, hipStream_t st, double T_one, double P_one, bool adaptive_scale,
                          bool tiled64) {
   const LinesDev L = lines_dev(sp);
   tiled64 = tiled64 && fp64;
-  if (tiled64 && tangent) return set_err(EXO_EINVAL, "the tiled FP64 form has no tangents");
+  if (fp64 && !tiled64 && tangent) return set_err(EXO_EINVAL, "the plain FP64 form has no tangent mode");
   const OpacityPlan P = plan_opacity(sp.n, nlay, ng, fp64, tangent, tiled64);
   int rc;
   if ((rc = reserve_opacity(ws, P))) return rc;
@@ -577,7 +580,8 @@ int exo::species_opacity(exo_ctx* c, Workspace& ws, const Species& sp, const dou
                                 fp64 ? nullptr : (LineRec*)ws.rec.p,
                                 (!fp64 && tangent) ? (LineRecT*)ws.rect.p : nullptr,
                                 (fp64 && !tiled64) ? (LineRec64*)ws.rec64.p : nullptr, g2bits, st,
-                                tiled64 ? (LineRec64T*)ws.rec64.p : nullptr));
+                                tiled64 ? (LineRec64T*)ws.rec64.p : nullptr,
+                                (tiled64 && tangent) ? (LineRec64TT*)ws.rect.p : nullptr));
     if (!fp64)
       HIP_TRY(launch_far_reach((const LineRec*)ws.rec.p, sp.n, nl, tangent, g2bits, reach2, t3, outer2, amax, st));
     VoigtArgs A{};
@@ -589,6 +593,7 @@ int exo::species_opacity(exo_ctx* c, Workspace& ws, const Species& sp, const dou
     A.rect = (const LineRecT*)ws.rect.p;
     A.rec64 = tiled64 ? nullptr : (const LineRec64*)ws.rec64.p;
     A.rec64t = tiled64 ? (const LineRec64T*)ws.rec64.p : nullptr;
+    A.rect64t = (tiled64 && tangent) ? (const LineRec64TT*)ws.rect.p : nullptr;
     A.far_reach2 = reach2;
     A.far_t3 = t3;
     A.far_outer2 = outer2;
@@ -597,10 +602,12 @@ int exo::species_opacity(exo_ctx* c, Workspace& ws, const Species& sp, const dou
     A.out_scale_dev = oscale;
     A.out_scale64 = 1.0 / amp_scale;
     A.ld_out = ng;
-    if (fp64) A.out64 = (double*)out + (int64_t)l0 * ng;
-    else {
+    if (fp64) {
+      A.out64 = (double*)out + (int64_t)l0 * ng;
+      A.out_t64 = tangent ? (double*)out_t + (int64_t)l0 * ng : nullptr;
+    } else {
       A.out = (float*)out + (int64_t)l0 * ng;
-      A.out_t = tangent ? out_t + (int64_t)l0 * ng : nullptr;
+      A.out_t = tangent ? (float*)out_t + (int64_t)l0 * ng : nullptr;
     }
     int64_t ks, lps;
     split_plan(ng, nl, sp.n, fp64 && !tiled64, &ks, &lps);
@@ -610,6 +617,7 @@ int exo::species_opacity(exo_ctx* c, Workspace& ws, const Species& sp, const dou
       A.part = (float2*)ws.part.p;
       A.part_t = (float2*)ws.part_t.p;
       A.part64 = (double*)ws.part.p;
+      A.part_t64 = (double*)ws.part_t.p;
     }
     if ((rc = voigt_launch_profiled(ws.no_alloc ? nullptr : c, A, fp64, tangent, st, tiled64))) return rc;
   }
@@ -1024,7 +1032,7 @@ int exo::forward_core(exo_ctx* c, Workspace& ws, const exo_atmos* a, int64_t gb,
 
   const size_t esz = fp64 ? sizeof(double) : sizeof(float);
   if ((rc = ws.reserve(ws.tau, (size_t)M * NL * gl * esz))) return rc;
-  if (tangent && (rc = ws.reserve(ws.taut, (size_t)M * NL * gl * sizeof(float)))) return rc;
+  if (tangent && (rc = ws.reserve(ws.taut, (size_t)M * NL * gl * esz))) return rc;
   const bool modit = a->opacity == EXO_OPACITY_MODIT;
   if (modit && tangent) return set_err(EXO_EINVAL, "the MODIT opacity has no tangents");
   // every species' buffers fit in the largest plan, reserved once up front
@@ -1033,7 +1041,7 @@ int exo::forward_core(exo_ctx* c, Workspace& ws, const exo_atmos* a, int64_t gb,
   for (int m = 0; m < M; ++m) {
     const Species& sp = c->sp[a->species[m]];
     char* out = (char*)ws.tau.p + (size_t)m * NL * gl * esz;
-    float* out_t = tangent ? (float*)ws.taut.p + (size_t)m * NL * gl : nullptr;
+    void* out_t = tangent ? (char*)ws.taut.p + (size_t)m * NL * gl * esz : nullptr;
     if (modit)
       rc = modit_opacity(c, ws, sp, A.T, A.P, A.col + (size_t)m * NL, NL, a->modit_dln_gamma, fp64, d_nu,
                          c->h_nu[gb], c->h_nu[gb + gl - 1], gl, out, st);
@@ -1146,27 +1154,30 @@ int exo::vjp_impl(exo_ctx* c, Workspace& ws, const exo_atmos* a, const exo_respo
   int64_t gb, gl;
   int rc;
   if ((rc = validate_atmos(c, a, &gb, &gl))) return rc;
-  if (precision != EXO_FP32_KAHAN)
-    return set_err(EXO_EINVAL, "the gradient is provided for EXO_FP32_KAHAN");
+  if (precision != EXO_FP32_KAHAN && precision != EXO_FP64 && precision != EXO_FP64_TILED)
+    return set_err(EXO_EINVAL, "bad precision");
   if (a->opacity != EXO_OPACITY_LPF) return set_err(EXO_EINVAL, "the gradient is provided for the direct opacity");
   const bool fused = data != nullptr;
+  // FP64 gradients run the tiled FP64 form (the plain form has no tangent mode)
+  const bool fp64 = precision != EXO_FP32_KAHAN;
+  if (fused && fp64) return set_err(EXO_EINVAL, "the fused likelihood gradient is provided for EXO_FP32_KAHAN");
   if (fused ? (!sigma || !loss || !grad) : (!cot || !grad))
     return set_err(EXO_EINVAL, fused ? "sigma_dev / loss_host / grad_host is NULL" : "cot_dev / grad_host is NULL");
   RespDev R{};
   if (r && (rc = prepare_response(c, r, gl, &R))) return rc;
   const int NL = a->n_layers, M = a->n_species;
-  if ((rc = forward_core(c, ws, a, gb, gl, false, true, st))) return rc;
+  if ((rc = forward_core(c, ws, a, gb, gl, fp64, true, st, fp64))) return rc;
   const double* F0 = (const double*)ws.F0.p;
   const int64_t nbg = (gl + 255) / 256;
   if ((rc = ws.reserve(ws.F0bar, (size_t)gl * sizeof(double)))) return rc;
   double* F0bar = (double*)ws.F0bar.p;
   // Gaussian likelihood: the spectrum (into flux_dev or scratch), then its cotangent
   const int64_t nout = r ? R.ol : gl, nbL = (nout + 255) / 256;
-  float* Fout = (float*)flux;
+  void* Fout = flux;
   if (fused) {
     if (!Fout) {
       if ((rc = ws.reserve(ws.lossF, (size_t)nout * sizeof(float)))) return rc;
-      Fout = (float*)ws.lossF.p;
+      Fout = ws.lossF.p;
     }
     if ((rc = ws.reserve(ws.lossC, (size_t)nout * sizeof(float)))) return rc;
     if ((rc = ws.reserve(ws.lossP, (size_t)nbL * sizeof(double)))) return rc;
@@ -1174,18 +1185,18 @@ int exo::vjp_impl(exo_ctx* c, Workspace& ws, const exo_atmos* a, const exo_respo
   }
   int64_t nbR = 0;
   if (r) {
-    if ((rc = apply_response(ws, R, F0, Fout, false, st))) return rc;
-    if (fused) HIP_TRY(launch_gauss_cot(Fout, data, sigma, nout, (float*)ws.lossC.p, (double*)ws.lossP.p, st));
+    if ((rc = apply_response(ws, R, F0, Fout, fp64, st))) return rc;
+    if (fused) HIP_TRY(launch_gauss_cot((const float*)Fout, data, sigma, nout, (float*)ws.lossC.p, (double*)ws.lossP.p, st));
     const int64_t nmid = R.ol + 2 * R.K;
     nbR = (nmid + 255) / 256;
     if ((rc = ws.reserve(ws.midbar, (size_t)nmid * sizeof(double)))) return rc;
     if ((rc = ws.reserve(ws.partR, (size_t)2 * nbR * sizeof(double)))) return rc;
-    HIP_TRY(launch_response_vjp(R, F0, cot, false, (double*)ws.midbar.p, F0bar, gl,
+    HIP_TRY(launch_response_vjp(R, F0, cot, fp64, (double*)ws.midbar.p, F0bar, gl,
                                 (double*)ws.partR.p, nbR, st));
   } else {
-    if (Fout) HIP_TRY(launch_cast_copy(F0, Fout, false, gl, st));
-    if (fused) HIP_TRY(launch_gauss_cot(Fout, data, sigma, nout, (float*)ws.lossC.p, (double*)ws.lossP.p, st));
-    HIP_TRY(launch_to_double(cot, false, F0bar, gl, st));
+    if (Fout) HIP_TRY(launch_cast_copy(F0, Fout, fp64, gl, st));
+    if (fused) HIP_TRY(launch_gauss_cot((const float*)Fout, data, sigma, nout, (float*)ws.lossC.p, (double*)ws.lossP.p, st));
+    HIP_TRY(launch_to_double(cot, fp64, F0bar, gl, st));
   }
   if ((rc = ws.reserve(ws.Fup, (size_t)NL * gl * sizeof(double)))) return rc;
   if ((rc = ws.reserve(ws.taubar, (size_t)NL * gl * sizeof(double)))) return rc;
@@ -1197,8 +1208,8 @@ int exo::vjp_impl(exo_ctx* c, Workspace& ws, const exo_atmos* a, const exo_respo
   Rt.Fup = (double*)ws.Fup.p;
   Rt.taubar = (double*)ws.taubar.p;
   Rt.partT = (double*)ws.partT.p;
-  HIP_TRY(launch_rt_adjoint(Rt, false, nbg, st));
-  HIP_TRY(launch_grad_x(Rt.taubar, ws.tau.p, false, M, NL, gl, (double*)ws.partX.p, nbg, st));
+  HIP_TRY(launch_rt_adjoint(Rt, fp64, nbg, st));
+  HIP_TRY(launch_grad_x(Rt.taubar, ws.tau.p, fp64, M, NL, gl, (double*)ws.partX.p, nbg, st));
   const double* lay = (const double*)ws.layer.p;
   HIP_TRY(launch_grad_final(Rt.partT, nbg, (const double*)ws.partX.p, nbg, (const double*)ws.partR.p,
                             nbR, lay, lay + 2 * NL, NL, M, a->T0_K, a->T_layers ? 0 : 1,

@@ -4,6 +4,7 @@
 #include "exo_lines.h"
 
 #include <mutex>
+#include <type_traits>
 #include <vector>
 
 namespace exo {
@@ -55,7 +56,8 @@ __global__ __launch_bounds__(256) void k_line_records(LinesDev L, const double* 
                                                       LineRecT* __restrict__ rect,
                                                       LineRec64* __restrict__ rec64,
                                                       unsigned int* __restrict__ g2max_bits,
-                                                      LineRec64T* __restrict__ rec64t) {
+                                                      LineRec64T* __restrict__ rec64t,
+                                                      LineRec64TT* __restrict__ rect64t) {
   const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool in = l < L.n;
   const int y = blockIdx.y;
@@ -70,7 +72,8 @@ __global__ __launch_bounds__(256) void k_line_records(LinesDev L, const double* 
   if (rec64t) {
     if (!in) return;
     const LineState s = line_state(L, l, T, P);
-    make_line_record64t(s.S * col * amp_scale, s.beta, s.gam, rec64t + o);
+    make_line_record64t(s.S * col * amp_scale, s.beta, s.gam, s.dlnS, s.dbeta, s.dgam, rec64t + o,
+                        rect64t ? rect64t + o : nullptr);
     return;
   }
   if (rec64) {
@@ -777,6 +780,10 @@ struct Stage64 {
   double a[kChunk64];
   double acore[kChunk64];
 };
+struct Stage64T : Stage64 {   // tangent mode
+  double t[8][kChunk64];
+  double kA[kChunk64], kw[kChunk64], da[kChunk64];
+};
 
 // 1/D in FP64: the hardware reciprocal and two Newton steps (each doubles
 // the number of correct bits of the ~23-bit estimate).
@@ -786,26 +793,38 @@ __device__ __forceinline__ double rcp64(double D) {
   return fma(inv, fma(-D, inv, 1.0), inv);
 }
 
-template <bool NEAR, int G>
+template <bool NEAR, bool TAN, int G, class ST>
 __device__ __forceinline__ void lines64(int sb, int se, const LineRec64T* __restrict__ R,
+                                        const LineRec64TT* __restrict__ RT,
                                         const double* __restrict__ nuc, const double (&nuj)[G],
-                                        Stage64* __restrict__ st, int lane, double (&acc)[G]) {
+                                        ST* __restrict__ st, int lane, double (&acc)[G], double (&tacc)[G]) {
   for (int l0 = sb; l0 < se; l0 += kChunk64) {
     const int l1 = min(l0 + kChunk64, se);
-    const int li = l0 + (lane & 31);
+    const int h = lane & 31;
+    const int li = l0 + h;
     if (li < l1) {
       const LineRec64T& q = R[li];
       if (lane < 32) {
 #pragma unroll
-        for (int k = 0; k < 7; ++k) st->e[k][lane] = q.e[k];
-        st->gam2[lane] = q.gam2;
+        for (int k = 0; k < 7; ++k) st->e[k][h] = q.e[k];
+        st->gam2[h] = q.gam2;
       } else {
-        const int h = lane & 31;
         st->nu[h] = nuc[li];
         st->thr[h] = q.thr;
         st->winv[h] = q.winv;
         st->a[h] = q.a;
         st->acore[h] = q.acore;
+      }
+      if constexpr (TAN) {
+        const LineRec64TT& qt = RT[li];
+        if (lane < 32) {
+#pragma unroll
+          for (int k = 0; k < 8; ++k) st->t[k][h] = qt.t[k];
+        } else {
+          st->kA[h] = qt.kA;
+          st->kw[h] = qt.kw;
+          st->da[h] = qt.da;
+        }
       }
     }
     wave_lds_sync();
@@ -821,18 +840,32 @@ __device__ __forceinline__ void lines64(int sb, int se, const LineRec64T* __rest
         const double d = nuj[g] - nul;
         const double D = fma(d, d, g2);
         if (NEAR && D < st->thr[i]) {
+          const double x = d * st->winv[i], a = st->a[i];
           double H, L;
-          core_w(d * st->winv[i], st->a[i], &H, &L);
+          core_w(x, a, &H, &L);
           acc[g] = fma(st->acore[i], H, acc[g]);
+          if constexpr (TAN) {
+            // custom derivatives of Sec. 2.1.1:
+            //   dH/dx = 2aL - 2xH,  dH/da = 2xL + 2aH - 2/sqrt(pi)
+            const double Hx = 2.0 * (a * L - x * H);
+            const double Ha = 2.0 * (x * L + a * H) - 1.1283791670955126;
+            tacc[g] = fma(st->acore[i], st->kA[i] * H + Hx * x * st->kw[i] + Ha * st->da[i], tacc[g]);
+          }
         } else {
           const double r = rcp64(D);
-          double h = fma(e[6], r, e[5]);
-          h = fma(h, r, e[4]);
-          h = fma(h, r, e[3]);
-          h = fma(h, r, e[2]);
-          h = fma(h, r, e[1]);
-          h = fma(h, r, e[0]);
-          acc[g] = fma(h, r, acc[g]);
+          double hv = fma(e[6], r, e[5]);
+          hv = fma(hv, r, e[4]);
+          hv = fma(hv, r, e[3]);
+          hv = fma(hv, r, e[2]);
+          hv = fma(hv, r, e[1]);
+          hv = fma(hv, r, e[0]);
+          acc[g] = fma(hv, r, acc[g]);
+          if constexpr (TAN) {
+            double ht = fma(st->t[7][i], r, st->t[6][i]);
+#pragma unroll
+            for (int k = 5; k >= 0; --k) ht = fma(ht, r, st->t[k][i]);
+            tacc[g] = fma(ht, r, tacc[g]);
+          }
         }
       }
     }
@@ -840,18 +873,20 @@ __device__ __forceinline__ void lines64(int sb, int se, const LineRec64T* __rest
   }
 }
 
-template <int G>
+template <bool TAN, int G>
 __global__ __launch_bounds__(256) void k_voigt_f64t(VoigtArgs A) {
+  using ST = typename std::conditional<TAN, Stage64T, Stage64>::type;
   const int y = blockIdx.y;
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  __shared__ Stage64 stage[4];
+  __shared__ ST stage[4];
   const int64_t tile0 = (int64_t)blockIdx.x * (256 * G);
   double nuj[G];
   load_points<G>(A, tile0, w, lane, nuj);
   const int lb = (int)blockIdx.z * (int)A.lines_per_split;
   const int le = min(lb + (int)A.lines_per_split, (int)A.n_lines);
   const LineRec64T* __restrict__ R = A.rec64t + (int64_t)y * A.n_lines;
+  const LineRec64TT* __restrict__ RT = TAN ? A.rect64t + (int64_t)y * A.n_lines : nullptr;
   // the last line (largest centre) has the largest Doppler width, hence the
   // largest core threshold of the layer
   const double reach = sqrt(R[A.n_lines - 1].thr) * (1.0 + 1e-12);
@@ -860,18 +895,25 @@ __global__ __launch_bounds__(256) void k_voigt_f64t(VoigtArgs A) {
   const double hi = A.nu[jw + G * 64 - 1 < jlast ? jw + G * 64 - 1 : jlast];
   const int i0 = __builtin_amdgcn_readfirstlane(search_sorted<false>(A.nu_c, lb, le, lo - reach));
   const int i1 = __builtin_amdgcn_readfirstlane(search_sorted<true>(A.nu_c, i0, le, hi + reach));
-  double acc[G];
+  double acc[G], tacc[G];
 #pragma unroll
-  for (int g = 0; g < G; ++g) acc[g] = 0.0;
-  lines64<false, G>(lb, i0, R, A.nu_c, nuj, &stage[w], lane, acc);
-  lines64<true, G>(i0, i1, R, A.nu_c, nuj, &stage[w], lane, acc);
-  lines64<false, G>(i1, le, R, A.nu_c, nuj, &stage[w], lane, acc);
+  for (int g = 0; g < G; ++g) acc[g] = tacc[g] = 0.0;
+  lines64<false, TAN, G>(lb, i0, R, RT, A.nu_c, nuj, &stage[w], lane, acc, tacc);
+  lines64<true, TAN, G>(i0, i1, R, RT, A.nu_c, nuj, &stage[w], lane, acc, tacc);
+  lines64<false, TAN, G>(i1, le, R, RT, A.nu_c, nuj, &stage[w], lane, acc, tacc);
 #pragma unroll
   for (int g = 0; g < G; ++g) {
     const int64_t j = tile0 + (int64_t)(w * G + g) * 64 + lane;
     if (j >= A.ng) continue;
-    if (A.ksplit == 1) A.out64[(int64_t)y * A.ld_out + j] = acc[g] * A.out_scale64;
-    else A.part64[((int64_t)blockIdx.z * A.nlay + y) * A.ng + j] = acc[g];
+    if (A.ksplit == 1) {
+      const int64_t o = (int64_t)y * A.ld_out + j;
+      A.out64[o] = acc[g] * A.out_scale64;
+      if (TAN) A.out_t64[o] = tacc[g] * A.out_scale64;
+    } else {
+      const int64_t p = ((int64_t)blockIdx.z * A.nlay + y) * A.ng + j;
+      A.part64[p] = acc[g];
+      if (TAN) A.part_t64[p] = tacc[g];
+    }
   }
 }
 
@@ -907,9 +949,14 @@ __global__ __launch_bounds__(256) void k_voigt_combine64(VoigtArgs A) {
   const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const int y = blockIdx.y;
   if (j >= A.ng) return;
-  double s = 0.0;
-  for (int z = 0; z < A.ksplit; ++z) s += A.part64[((int64_t)z * A.nlay + y) * A.ng + j];
+  double s = 0.0, t = 0.0;
+  for (int z = 0; z < A.ksplit; ++z) {
+    const int64_t p = ((int64_t)z * A.nlay + y) * A.ng + j;
+    s += A.part64[p];
+    if (A.out_t64) t += A.part_t64[p];
+  }
   A.out64[(int64_t)y * A.ld_out + j] = s * A.out_scale64;
+  if (A.out_t64) A.out_t64[(int64_t)y * A.ld_out + j] = t * A.out_scale64;
 }
 
 // ---------------------------------------------------------------------------
@@ -962,7 +1009,7 @@ hipError_t launch_line_records(const LinesDev& L, const double* T_lay, const dou
                                const double* col_lay, double T_one, double P_one, double amp_scale,
                                const unsigned long long* amax, float* oscale, int layer0, int nlay,
                                LineRec* rec, LineRecT* rect, LineRec64* rec64, unsigned int* g2max_bits,
-                               hipStream_t st, LineRec64T* rec64t) {
+                               hipStream_t st, LineRec64T* rec64t, LineRec64TT* rect64t) {
   dim3 grid((unsigned)((L.n + 255) / 256), (unsigned)nlay);
   if (amax) {
     // the scale needs the largest strength of the call: one layer at (T_one, P_one)
@@ -972,7 +1019,7 @@ hipError_t launch_line_records(const LinesDev& L, const double* T_lay, const dou
   }
   hipLaunchKernelGGL(k_line_records, grid, dim3(256), 0, st, L, T_lay, P_lay, col_lay, T_one, P_one,
                      amp_scale, layer0, amax, oscale, rec, rect, rec64, (rec64 || rec64t) ? nullptr : g2max_bits,
-                     rec64t);
+                     rec64t, rec64t ? rect64t : nullptr);
   return hipGetLastError();
 }
 
@@ -998,10 +1045,11 @@ hipError_t launch_zero_words(void* p, size_t bytes, hipStream_t st) {
 
 hipError_t launch_voigt(const VoigtArgs& A, bool fp64, bool tangent, hipStream_t st, bool tiled) {
   if (fp64 && tiled) {
-    if (tangent) return hipErrorInvalidValue;
+    if (tangent && (!A.rect64t || !A.out_t64 || (A.ksplit > 1 && !A.part_t64))) return hipErrorInvalidValue;
     constexpr int G = kVoigtG;
     dim3 grid((unsigned)((A.ng + 256 * G - 1) / (256 * G)), (unsigned)A.nlay, (unsigned)A.ksplit);
-    hipLaunchKernelGGL((k_voigt_f64t<G>), grid, dim3(256), 0, st, A);
+    if (tangent) hipLaunchKernelGGL((k_voigt_f64t<true, G>), grid, dim3(256), 0, st, A);
+    else hipLaunchKernelGGL((k_voigt_f64t<false, G>), grid, dim3(256), 0, st, A);
     if (A.ksplit > 1) {
       dim3 g2((unsigned)((A.ng + 255) / 256), (unsigned)A.nlay);
       hipLaunchKernelGGL(k_voigt_combine64, g2, dim3(256), 0, st, A);
