@@ -353,11 +353,12 @@ def summarize_stats(csv_path, out_path, modit=False):
             "# Kernel trace summary: config-2 emission bench (rocprofv3 --kernel-trace --stats)", "",
             "Command (repository root, one MI355X):", "", "```",
             "rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/prof_bench -o bench -- \\",
-            "    python3 bench.py --steps 3 --warmup 1 --no-cpu-baseline --fp64-reps 1 --serve-requests 0 --no-modit",
+            "    python3 bench.py --steps 3 --warmup 1 --no-cpu-baseline --fp64-reps 1 --serve-requests 0 --no-modit "
+            "--no-config3",
             "python3 bench.py --summarize-stats gpurun_out/prof_bench/bench_kernel_stats.csv", "```", "",
             "Workload: 2 species x 1e5 lines, 20,000-point log-uniform grid, 100 layers.",
             "The run does 1 warm-up + 3 timed flux_vjp steps (two tangent-mode Voigt sums each),",
-            "then 4 FP32 forward spectra and 2 plain-FP64 forward spectra (two Voigt sums each),",
+            "then 4 FP32 forward spectra, 2 plain-FP64 and 4 tiled-FP64 forward spectra (two Voigt sums each),",
             "then 4 loss_grad (leapfrog step) and 4 flux_jvp calls (tangent-mode Voigt sums as well),",
             "then the config-1 cross-section timing (1000 lines x 4000 points, one layer: 51 FP32 and",
             "51 plain-FP64 calls, hence the many short `k_voigt_f32<false, 4>` and `k_voigt_f64` launches).", "",
