@@ -5,6 +5,23 @@
 
 namespace exo {
 
+// Response convolutions: taps per LDS chunk and the input window they reach
+// from a block of 256 consecutive outputs.
+constexpr int kTapChunk = 512;
+constexpr int kWin = 256 + kTapChunk - 1;
+
+// win[m] = src[lo + m] for m < n, 0 where lo + m lies outside [vlo, vhi]
+// (every index a valid output reads lies inside).  Block-wide; the caller
+// synchronises.
+template <typename T>
+__device__ __forceinline__ void stage_window(double* __restrict__ win, const T* __restrict__ src, int64_t lo,
+                                             int n, int64_t vlo, int64_t vhi) {
+  for (int m = threadIdx.x; m < n; m += 256) {
+    const int64_t idx = lo + m;
+    win[m] = (idx >= vlo && idx <= vhi) ? (double)src[idx] : 0.0;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Per-layer quantities: T_n = T0 (P_n/1 bar)^alpha (Sec. 5.2), dP_n, the
 // column factor dP/(m_u g) X_m/M_m of Eq. dtau_line2, and the layer factor of
@@ -167,17 +184,30 @@ __global__ __launch_bounds__(256) void k_conv_rot_jvp(RespDev R, const double* _
                                                       const double* __restrict__ dF0, double d_rv,
                                                       double d_vs, double* __restrict__ dmid,
                                                       int64_t nmid) {
-  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (p >= nmid) return;
-  const int64_t i = R.ob - R.K + p;
-  const double* __restrict__ src = F0 + (i - R.dlo);
-  const double* __restrict__ dsrc = dF0 + (i - R.dlo);
+  __shared__ double tap[kTapChunk], tap2[kTapChunk];
+  __shared__ double win[kWin], dwin[kWin];
+  const int t = threadIdx.x;
+  const int64_t p0 = (int64_t)blockIdx.x * 256, p = p0 + t;
+  // F0 indices the valid outputs read: [ob - K - dlo - (nrot - 1), ob - K + nmid - 1 - dlo]
+  const int64_t vlo = R.ob - R.K - R.dlo - (R.nrot - 1), vhi = R.ob - R.K + nmid - 1 - R.dlo;
   double acc = 0.0;
-  for (int64_t k = 0; k < R.nrot; ++k) {
-    acc = fma(R.rot[k], dsrc[-k], acc);
-    acc = fma(fma(R.drot_rv[k], d_rv, R.drot_vs[k] * d_vs), src[-k], acc);
+  for (int64_t k0 = 0; k0 < R.nrot; k0 += kTapChunk) {
+    const int nk = (int)min((int64_t)kTapChunk, R.nrot - k0);
+    const int64_t lo = R.ob - R.K + p0 - R.dlo - (k0 + nk - 1);
+    __syncthreads();
+    for (int m = t; m < nk; m += 256) {
+      tap[m] = R.rot[k0 + m];
+      tap2[m] = fma(R.drot_rv[k0 + m], d_rv, R.drot_vs[k0 + m] * d_vs);
+    }
+    stage_window(win, F0, lo, 255 + nk, vlo, vhi);
+    stage_window(dwin, dF0, lo, 255 + nk, vlo, vhi);
+    __syncthreads();
+    for (int kk = 0; kk < nk; ++kk) {
+      acc = fma(tap[kk], dwin[t + nk - 1 - kk], acc);
+      acc = fma(tap2[kk], win[t + nk - 1 - kk], acc);
+    }
   }
-  dmid[p] = acc;
+  if (p < nmid) dmid[p] = acc;
 }
 
 // sum_{n,j} taubar_nj tau^m_nj per block (fixed order), for every species m.
@@ -305,57 +335,99 @@ __global__ __launch_bounds__(256) void k_taps(RespDev R) {
   for (int64_t k = threadIdx.x; k < 2 * R.K + 1; k += 256) R.ip[k] /= tots[0];
 }
 
+// The response convolutions below are 1-D sums over a few hundred taps on
+// the log-uniform grid.  A block of 256 consecutive outputs stages the taps,
+// in chunks of kTapChunk, and the input window those taps reach (255 + chunk
+// points) in LDS, so every tap and input point is read from memory once per
+// block; each thread then sums its output over the chunk from LDS, taps in
+// increasing order (the same order as a plain per-output loop).
+
 // mid[p] = G at model index i = ob - K + p:  G_i = sum_k rot_k F0_{i - dlo - k}
 __global__ __launch_bounds__(256) void k_conv_rot(RespDev R, const double* __restrict__ F0,
                                                   double* __restrict__ mid, int64_t nmid) {
-  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (p >= nmid) return;
-  const int64_t i = R.ob - R.K + p;
-  const double* __restrict__ src = F0 + (i - R.dlo);
+  __shared__ double tap[kTapChunk];
+  __shared__ double win[kWin];
+  const int t = threadIdx.x;
+  const int64_t p0 = (int64_t)blockIdx.x * 256, p = p0 + t;
+  const int64_t vlo = R.ob - R.K - R.dlo - (R.nrot - 1), vhi = R.ob - R.K + nmid - 1 - R.dlo;
   double acc = 0.0;
-  for (int64_t k = 0; k < R.nrot; ++k) acc = fma(R.rot[k], src[-k], acc);
-  mid[p] = acc;
+  for (int64_t k0 = 0; k0 < R.nrot; k0 += kTapChunk) {
+    const int nk = (int)min((int64_t)kTapChunk, R.nrot - k0);
+    const int64_t lo = R.ob - R.K + p0 - R.dlo - (k0 + nk - 1);   // F0 index of win[0]
+    __syncthreads();
+    for (int m = t; m < nk; m += 256) tap[m] = R.rot[k0 + m];
+    stage_window(win, F0, lo, 255 + nk, vlo, vhi);
+    __syncthreads();
+    for (int kk = 0; kk < nk; ++kk) acc = fma(tap[kk], win[t + nk - 1 - kk], acc);
+  }
+  if (p < nmid) mid[p] = acc;
 }
 
 // out[o] = F at model index ob + o = sum_{d=-K..K} ip_{d+K} G_{ob + o - d}
+//        = sum_k ip_k mid[o + 2K - k]
 template <typename TO>
 __global__ __launch_bounds__(256) void k_conv_ip(RespDev R, const double* __restrict__ mid,
                                                  TO* __restrict__ out) {
-  const int64_t o = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (o >= R.ol) return;
-  const double* __restrict__ src = mid + o + R.K;  // p = o + K - d
+  __shared__ double tap[kTapChunk];
+  __shared__ double win[kWin];
+  const int t = threadIdx.x;
+  const int64_t o0 = (int64_t)blockIdx.x * 256, o = o0 + t;
+  const int64_t ntap = 2 * R.K + 1, nmid = R.ol + 2 * R.K;
   double acc = 0.0;
-  for (int64_t k = 0; k < 2 * R.K + 1; ++k) acc = fma(R.ip[k], src[R.K - k], acc);
-  out[o] = (TO)acc;
+  for (int64_t k0 = 0; k0 < ntap; k0 += kTapChunk) {
+    const int nk = (int)min((int64_t)kTapChunk, ntap - k0);
+    const int64_t lo = o0 + 2 * R.K - (k0 + nk - 1);
+    __syncthreads();
+    for (int m = t; m < nk; m += 256) tap[m] = R.ip[k0 + m];
+    stage_window(win, mid, lo, 255 + nk, 0, nmid - 1);
+    __syncthreads();
+    for (int kk = 0; kk < nk; ++kk) acc = fma(tap[kk], win[t + nk - 1 - kk], acc);
+  }
+  if (o < R.ol) out[o] = (TO)acc;
 }
 
 // Transpose of the IP stage: midbar[p] = sum_d ip_{d+K} cot[o = p - K + d]
+//                                      = sum_k ip_k cot[p - 2K + k], 0 <= o < ol
 template <typename TC>
 __global__ __launch_bounds__(256) void k_convT_ip(RespDev R, const TC* __restrict__ cot,
                                                   double* __restrict__ midbar, int64_t nmid) {
-  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (p >= nmid) return;
+  __shared__ double tap[kTapChunk];
+  __shared__ double win[kWin];
+  const int t = threadIdx.x;
+  const int64_t p0 = (int64_t)blockIdx.x * 256, p = p0 + t;
+  const int64_t ntap = 2 * R.K + 1;
   double acc = 0.0;
-  for (int64_t k = 0; k < 2 * R.K + 1; ++k) {
-    const int64_t o = p - 2 * R.K + k;   // d = k - K
-    if (o >= 0 && o < R.ol) acc = fma(R.ip[k], (double)cot[o], acc);
+  for (int64_t k0 = 0; k0 < ntap; k0 += kTapChunk) {
+    const int nk = (int)min((int64_t)kTapChunk, ntap - k0);
+    const int64_t lo = p0 - 2 * R.K + k0;   // cot index of win[0]
+    __syncthreads();
+    for (int m = t; m < nk; m += 256) tap[m] = R.ip[k0 + m];
+    stage_window(win, cot, lo, 255 + nk, 0, R.ol - 1);   // outside [0, ol): 0
+    __syncthreads();
+    for (int kk = 0; kk < nk; ++kk) acc = fma(tap[kk], win[t + kk], acc);
   }
-  midbar[p] = acc;
+  if (p < nmid) midbar[p] = acc;
 }
 
 // Transpose of the rotation stage: F0bar[j] = sum_k rot_k midbar[p(i = j + dlo + k)]
 __global__ __launch_bounds__(256) void k_convT_rot(RespDev R, const double* __restrict__ midbar,
                                                    int64_t nmid, double* __restrict__ F0bar,
                                                    int64_t ng) {
-  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (j >= ng) return;
-  const int64_t p0 = j + R.dlo - (R.ob - R.K);   // p for k = 0
+  __shared__ double tap[kTapChunk];
+  __shared__ double win[kWin];
+  const int t = threadIdx.x;
+  const int64_t j0 = (int64_t)blockIdx.x * 256, j = j0 + t;
   double acc = 0.0;
-  for (int64_t k = 0; k < R.nrot; ++k) {
-    const int64_t p = p0 + k;
-    if (p >= 0 && p < nmid) acc = fma(R.rot[k], midbar[p], acc);
+  for (int64_t k0 = 0; k0 < R.nrot; k0 += kTapChunk) {
+    const int nk = (int)min((int64_t)kTapChunk, R.nrot - k0);
+    const int64_t lo = j0 + R.dlo - (R.ob - R.K) + k0;   // midbar index of win[0]
+    __syncthreads();
+    for (int m = t; m < nk; m += 256) tap[m] = R.rot[k0 + m];
+    stage_window(win, midbar, lo, 255 + nk, 0, nmid - 1);   // outside [0, nmid): 0
+    __syncthreads();
+    for (int kk = 0; kk < nk; ++kk) acc = fma(tap[kk], win[t + kk], acc);
   }
-  F0bar[j] = acc;
+  if (j < ng) F0bar[j] = acc;
 }
 
 // RV / vsini: sum_p midbar[p] * sum_k drot_k F0_{i - dlo - k}; block partials.
@@ -363,17 +435,33 @@ __global__ __launch_bounds__(256) void k_rot_param_grad(RespDev R, const double*
                                                         const double* __restrict__ midbar,
                                                         int64_t nmid, double* __restrict__ partR) {
   __shared__ double sm[4];
-  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  __shared__ double tap_rv[kTapChunk], tap_vs[kTapChunk];
+  __shared__ double win[kWin];
+  const int t = threadIdx.x;
+  const int64_t p0 = (int64_t)blockIdx.x * 256, p = p0 + t;
+  const int64_t vlo = R.ob - R.K - R.dlo - (R.nrot - 1), vhi = R.ob - R.K + nmid - 1 - R.dlo;
   double a = 0.0, b = 0.0;
-  if (p < nmid) {
-    const int64_t i = R.ob - R.K + p;
-    const double* __restrict__ src = F0 + (i - R.dlo);
-    for (int64_t k = 0; k < R.nrot; ++k) {
-      a = fma(R.drot_rv[k], src[-k], a);
-      b = fma(R.drot_vs[k], src[-k], b);
+  for (int64_t k0 = 0; k0 < R.nrot; k0 += kTapChunk) {
+    const int nk = (int)min((int64_t)kTapChunk, R.nrot - k0);
+    const int64_t lo = R.ob - R.K + p0 - R.dlo - (k0 + nk - 1);
+    __syncthreads();
+    for (int m = t; m < nk; m += 256) {
+      tap_rv[m] = R.drot_rv[k0 + m];
+      tap_vs[m] = R.drot_vs[k0 + m];
     }
+    stage_window(win, F0, lo, 255 + nk, vlo, vhi);
+    __syncthreads();
+    for (int kk = 0; kk < nk; ++kk) {
+      const double f = win[t + nk - 1 - kk];
+      a = fma(tap_rv[kk], f, a);
+      b = fma(tap_vs[kk], f, b);
+    }
+  }
+  if (p < nmid) {
     a *= midbar[p];
     b *= midbar[p];
+  } else {
+    a = b = 0.0;
   }
   const double sa = block_sum256(a, sm);
   const double sb = block_sum256(b, sm);
