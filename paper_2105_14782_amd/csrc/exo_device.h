@@ -26,10 +26,9 @@ constexpr double kLn10 = 2.30258509299404568402;
 constexpr double kHjertSwitch = 111.0;
 constexpr int kM916 = 27;                  // series length M (plain FP64 form)
 // Core branch of the FP32 sum: Weideman's rational approximation of w with
-// kWeidN terms (Weideman 1994, SIAM J. Numer. Anal. 31, 1497) at z for
-// a >= kWeidAmin (H within 2.4e-7 relative over x^2 + a^2 < 111 there), and
-// on the real axis, continued to first order in a, below.
-constexpr int kWeidN = 32;
+// 20-32 terms by the pair's a (Weideman 1994, SIAM J. Numer. Anal. 31, 1497)
+// at z for a >= kWeidAmin (H within 2.3e-7 relative over x^2 + a^2 < 111
+// there), and on the real axis, continued to first order in a, below.
 constexpr double kWeidAmin = 1e-5;
 
 // Records written by the line-parameter kernel for one (line, layer) and read

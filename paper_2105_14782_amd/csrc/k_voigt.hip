@@ -306,30 +306,38 @@ __device__ inline void neumaier(float& s, float& c, float v) {
 // t_k = L tan(theta_k/2), f(t) = e^{-t^2} (L^2 + t^2), M = 2N.  About half the
 // operations of the paper's Algorithm-916 series (no exponentials, no sine),
 // with H and L = Im w from the same evaluation.  Its absolute error is a
-// small fraction of |w|, which near the real axis far from the centre
-// (small a) is much larger than H; below kWeidAmin it is therefore used on
-// the real axis only (core_w below).
+// small fraction of |w| that falls exponentially with N; near the real axis
+// far from the centre (small a) |w| is much larger than H, so the N a pair
+// needs grows as a falls (core_w below).  The coefficients of every N used
+// live back to back in one table.
 // ---------------------------------------------------------------------------
-__device__ double g_weid[kWeidN];  // c_1 .. c_N, filled once per device
+constexpr int kWeidNs[4] = {20, 24, 28, 32};
+constexpr int kWeidOff[4] = {0, 20, 44, 72};
+constexpr int kWeidTab = 104;
+__device__ double g_weid[kWeidTab];  // c_1 .. c_N of each N, filled once per device
 
 __global__ __launch_bounds__(64) void k_weid_init() {
   const int n = threadIdx.x + 1;
-  if (n > kWeidN) return;
-  constexpr int M = 2 * kWeidN;
-  const double L = sqrt((double)kWeidN / kSqrt2);
-  double s = 0.0;
-  for (int k = -M + 1; k <= M - 1; ++k) {
-    const double th = k * (kPi / M);
-    const double t = L * tan(0.5 * th);
-    s += exp(-t * t) * (L * L + t * t) * cos(n * th);
+  for (int t = 0; t < 4; ++t) {
+    const int N = kWeidNs[t];
+    if (n > N) continue;
+    const int M = 2 * N;
+    const double L = sqrt((double)N / kSqrt2);
+    double s = 0.0;
+    for (int k = -M + 1; k <= M - 1; ++k) {
+      const double th = k * (kPi / M);
+      const double tt = L * tan(0.5 * th);
+      s += exp(-tt * tt) * (L * L + tt * tt) * cos(n * th);
+    }
+    g_weid[kWeidOff[t] + n - 1] = s / (2.0 * M);
   }
-  g_weid[n - 1] = s / (2.0 * M);
 }
 
-// Re w and Im w at z = x + ia (a > 0) in FP64 from the coefficients.
+// Re w and Im w at z = x + ia (a >= 0) in FP64 from the N coefficients c.
+template <int N>
 __device__ inline void weideman_w(double x, double a, const double __attribute__((address_space(4)))* c,
                                   double* re, double* im) {
-  const double L = sqrt((double)kWeidN / kSqrt2);
+  const double L = sqrt((double)N / kSqrt2);
   // u = 1/(L - iz) = 1/((L + a) - ix) = ((L + a) + ix)/den
   const double p = L + a;
   const double den = fma(p, p, x * x);
@@ -340,9 +348,9 @@ __device__ inline void weideman_w(double x, double a, const double __attribute__
   // Z = (L + iz) u = ((L - a) + ix) u
   const double q = L - a;
   const double zr = fma(q, ur, -x * ui), zi = fma(q, ui, x * ur);
-  double sr = c[kWeidN - 1], si = 0.0;
+  double sr = c[N - 1], si = 0.0;
 #pragma unroll 8
-  for (int n = kWeidN - 2; n >= 0; --n) {
+  for (int n = N - 2; n >= 0; --n) {
     const double tr = fma(sr, zr, fma(-si, zi, c[n]));
     si = fma(sr, zi, si * zr);
     sr = tr;
@@ -354,27 +362,35 @@ __device__ inline void weideman_w(double x, double a, const double __attribute__
   *im = fma(ur, vi, ui * vr);
 }
 
+template <int T>
 __device__ inline const double __attribute__((address_space(4)))* weid_coeffs() {
-  return (const double __attribute__((address_space(4)))*)(const double*)g_weid;
+  return (const double __attribute__((address_space(4)))*)((const double*)g_weid + kWeidOff[T]);
 }
 
-// H = Re w and L = Im w at z = x + ia in the core branch.  For a >= kWeidAmin
-// the rational approximation at z.  Below, w to first order in a about the
-// real axis, where w(x) = e^{-x^2} + i Im w(x) and w'(z) = -2z w(z) + 2i/sqrt(pi):
+// H = Re w and L = Im w at z = x + ia in the core branch, with the shortest
+// rational approximation that keeps H within 2.3e-7 relative over
+// x^2 + a^2 < 111 for the pair's a (measured against wofz on a dense grid:
+// N = 32 for 1e-5 <= a < 1e-3, 28 up to 3e-2, 24 up to 1, 20 beyond, where
+// the relative error of H falls about as 1/a).  For a < kWeidAmin, w to first
+// order in a about the real axis, where w(x) = e^{-x^2} + i Im w(x) and
+// w'(z) = -2z w(z) + 2i/sqrt(pi):
 //   H = e^{-x^2} + 2a (x Im w(x) - 1/sqrt(pi)),  L = Im w(x) - 2ax e^{-x^2},
-// with Im w(x) from the rational approximation (accurate there relative to
-// |w| ~ Im w) and e^{-x^2} exact.  The neglected terms are O(a^2 x^2)
-// relative (2e-9 at a = 1e-5 over the core); the rational form's own error in
-// H never enters, since H is mostly e^{-x^2} or the small difference
-// x Im w - 1/sqrt(pi), both formed from accurate parts.  a is uniform per
-// line, so the branch does not diverge.
+// with Im w(x) from the rational approximation (N = 28: accurate there
+// relative to |w| ~ Im w) and e^{-x^2} exact.  The neglected terms are
+// O(a^2 x^2) relative (2e-9 at a = 1e-5 over the core); the rational form's
+// own error in H never enters, since H is mostly e^{-x^2} or the small
+// difference x Im w - 1/sqrt(pi), both formed from accurate parts.  a is
+// uniform per line, so the branches do not diverge.
 __device__ inline void core_w(double x, double a, double* H, double* L) {
   if (a >= kWeidAmin) {
-    weideman_w(x, a, weid_coeffs(), H, L);
+    if (a < 1e-3) weideman_w<32>(x, a, weid_coeffs<3>(), H, L);
+    else if (a < 3e-2) weideman_w<28>(x, a, weid_coeffs<2>(), H, L);
+    else if (a < 1.0) weideman_w<24>(x, a, weid_coeffs<1>(), H, L);
+    else weideman_w<20>(x, a, weid_coeffs<0>(), H, L);
     return;
   }
   double re, im;
-  weideman_w(x, 0.0, weid_coeffs(), &re, &im);
+  weideman_w<28>(x, 0.0, weid_coeffs<2>(), &re, &im);
   const double ex2 = exp_core(-x * x);
   *H = ex2 + 2.0 * a * fma(x, im, -0.56418958354775628);
   *L = im - 2.0 * a * x * ex2;
