@@ -607,27 +607,28 @@ __device__ __forceinline__ void near_lines(int sb, int se, const LineRec* __rest
       for (int g = 0; g < G; ++g) {
         const float dd = (float)(nuj[g] - nul);  // FP64 offset, rounded once
         const float D = fmaf(dd, dd, e4g.w);
-        const float r = __builtin_amdgcn_rcpf(D);
+        // core pairs (marked here, evaluated after the loop) take r = 0, so
+        // the wing terms add exactly nothing for them (and never overflow)
+        const bool in_core = D < thr;
+        cm[g] |= (uint32_t)in_core << i;
+        const float r = in_core ? 0.f : __builtin_amdgcn_rcpf(D);
         float h = fmaf(e4g.z, r, e4g.y);
         h = fmaf(h, r, e4g.x);
         h = fmaf(h, r, e03.w);
         h = fmaf(h, r, e03.z);
         h = fmaf(h, r, e03.y);
         h = fmaf(h, r, e03.x);
-        float ht = 0.f;
+        blk[g] = fmaf(h, r, blk[g]);
         if (TAN) {
-          ht = fmaf(t47.w, r, t47.z);
+          float ht = fmaf(t47.w, r, t47.z);
           ht = fmaf(ht, r, t47.y);
           ht = fmaf(ht, r, t47.x);
           ht = fmaf(ht, r, t03.w);
           ht = fmaf(ht, r, t03.z);
           ht = fmaf(ht, r, t03.y);
           ht = fmaf(ht, r, t03.x);
+          tblk[g] = fmaf(ht, r, tblk[g]);
         }
-        const bool in_core = D < thr;
-        cm[g] |= (uint32_t)in_core << i;
-        blk[g] += in_core ? 0.f : h * r;
-        if (TAN) tblk[g] += in_core ? 0.f : ht * r;
       }
     }
     wave_lds_sync();
