@@ -638,7 +638,7 @@ def serving_bench(n_req, loads=(0.9,), n_streams=4, budget=48 << 30, n_cap=200):
         reqs = synth.serving_requests(n_req, rate, nu_master=nu)
         arr = np.array([q.arrival_s for q in reqs])
         st0 = srv.stats()
-        res = serve.run_stream(srv, args(reqs), arr)
+        res = serve.run_stream(srv, args(reqs), arr, progress=max(250, n_req // 20))
         st1 = srv.stats()
         lat = res["latency_s"]
         runs.append({"load": rho, "arrival_rate_hz": rate, "spectra_per_s": res["spectra_per_s"],

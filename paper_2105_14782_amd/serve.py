@@ -118,11 +118,13 @@ class Server:
 
 
 def run_stream(server: Server, requests: List[tuple], arrival_s: Optional[np.ndarray] = None,
-               precision="fp32") -> dict:
+               precision="fp32", progress: int = 0) -> dict:
     """Submit (atmos, response) pairs at the given arrival times (seconds from
     start; None = all at once) and wait for all.  Each request's latency is
     measured from its scheduled arrival, so a submitter that falls behind
-    the schedule adds to it.  Returns latencies, results and throughput."""
+    the schedule adds to it.  progress > 0 prints a line to stderr every
+    `progress` submissions.  Returns latencies, results and throughput."""
+    import sys
     n = len(requests)
     tickets = [None] * n
     t0 = time.monotonic()
@@ -134,6 +136,10 @@ def run_stream(server: Server, requests: List[tuple], arrival_s: Optional[np.nda
             if delay > 0:
                 time.sleep(delay)
             tickets[i] = server.submit(a, r, precision, arrival_s=due)
+            if progress and (i + 1) % progress == 0:
+                st = server.stats()
+                print(f"serving: submitted {i + 1}/{n} at {time.monotonic() - t0:.1f} s, "
+                      f"{st['completed']} done, {st['queued']} queued", file=sys.stderr, flush=True)
 
     th = threading.Thread(target=submitter)
     th.start()
