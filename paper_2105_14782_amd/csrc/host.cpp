@@ -569,10 +569,8 @@ int exo::species_opacity(exo_ctx* c, Workspace& ws, const Species& sp, const dou
   const bool adaptive = adaptive_scale && !fp64 && d_T == nullptr && nlay == 1;
   unsigned long long* amax = adaptive ? (unsigned long long*)(g2bits + 4 * kMaxLayers) : nullptr;
   float* oscale = adaptive ? (float*)(g2bits + 4 * kMaxLayers + 2) : nullptr;
-  if (!fp64 && ws.tier_zeroed != ws.tier.p) {
-    if (ws.no_alloc) HIP_TRY(launch_zero_words(ws.tier.p, kTierBytes, st));
-    else HIP_TRY(hipMemsetAsync(ws.tier.p, 0, kTierBytes, st));
-  }
+  // cleared by a kernel, not a memset: the call may be captured in a graph
+  if (!fp64 && ws.tier_zeroed != ws.tier.p) HIP_TRY(launch_zero_words(ws.tier.p, kTierBytes, st));
   ws.tier_zeroed = nullptr;
   for (int l0 = 0; l0 < nlay; l0 += nlc) {
     const int nl = std::min(nlc, nlay - l0);
