@@ -540,16 +540,19 @@ def _resp_with(resp, theta):
     return replace(resp, rv_kms=float(theta[-2]), vsini_kms=float(theta[-1]))
 
 
-def flux_tangents(wl, theta, per_layer=False):
+def flux_tangents(wl, theta, per_layer=False, nu_idx=None):
     """F and dF/dtheta for theta = (T0, alpha, log10 X_1..X_M, RV, vsini).
 
     Forward-mode: the tangent of every intermediate quantity is carried
     through the recurrence of Eq. rerr and the response.  With per_layer,
-    also dF/dT_n for every layer n.
+    also dF/dT_n for every layer n.  Without a response every grid point's
+    column is independent, and nu_idx restricts the result to those points.
     """
     atm = wl.atmos
     nm = len(wl.lines)
-    c = optical_depths(wl, theta, want_dT=True)
+    if nu_idx is not None and wl.response is not None:
+        raise ValueError("grid points can be selected only without the response")
+    c = optical_depths(wl, theta, nu_idx=nu_idx, want_dT=True)
     P = atm.P_bar
     T = c.T
     NL = P.size

@@ -126,6 +126,42 @@ def test_jvp_full_config2_against_fp64_differences(exo):
     c.close()
 
 
+def test_full_config4_sampled_derivatives_against_oracle(exo):
+    """Full configuration-4 size (2 x 1e5 lines, 20,000 points, 100 layers) in
+    the bench's launch shapes, without the response so that every grid
+    point's column is independent: J e_k along T0, alpha and both mixing
+    ratios at 64 sampled points (both ends and 62 random ones), and the VJP of
+    a cotangent carried by those points (every parameter and every layer's
+    dL/dT_n), against the oracle's forward-mode tangents at those points."""
+    _say("full config-4 size, sampled points: JVP and VJP vs oracle")
+    wl = replace(synth.make_config(4, "full"), response=None)
+    th = np.array(wl.theta, dtype=float)
+    c = _ctx(exo, wl)
+    atm, _ = _inputs(exo, wl, th)
+    rng = np.random.default_rng(2027)
+    ng = wl.nu.size
+    idx = np.concatenate([[0], np.sort(rng.choice(np.arange(1, ng - 1), 62, replace=False)), [ng - 1]])
+    t = O.flux_tangents(wl, th, per_layer=True, nu_idx=idx)
+    for k in range(4):
+        e = np.zeros(6)
+        e[k] = 1.0
+        _, dF = c.flux_jvp(atm, None, e, want_flux=False)
+        err = _rel(dF.cpu().double().numpy()[idx], t["dF"][k])
+        _say(f"  J e_{k}: max rel err {err:.2e}")
+        assert err < RTOL_GRAD, (k, err)
+    cot = np.zeros(ng)
+    cot[idx] = rng.normal(size=idx.size)
+    g, gl, _ = c.flux_vjp(atm, None, torch.tensor(cot, dtype=torch.float32, device="cuda"), want_layers=True)
+    g_ref = t["dF"][:4] @ cot[idx]
+    gl_ref = t["dF_dTn"] @ cot[idx]
+    err = np.abs(g[:4] - g_ref) / np.maximum(np.abs(g_ref), 1e-6 * np.abs(g_ref).max())
+    errl = np.abs(gl - gl_ref) / np.maximum(np.abs(gl_ref), 1e-6 * np.abs(gl_ref).max())
+    _say(f"  VJP rel err {err}; per-layer max rel err {errl.max():.2e}")
+    assert np.all(err < RTOL_GRAD), (g, g_ref)
+    assert errl.max() < RTOL_GRAD
+    c.close()
+
+
 def test_jvp_vjp_dot_product(exo):
     wl = synth.make_config(4, "small")
     th = wl.theta

@@ -519,3 +519,18 @@ def test_strength_tangent_with_partition_table():
         lp = np.log(O.line_state(ll, T + h, 0.3).S)
         lm = np.log(O.line_state(ll, T - h, 0.3).S)
         np.testing.assert_allclose(st.dlnS_dT, (lp - lm) / (2 * h), rtol=1e-6, atol=1e-12)
+
+
+def test_sampled_tangents_equal_full_grid_tangents():
+    """Without the response every grid point's column is independent, so the
+    tangents at selected points equal those of the whole grid there."""
+    from dataclasses import replace
+    wl = replace(synth.make_config(4, "tiny"), response=None)
+    idx = np.array([0, 5, 77, 300, wl.nu.size - 1])
+    a = O.flux_tangents(wl, wl.theta, per_layer=True)
+    b = O.flux_tangents(wl, wl.theta, per_layer=True, nu_idx=idx)
+    np.testing.assert_array_equal(a["F"][idx], b["F"])
+    np.testing.assert_array_equal(a["dF"][:, idx], b["dF"])
+    np.testing.assert_array_equal(a["dF_dTn"][:, idx], b["dF_dTn"])
+    with pytest.raises(ValueError):
+        O.flux_tangents(synth.make_config(4, "tiny"), wl.theta, nu_idx=idx)
