@@ -778,6 +778,21 @@ def main():
     t64 = time_fwd("fp64", args.fp64_reps)
     t64t = time_fwd("fp64_tiled", max(3, args.fp64_reps))
 
+    # agreement of the forms on this workload (outside the timed regions):
+    # the FP32 spectrum against both FP64 spectra, and the FP32 gradient of
+    # the bench's cotangent against the FP64 one
+    F32 = ctx.emission_flux(atm, resp, "fp32").double()
+    F64 = ctx.emission_flux(atm, resp, "fp64")
+    F64t = ctx.emission_flux(atm, resp, "fp64_tiled")
+    g32, _, _ = ctx.flux_vjp(atm, resp, cot)
+    g64, _, _ = ctx.flux_vjp(atm, resp, cot.double(), precision="fp64_tiled")
+    agreement = {
+        "fp32_vs_fp64_plain_max_rel": float(((F32 - F64).abs() / F64.abs()).max()),
+        "fp32_vs_fp64_tiled_max_rel": float(((F32 - F64t).abs() / F64t.abs()).max()),
+        "fp64_tiled_vs_plain_max_rel": float(((F64t - F64).abs() / F64.abs()).max()),
+        "gradient_fp32_vs_fp64_max_rel": float(np.max(np.abs(g32 - g64) / np.maximum(np.abs(g64), 1e-6 * np.abs(g64).max()))),
+    }
+
     # one leapfrog step of the sampler: Gaussian likelihood and its gradient in one pass
     Fd = ctx.emission_flux(atm, resp, "fp32")
     dat = (Fd * (1.0 + 0.01 * torch.randn(Fd.numel(), device="cuda", generator=None))).contiguous()
@@ -839,6 +854,7 @@ def main():
         "fp32_over_fp64_spectra": t64 / t32,
         "fp32_over_fp64_plain_spectra": t64 / t32,
         "fp32_over_fp64_tiled_spectra": t64t / t32,
+        "agreement": agreement,
         "flux_jvp": {"ms_per_call": tjvp * 1e3, "evals_per_s": evals / tjvp},
         "leapfrog_loss_grad": {"ms_per_call": tloss * 1e3, "evals_per_s": evals / tloss},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",

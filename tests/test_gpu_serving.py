@@ -59,6 +59,28 @@ def test_results_identical_alone_and_in_mix(setup):
     assert torch.equal(ctx.emission_flux(a, r).cpu(), ref[3])
 
 
+def test_hundred_requests_identical_alone_and_in_mix(setup):
+    """100 requests with the serving workload's layer counts (50-200) and
+    windows of 2,000-20,000 points: each result is bitwise the one it gives
+    alone, with eight slots and every request submitted at once."""
+    api, ctx, lists, nu, _ = setup
+    from paper_2105_14782_amd import serve
+    reqs = synth.serving_requests(100, rate_hz=0.0, seed=2024, n_lists=6, nu_master=nu,
+                                  min_grid=2000, max_grid=20000, min_layers=50, max_layers=200)
+    args = [_req_args(api, nu, lists, q) for q in reqs]
+    ref = [ctx.emission_flux(a, r).cpu() for a, r in args]
+    mix = serve.Server(ctx, n_streams=8, mem_budget_bytes=8 << 30)
+    out = serve.run_stream(mix, args)
+    st = mix.stats()
+    mix.close()
+    print(f"  100 requests: peak in flight {st['peak_in_flight']}, "
+          f"{out['spectra_per_s']:.1f} spectra/s", flush=True)
+    assert st["completed"] == len(args) and st["failed"] == 0
+    assert st["peak_in_flight"] >= 2
+    same = [torch.equal(res.flux.cpu(), r0) for res, r0 in zip(out["results"], ref)]
+    assert all(same), [k for k, s in enumerate(same) if not s]
+
+
 def test_serving_result_matches_oracle(setup):
     api, ctx, lists, nu, reqs = setup
     from paper_2105_14782_amd import serve
