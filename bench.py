@@ -57,6 +57,7 @@ def parse():
     ap.add_argument("--cpu-points", type=int, default=256)
     ap.add_argument("--serve-requests", type=int, default=1000,
                     help="requests of the Poisson serving run (0: skip)")
+    ap.add_argument("--serve-streams", type=int, default=4, help="serving slots (1..16)")
     ap.add_argument("--serve-capacity-requests", type=int, default=200,
                     help="requests of the closed-loop capacity run that sets the arrival rate")
     ap.add_argument("--no-config3", action="store_true", help="skip the full config-3 direct-sum spectrum")
@@ -697,7 +698,7 @@ def main():
         print(json.dumps({"config3_direct": config3_direct_bench()}), flush=True)
         return
     if args.serving_only:
-        print(json.dumps({"serving": serving_bench(args.serve_requests, args.serve_load,
+        print(json.dumps({"serving": serving_bench(args.serve_requests, args.serve_load, n_streams=args.serve_streams,
                                                    n_cap=args.serve_capacity_requests)}), flush=True)
         return
     import torch
@@ -878,7 +879,8 @@ def main():
     }
     ctx.close()
     if args.serve_requests > 0:
-        out["serving"] = serving_bench(args.serve_requests, args.serve_load, n_cap=args.serve_capacity_requests)
+        out["serving"] = serving_bench(args.serve_requests, args.serve_load, n_streams=args.serve_streams,
+                                       n_cap=args.serve_capacity_requests)
     wl3 = None
     if not args.no_config3 or not args.no_modit:
         wl3 = synth.make_config(3, "full")
