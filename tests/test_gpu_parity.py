@@ -302,6 +302,36 @@ def test_emission_small_F0_zero_bottom(exo):
     assert maxrel(F0, ref) < RTOL_FLUX
 
 
+def test_emission_and_gradient_at_the_layer_limit(exo):
+    """4096 layers, the most an atmosphere may have (thin layers from 1e-8 to
+    1e2 bar): the spectrum in FP32 and FP64 and the VJP of a random cotangent
+    (every parameter and every layer) against the oracle; 4097 are refused."""
+    from dataclasses import replace
+    import paper_2105_14782_amd as pkg
+    _say("emission and gradient at 4096 layers")
+    wl0 = synth.make_config(4, "tiny")
+    wl = replace(wl0, atmos=replace(wl0.atmos, P_bar=np.logspace(-8.0, 2.0, 4096)))
+    c = _ctx_with(exo, wl)
+    th = wl.theta
+    atm = _atmos(exo, wl, th)
+    resp = exo.Response.from_workload(wl.response, th)
+    t = O.flux_tangents(wl, th, per_layer=True)
+    for prec, tol in [("fp32", RTOL_FLUX), ("fp64", 1e-5)]:
+        err = maxrel(c.emission_flux(atm, resp, prec).cpu().double().numpy(), t["F"])
+        _say(f"  {prec} max rel err {err:.3e}")
+        assert err < tol
+    cot = np.random.default_rng(4096).normal(size=resp.out_len).astype(np.float32)
+    g, gl, _ = c.flux_vjp(atm, resp, torch.tensor(cot, device="cuda"), want_layers=True)
+    err = _check_grad(g, t["dF"] @ cot.astype(np.float64), RTOL_GRAD)
+    errl = _check_grad(gl, t["dF_dTn"] @ cot.astype(np.float64), RTOL_GRAD)
+    _say(f"  grad rel err {err.max():.2e}; per-layer max rel err {errl.max():.2e}")
+    assert np.all(err < RTOL_GRAD) and np.all(errl < RTOL_GRAD)
+    over = _atmos(exo, replace(wl, atmos=replace(wl.atmos, P_bar=np.logspace(-8.0, 2.0, 4097))), th)
+    with pytest.raises(pkg.ExoError) as e:
+        c.emission_flux(over, resp)
+    assert e.value.code == pkg.EXO_EINVAL
+
+
 def test_emission_sub_grid_window(exo):
     """A model grid that is a window of the registered grid gives the window's spectrum."""
     wl = synth.make_config(2, "small")

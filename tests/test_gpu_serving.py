@@ -81,6 +81,22 @@ def test_hundred_requests_identical_alone_and_in_mix(setup):
     assert all(same), [k for k, s in enumerate(same) if not s]
 
 
+def test_fp64_requests_identical_to_the_synchronous_api(setup):
+    """FP64 requests in the serving engine give the synchronous FP64 spectrum bitwise."""
+    api, ctx, lists, nu, reqs = setup
+    from paper_2105_14782_amd import serve
+    args = [_req_args(api, nu, lists, q) for q in reqs[:6]]
+    ref = [ctx.emission_flux(a, r, "fp64").cpu() for a, r in args]
+    srv = serve.Server(ctx, n_streams=3, mem_budget_bytes=4 << 30)
+    out = serve.run_stream(srv, args, precision="fp64")
+    st = srv.stats()
+    srv.close()
+    assert st["completed"] == len(args) and st["failed"] == 0
+    for k, (res, r0) in enumerate(zip(out["results"], ref)):
+        assert res.flux.dtype == torch.float64
+        assert torch.equal(res.flux.cpu(), r0), k
+
+
 def test_serving_result_matches_oracle(setup):
     api, ctx, lists, nu, reqs = setup
     from paper_2105_14782_amd import serve
