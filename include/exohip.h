@@ -69,8 +69,9 @@ typedef enum {
    * mapping, per-wave record staging, near/far split and core branch (the
    * rational approximation of w), with the full asymptotic polynomial on
    * every wing pair and plain FP64 accumulation.  For measuring the cost of
-   * precision alone.  Forward only (exo_cross_section, exo_emission_flux);
-   * outputs are double. */
+   * precision alone.  Taken by exo_cross_section, exo_emission_flux and
+   * exo_flux_vjp (whose FP64 gradient always runs this form, through its
+   * tangent mode); outputs are double. */
   EXO_FP64_TILED = 2
 } exo_precision;
 
