@@ -120,6 +120,24 @@ def test_cross_section_config1(exo, prec):
     assert err < (RTOL_FLUX if prec == "fp32" else 1e-5)
 
 
+@pytest.mark.parametrize("factor", [1e-8, 1e14, 1e27])
+def test_cross_section_strength_scales(exo, factor):
+    """The config-1 list with every strength multiplied by `factor` (strengths
+    from 1e-33 to 1e7 cm/molecule over the three cases): the FP32 records
+    carry a power-of-two scale chosen on the device from the largest
+    strength, so the relative error is that of the unscaled list."""
+    from dataclasses import replace
+    _say(f"cross_section strengths x {factor:g}")
+    wl = synth.make_config(1, "full")
+    ll = replace(wl.lines[0], S0=wl.lines[0].S0 * factor)
+    c = _ctx_with(exo, replace(wl, lines=[ll]))
+    ref = O.cross_section(ll, wl.T, wl.P_bar, wl.nu)
+    for prec, tol in [("fp32", RTOL_FLUX), ("fp64", 1e-5)]:
+        err = maxrel(c.cross_section(0, wl.T, wl.P_bar, prec).cpu().double().numpy(), ref)
+        _say(f"  {prec} max rel err {err:.3e}")
+        assert err < tol
+
+
 @pytest.mark.parametrize("n_lines,n_nu", [(1, 2), (1, 7), (33, 257), (97, 1023), (200, 4097)])
 def test_cross_section_ragged_shapes(exo, n_lines, n_nu):
     rng = np.random.default_rng(n_lines * 7919 + n_nu)
