@@ -303,9 +303,9 @@ __device__ inline void neumaier(float& s, float& c, float v) {
 //   w(z) ~ u/sqrt(pi) + 2 u^2 sum_{n=1..N} c_n Z^(n-1), with
 // u = 1/(L - iz), Z = (L + iz)/(L - iz), L = (N/sqrt2)^(1/2), and
 // c_n = (1/2M) sum_{|k|<M} f(t_k) cos(n theta_k), theta_k = k pi/M,
-// t_k = L tan(theta_k/2), f(t) = e^{-t^2} (L^2 + t^2), M = 2N.  About half the
-// operations of the paper's Algorithm-916 series (no exponentials, no sine),
-// with H and L = Im w from the same evaluation.  Its absolute error is a
+// t_k = L tan(theta_k/2), f(t) = e^{-t^2} (L^2 + t^2), M = 2N.  About 2N + 20
+// FP64 operations, a fraction of the paper's Algorithm-916 series (no
+// exponentials, no sine), with H and L = Im w from the same evaluation.  Its absolute error is a
 // small fraction of |w| that falls exponentially with N; near the real axis
 // far from the centre (small a) |w| is much larger than H, so the N a pair
 // needs grows as a falls (core_w below).  The coefficients of every N used
@@ -348,13 +348,22 @@ __device__ inline void weideman_w(double x, double a, const double __attribute__
   // Z = (L + iz) u = ((L - a) + ix) u
   const double q = L - a;
   const double zr = fma(q, ur, -x * ui), zi = fma(q, ui, x * ur);
-  double sr = c[N - 1], si = 0.0;
+  // s = sum_{n<N} c_n Z^n with real c_n, by dividing the polynomial by the
+  // real quadratic t^2 - 2 Re(Z) t + |Z|^2, which vanishes at Z: the
+  // remainder alpha t + beta gives s = alpha Z + beta (Goertzel's method;
+  // Knuth, TAOCP vol. 2, 4.6.4).  Two real FMAs per coefficient instead of
+  // the four of complex Horner steps.  |Z| <= 1 for a >= 0, so the
+  // recurrence does not amplify rounding.
+  const double r = 2.0 * zr, m = -fma(zr, zr, zi * zi);
+  double e2 = 0.0, e1 = c[N - 1];
 #pragma unroll 8
-  for (int n = N - 2; n >= 0; --n) {
-    const double tr = fma(sr, zr, fma(-si, zi, c[n]));
-    si = fma(sr, zi, si * zr);
-    sr = tr;
+  for (int k = N - 3; k >= 1; --k) {
+    const double e = fma(r, e1, fma(m, e2, c[k + 1]));
+    e2 = e1;
+    e1 = e;
   }
+  const double al = fma(r, e1, fma(m, e2, c[1]));
+  const double sr = fma(al, zr, fma(m, e1, c[0])), si = al * zi;
   // w = u (1/sqrt(pi) + 2 u s)
   const double vr = 0.56418958354775628 + 2.0 * fma(ur, sr, -ui * si);
   const double vi = 2.0 * fma(ur, si, ui * sr);
