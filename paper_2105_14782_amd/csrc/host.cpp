@@ -469,10 +469,11 @@ static constexpr size_t kRecBudget = size_t(4) << 30;
 // device (fixed by the shape only, so results never depend on the load).
 // Splits go down to 16 lines: a small problem (a few tiles) is otherwise
 // bound by one wave's line-record load latency, line after line.  The target
-// is 8192 workgroups, four per resident slot (2048 of 4 waves at 8 waves per
-// SIMD): a wave's near lines and core pairs fall in one split, so finer
-// splits even out the workgroups' run times (config 2: 5 splits instead of 2,
-// 2.8 % faster per step; 16384 the same, 4096 half the gain).
+// is 8192 workgroups, 5-6 per resident slot (1280 of 4 waves at the tangent
+// kernel's 5 waves per SIMD, 1536 at the forward kernel's 6): a wave's near
+// lines and core pairs fall in one split, so finer splits even out the
+// workgroups' run times (config 2: 5 splits instead of 2, 2.8 % faster per
+// step; 4096, 6144 and 12288 measured no better).
 static void split_plan(int64_t ng, int nl, int64_t n_lines, bool one_point, int64_t* ks_out,
                        int64_t* lps_out) {
   // one_point: the plain FP64 form (one grid point per thread)

@@ -476,8 +476,8 @@ struct FarStage {
 };
 // The near tier stages its lines the same way (full polynomials, the core
 // threshold and the FP64 centre; lanes 0..31 the value side, 32..63 the
-// tangent side of 32 lines), and walks them one line per iteration: two
-// lines in flight spill inside the loop at 64 registers per lane.
+// tangent side of 32 lines), and walks them one line per iteration (two
+// lines in flight spilled inside the loop at 64 registers per lane).
 struct NearStage {
   float4 e03[kChunk];  // e0..e3
   float4 e4g[kChunk];  // e4, e5, e6, gamma^2
@@ -743,21 +743,22 @@ __device__ __forceinline__ void voigt_body(const VoigtArgs& A) {
   }
 }
 
-// The kernels.  Both ask for 8 waves per SIMD (64 registers per lane): the
-// line loops stay free of spills (the tangent kernel's land around the
-// out-of-line core call and the chunk bookkeeping), and the extra waves hide
-// memory and LDS latency: with scalar-loaded line records the tangent kernel measured
-// 2.6 % faster than at 7 waves (72 registers), 9 % faster than at 5 (96, its
-// spill-free budget); the forward kernel 10 % faster than at 7.
+// The kernels.  The tangent kernel asks for 5 waves per SIMD (96 registers
+// per lane), where nothing spills around the out-of-line core call; the
+// forward kernel for 6 (80 registers).  With the records staged through LDS
+// and the core's polynomial evaluated by Goertzel's method, the tangent
+// kernel measured 4.5 % faster at 5 waves than at 8 (64 registers, spills
+// around the call), 1.7 % faster than at 4 and 1 % faster than at 6; the
+// forward kernel 1.5 % faster at 6 than at 8.
 template <bool TAN, int G>
 __global__ void k_voigt_f32(VoigtArgs A);
 template <>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_voigt_f32<false, kVoigtG>(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 6))) void k_voigt_f32<false, kVoigtG>(
     VoigtArgs A) {
   voigt_body<false, kVoigtG>(A);
 }
 template <>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_voigt_f32<true, kVoigtG>(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 5))) void k_voigt_f32<true, kVoigtG>(
     VoigtArgs A) {
   voigt_body<true, kVoigtG>(A);
 }
