@@ -201,3 +201,50 @@ def test_small_requests_bypass_a_head_waiting_for_memory(setup):
     assert ahead == st["bypasses"]
     for k, (r, f) in enumerate(zip(res, ref)):
         assert torch.equal(r.flux.cpu(), f), k
+
+
+def test_full_scale_serving_requests_against_oracle():
+    """The serving workload at its full scale: the resident pool of 16 lists
+    (1e3-1e6 lines over 3900-5100 cm^-1) on the R0 = 1e6 master grid, and the
+    three largest of 40 requests drawn from its arrival process (by line x
+    point x layer count), served together without the response.  Each F0 at
+    64 sampled points (both window ends and 62 random ones) against the
+    oracle over all lines and layers."""
+    import time
+    from paper_2105_14782_amd import api, serve
+    lists, nu = synth.serving_pool()
+    ctx = api.Context(0)
+    for s, ll in enumerate(lists):
+        ctx.set_lines(s, ll)
+    ctx.set_grid(nu)
+    pool = synth.serving_requests(40, rate_hz=0.0, seed=4242, nu_master=nu)
+    work = [(lists[q.species[0]].n + lists[q.species[1]].n) * q.grid_len * q.n_layers for q in pool]
+    reqs = [pool[k] for k in np.argsort(work)[-3:]]
+    args = []
+    for q in reqs:
+        P, T0, al, logx, rv, vs = synth.serving_atmosphere(q)
+        args.append(api.Atmos(P, T0, al, list(q.species), list(logx), cia_alpha0=5e-46, cia_Tpow=1.0,
+                              cia_slope=0.1, cia_nu_c=4500.0, vmr_h2=0.75 * 2.33 / 2.016,
+                              grid_begin=q.grid_begin, grid_len=q.grid_len))
+    srv = serve.Server(ctx, n_streams=3, mem_budget_bytes=48 << 30)
+    tickets = [srv.submit(a, None) for a in args]
+    res = [srv.wait(t) for t in tickets]
+    st = srv.stats()
+    srv.close()
+    assert st["completed"] == 3 and st["failed"] == 0
+    rng = np.random.default_rng(4243)
+    for q, a, r in zip(reqs, args, res):
+        F = r.flux.cpu().double().numpy()
+        idx = np.concatenate([[0], np.sort(rng.choice(np.arange(1, q.grid_len - 1), 62, replace=False)),
+                              [q.grid_len - 1]])
+        wl = synth.Workload("serve-full", [lists[q.species[0]], lists[q.species[1]]],
+                            nu[q.grid_begin:q.grid_begin + q.grid_len],
+                            synth.Atmosphere(a.P_bar, a.T0, a.alpha, np.asarray(a.log10_mmr), cia_nu_c=4500.0),
+                            None)
+        t = time.monotonic()
+        ref = O.emission_F0(wl, np.array([a.T0, a.alpha, *a.log10_mmr]), nu_idx=idx)
+        err = float(np.max(np.abs(F[idx] - ref) / np.abs(ref)))
+        print(f"  {lists[q.species[0]].n + lists[q.species[1]].n} lines x {q.grid_len} points x "
+              f"{q.n_layers} layers: max rel err {err:.2e} (oracle {time.monotonic() - t:.1f} s)", flush=True)
+        assert err < 1e-4
+    ctx.close()
