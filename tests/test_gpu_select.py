@@ -98,3 +98,38 @@ def test_selection_errors(exo):
     with pytest.raises(pkg.ExoError) as e:
         c.select_lines(1, -3.0, a, 1000.0)
     assert e.value.code == pkg.EXO_ENOTSET
+
+
+def test_selection_full_config3_sampled(exo):
+    """The full 1e7-line config-3 list on its 100-layer atmosphere, as the
+    bench selects it (isothermal 1700 K, strengths scanned over 500-1700 K,
+    margin 2): the GPU mask of 20,000 random lines against the oracle's
+    selection of those lines (each line's decision depends on that line
+    alone)."""
+    wl = synth.make_config(3, "full")
+    full = wl.lines[0]
+    c = exo.Context(0)
+    c.set_lines(0, full)
+    a = exo.Atmos.from_workload(wl.atmos, [0])
+    T_scan = np.arange(500.0, 1701.0, 100.0)
+    lx = math.log10(0.0023)
+    keep, n_kept = c.select_lines(0, lx, a, 1700.0, T_scan, 2)
+    keep = keep.cpu().numpy().astype(bool)
+    assert n_kept == int(keep.sum())
+    idx = np.sort(np.random.default_rng(303).choice(full.n, 20000, replace=False))
+    sub = replace(full, nu_c=full.nu_c[idx], S0=full.S0[idx], E_low=full.E_low[idx],
+                  alpha_ref=full.alpha_ref[idx], n_texp=full.n_texp[idx])
+    ref, _, _ = SEL.select_lines(sub, lx, wl.atmos, 1700.0, T_scan, 2)
+    bad = np.nonzero(keep[idx] != ref)[0]
+    if bad.size:
+        P = np.asarray(wl.atmos.P_bar, float)
+        dP = O.layer_dP_bar(P)
+        sb = replace(sub, nu_c=sub.nu_c[bad], S0=sub.S0[bad], E_low=sub.E_low[bad],
+                     alpha_ref=sub.alpha_ref[bad], n_texp=sub.n_texp[bad])
+        _, psi = SEL.contribution_argmax(SEL.line_centre_dtau(sb, lx, wl.atmos, 1700.0, T_scan), P, dP)
+        dc = np.stack([O.dtau_cia(1700.0, P[n], dP[n], np.asarray(sb.nu_c), wl.atmos) for n in range(P.size)])
+        _, psic = SEL.contribution_argmax(dc, P, dP)
+        assert (_near_ties(psi) | _near_ties(psic)).all(), bad
+    _say(f"  kept {n_kept} of {full.n}; sampled 20000: {int(ref.sum())} kept by the oracle, "
+         f"mismatches at near-ties: {bad.size}")
+    c.close()
