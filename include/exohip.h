@@ -149,7 +149,8 @@ int exo_set_grid(exo_ctx* ctx, int64_t n_nu, const double* nu);
  * (Eq. crosssec summed over lines):
  *   sigma(nu_j) = sum_l S_l(T) V(nu_j - nu_l; beta_l(T), gamma_l(T, P)).
  * sigma_dev: device, [n_nu] float (EXO_FP32_KAHAN) or double (EXO_FP64,
- * EXO_FP64_TILED).
+ * EXO_FP64_TILED).  A float cross-section beyond the FP32 range comes back
+ * as +inf.
  * Errors: EXO_ENOTSET, EXO_EINVAL (T <= 0, P < 0, bad precision),
  * EXO_ENOMEM, EXO_EDEVICE. */
 int exo_cross_section(exo_ctx* ctx, int s, double T_K, double P_bar, int precision,
@@ -185,6 +186,10 @@ int exo_cross_section_noalloc(exo_ctx* ctx, int s, double T_K, double P_bar, int
  * Needs a log-uniform grid.  Only lines with nu_0 <= nu_l <= nu_{N-1} enter
  * the density; the transform length is the smallest power of two >= 2N (the
  * aliasing correction the paper mentions is unpublished and not applied).
+ * FP32: the strengths are carried with exact power-of-two scales per block
+ * of lines and per layer, so no intermediate sum overflows; a result beyond
+ * the FP32 range comes back infinite, and values far below the layer's
+ * largest lose precision to the transform's rounding (App. B).
  * sigma_dev as exo_cross_section.  Errors: EXO_EINVAL, EXO_ENOTSET,
  * EXO_ENOMEM, EXO_EDEVICE. */
 int exo_cross_section_modit(exo_ctx* ctx, int species, double T_K, double P_bar, int precision,

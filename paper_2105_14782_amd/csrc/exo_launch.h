@@ -104,7 +104,7 @@ constexpr int kModitRows = kModitMaxBins / 2;
 struct ModitBins {
   double lng0, d;   // ln gamma~_k = lng0 + k d
   int K;
-  int pad;
+  int yexp;         // FP32: the layer's strength exponent (largest block exponent), 0 in FP64
 };
 // Per-layer constants of the MODIT line pass.
 struct ModitLayer {
@@ -116,7 +116,8 @@ struct ModitArgs {
   const double* P;         // device [nl] layer pressures
   const double* col;       // device [nl] column factors, or NULL: when given the output is
                            // col[n] sigma clamped at zero (an optical depth)
-  double mass, R0, amp_scale, dlng;
+  double mass, R0, dlng;
+  int amp_exp;             // FP32: a layer's largest strength is held at about 2^amp_exp (0 in FP64)
   const double* nu;        // grid [ng] (log-uniform)
   int64_t ng, n_fft;
   const double* nu_c;      // sorted centres (= L.nu_c)
@@ -126,8 +127,9 @@ struct ModitArgs {
   void* f;                 // [n_in] R: position of the line in its cell, in [0, 1]
   int64_t* cell;           // [ng + 1]: lines of cell j are [cell[j], cell[j + 1]) (window-relative)
   ModitLayer* lay;         // [nl]
-  void* rec;               // [nl][n_in] {ln gamma~, S amp_scale} as R pairs
-  double* part;            // [nl][2 n_part] min/max partials of ln gamma~, one per line block
+  void* rec;               // [nl][n_in] {ln gamma~, S} as R pairs (FP32: S 2^(amp_exp - block exponent))
+  double* part;            // [nl][3 n_part] per line block: min and max of ln gamma~, and (FP32)
+                           // the block's strength exponent
   int64_t n_part;
   ModitBins* bins;         // device [nl]
   void *rows0, *rows1;     // [nl][kModitRows][n_fft] complex (float2 or double2), bins in pairs

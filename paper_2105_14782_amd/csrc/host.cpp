@@ -741,14 +741,14 @@ static ModitPlan modit_plan(int64_t n_in, int64_t ng, int nlay, bool fp64) {
   q.n_fft = modit_fft_len(ng);
   q.nbl = (ni + 255) / 256;
   const size_t per_layer = 2 * (size_t)kModitRows * q.n_fft * csz + (size_t)ni * psz +
-                           2 * (size_t)q.nbl * sizeof(double) + sizeof(ModitBins) + sizeof(ModitLayer);
+                           3 * (size_t)q.nbl * sizeof(double) + sizeof(ModitBins) + sizeof(ModitLayer);
   const size_t nb = std::max<size_t>(1, kModitBudget / per_layer);
   q.nb = (int)std::min<size_t>({nb, (size_t)nlay, (size_t)kModitMaxLayersPerLaunch});
   q.off_cell = align256((size_t)ni * sizeof(double));
   q.off_lay = q.off_cell + align256((size_t)(ng + 1) * sizeof(int64_t));
   q.off_rec = q.off_lay + align256((size_t)q.nb * sizeof(ModitLayer));
   q.lines_bytes = q.off_rec + (size_t)q.nb * ni * psz;
-  q.part_bytes = align256((size_t)q.nb * 2 * q.nbl * sizeof(double)) + (size_t)q.nb * sizeof(ModitBins);
+  q.part_bytes = align256((size_t)q.nb * 3 * q.nbl * sizeof(double)) + (size_t)q.nb * sizeof(ModitBins);
   q.rows_bytes = (size_t)q.nb * kModitRows * q.n_fft * csz;
   return q;
 }
@@ -778,8 +778,6 @@ int exo::modit_opacity(exo_ctx* c, Workspace& ws, const Species& sp, const doubl
   M.L = lines_dev(sp);
   M.mass = sp.mass;
   M.R0 = kCkms / c->dv_kms;   // 1 / mean ln spacing
-  // FP32: the same exact power-of-two scale as the direct cross-section
-  M.amp_scale = fp64 ? 1.0 : 18446744073709551616.0;
   M.dlng = dlng;
   M.nu = d_nu;
   M.ng = ng;
@@ -787,6 +785,14 @@ int exo::modit_opacity(exo_ctx* c, Workspace& ws, const Species& sp, const doubl
   modit_window(sp, nu_lo, nu_hi, &M.l0, &M.n_in);
   const ModitPlan q = modit_plan(M.n_in, ng, nlay, fp64);
   M.n_fft = q.n_fft;
+  // FP32: a layer's largest strength goes to ~2^amp_exp, so that n_fft times
+  // the sum of all strengths stays below 2^124
+  if (!fp64) {
+    int lf = 0, ll = 0;
+    while (((int64_t)1 << lf) < q.n_fft) ++lf;
+    while (((int64_t)1 << ll) < std::max<int64_t>(M.n_in, 1)) ++ll;
+    M.amp_exp = 124 - lf - ll;
+  }
   M.n_part = q.nbl;
   M.out64 = fp64;
   const size_t esz = fp64 ? sizeof(double) : sizeof(float);
@@ -801,7 +807,7 @@ int exo::modit_opacity(exo_ctx* c, Workspace& ws, const Species& sp, const doubl
   M.lay = (ModitLayer*)(base + q.off_lay);
   M.rec = base + q.off_rec;
   M.part = (double*)ws.mpart.p;
-  M.bins = (ModitBins*)((char*)ws.mpart.p + align256((size_t)q.nb * 2 * q.nbl * sizeof(double)));
+  M.bins = (ModitBins*)((char*)ws.mpart.p + align256((size_t)q.nb * 3 * q.nbl * sizeof(double)));
   M.rows0 = ws.mrows0.p;
   M.rows1 = ws.mrows1.p;
   for (int n0 = 0; n0 < nlay; n0 += q.nb) {

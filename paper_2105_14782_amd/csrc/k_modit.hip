@@ -5,7 +5,7 @@
 //
 //   1. per line: fractional grid index x (linear in ln nu between grid
 //      points), ln gamma~ with gamma~ = R0 gamma / nu (floored at 1e-3 beta~),
-//      strength S(T);
+//      strength S(T) (FP32: scaled by powers of two, below);
 //   2. width grid ln gamma~_k = lng0 + k d from the lines' range;
 //   3. lineshape density S_{jk}: every line split over the four neighbouring
 //      (j, k) nodes with linear weights, gathered per grid cell (the lines are
@@ -17,11 +17,20 @@
 //      exp(-2 pi^2 beta~^2 f^2 - 2 pi gamma~_k |f|) summed over k, inverse DFT;
 //   5. sigma(nu_i) = sigma(q_i) R0 / nu_i.
 // The DFTs are radix-4 / radix-2 Stockham passes through global memory.
+// FP32 range: strengths of one layer can span more decades than FP32 holds
+// (S(T) grows as exp(c2 E_low (1/T_ref - 1/T))), and every sum below is
+// bounded by n_fft times the sum of the strengths.  So each block of 256
+// lines stores S 2^(A - e_b), e_b = ceil(log2 of the block's largest S), the
+// density scales a line by 2^(e_b - e_n) with e_n the layer's largest e_b
+// (exact powers of two), and the output multiplies by 2^(e_n - A).  With
+// A = 126 - log2(n_fft) - log2(lines) - 2 no sum can overflow; strengths more
+// than ~2^(A + 126) below the layer's largest fall below FP32 and drop out.
 // Every kernel takes a batch of layers in blockIdx.y (the line positions x
 // are common to all of them); used as an opacity, the output of layer n is
 // col_n sigma, clamped at zero where the Nyquist-truncated transform rings
 // below it next to lines whose Doppler width is about one grid step.
 #include <algorithm>
+#include <type_traits>
 #include <utility>
 
 #include "exo_device.h"
@@ -109,36 +118,41 @@ __global__ __launch_bounds__(256) void k_modit_cells(const double* __restrict__ 
 }
 
 // -------------------------------------------------------------------------- 2
-__device__ inline void block_minmax256(double& mn, double& mx, double* sm) {
+// min/max of ln gamma~ and max of the strength exponent over a block of 256
+__device__ inline void block_reduce3_256(double& mn, double& mx, double& ym, double* sm) {
   for (int o = 32; o > 0; o >>= 1) {
     mn = fmin(mn, __shfl_xor(mn, o));
     mx = fmax(mx, __shfl_xor(mx, o));
+    ym = fmax(ym, __shfl_xor(ym, o));
   }
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   __syncthreads();
   if (lane == 0) {
     sm[w] = mn;
     sm[4 + w] = mx;
+    sm[8 + w] = ym;
   }
   __syncthreads();
   mn = fmin(fmin(sm[0], sm[1]), fmin(sm[2], sm[3]));
   mx = fmax(fmax(sm[4], sm[5]), fmax(sm[6], sm[7]));
+  ym = fmax(fmax(sm[8], sm[9]), fmax(sm[10], sm[11]));
 }
 
-// {ln gamma~, S amp_scale} of one line at one layer.  FP64: the formulas as
+// {ln gamma~, S} of one line at one layer.  FP64: the formulas as
 // written.  FP32 records: ln S = a - c2 E / T - ln q_r + ln(1 - e^{-c2 nu / T})
-// with a = ln(S0 amp_scale / (1 - e^{-c2 nu / T_ref})) + c2 E / T_ref; the
-// argument a - c2 E / T (whose terms nearly cancel) in FP64, its exponential
-// as 2^m exp2(y - m) with the integer m exact and exp2 in FP32 (relative
-// error ~1e-7), the remaining factors and ln gamma~ in FP32.
+// with a = ln(S0 / (1 - e^{-c2 nu / T_ref})) + c2 E / T_ref; y = log2 of the
+// first three terms (whose parts nearly cancel) in FP64 (modit_log2core),
+// then 2^(y + shift) as 2^m exp2(y + shift - m) with the integer m exact and
+// exp2 in FP32 (relative error ~1e-7), the remaining factor and ln gamma~ in
+// FP32.
 struct ModitLine {
   double nu, S0, E, alpha, nt, gnat;
-  double sfac;      // FP64 form: S0 amp_scale / (1 - e^{-c2 nu / T_ref})
+  double sfac;      // FP64 form: S0 / (1 - e^{-c2 nu / T_ref})
   double a, c2E;    // FP32 form
   float c2nu, R0nu;
 };
 
-__device__ inline ModitLine modit_line(const LinesDev& L, int64_t l, double R0, double amp_scale) {
+__device__ inline ModitLine modit_line(const LinesDev& L, int64_t l, double R0) {
   ModitLine m;
   m.nu = L.nu_c[l];
   m.S0 = L.S0[l];
@@ -147,7 +161,7 @@ __device__ inline ModitLine modit_line(const LinesDev& L, int64_t l, double R0, 
   m.nt = L.n_texp[l];
   m.gnat = L.gamma_nat ? L.gamma_nat[l] : 0.0;
   const double eR = exp(-kC2 * m.nu / kTref);
-  m.sfac = m.S0 * amp_scale / (1.0 - eR);
+  m.sfac = m.S0 / (1.0 - eR);
   m.c2E = kC2 * m.E;
   m.a = log(m.sfac) + m.c2E / kTref;
   m.c2nu = (float)(kC2 * m.nu);
@@ -155,70 +169,91 @@ __device__ inline ModitLine modit_line(const LinesDev& L, int64_t l, double R0, 
   return m;
 }
 
-template <typename R>
-__device__ inline typename Pair<R>::T modit_line_layer(const ModitLine& m, const ModitLayer& c, double R0);
+// log2 of S(T) without the stimulated-emission factor (<= 1); -2000 for S0 = 0
+__device__ inline double modit_log2core(const ModitLine& m, const ModitLayer& c) {
+  return fmax((fma(-m.c2E, c.invT, m.a) + c.ln_inv_qr) * 1.4426950408889634, -2000.0);
+}
 
-template <>
-__device__ inline double2 modit_line_layer<double>(const ModitLine& m, const ModitLayer& c, double R0) {
+__device__ inline double2 modit_line_layer64(const ModitLine& m, const ModitLayer& c, double R0) {
   const double eT = exp(-kC2 * m.nu * c.invT);
   const double S = m.sfac * c.inv_qr * exp(-m.c2E * (c.invT - 1.0 / kTref)) * (1.0 - eT);
   const double g = m.alpha * exp(-m.nt * c.lnTr) * c.P + m.gnat;
   return make_double2(fmax(log(R0 * g / m.nu), c.lng_floor), S);
 }
 
-template <>
-__device__ inline float2 modit_line_layer<float>(const ModitLine& m, const ModitLayer& c, double R0) {
-  // log2 of the core, clamped so that m stays a small integer (S0 = 0 gives
-  // y = -inf: the core is then 2^-200, zero in FP32)
-  const double y = fmin(fmax((fma(-m.c2E, c.invT, m.a) + c.ln_inv_qr) * 1.4426950408889634, -200.0), 200.0);
+__device__ inline float modit_lng32(const ModitLine& m, const ModitLayer& c) {
+  const float g = (float)m.alpha * expf(-(float)m.nt * (float)c.lnTr) * (float)c.P + (float)m.gnat;
+  return fmaxf(logf(m.R0nu * g), (float)c.lng_floor);
+}
+
+// S 2^shift from y = modit_log2core, clamped so that the exponent stays a
+// small integer (S0 = 0 and strengths below 2^-200 of the scale give
+// 2^-200, zero in FP32)
+__device__ inline float modit_strength32(const ModitLine& m, const ModitLayer& c, double y_raw, double shift) {
+  const double y = fmin(fmax(y_raw + shift, -200.0), 200.0);
   const double mi = rint(y);
   const float core = ldexpf(exp2f((float)(y - mi)), (int)mi);
-  const float invT = (float)c.invT;
-  const float S = core * (1.0f - expf(-m.c2nu * invT));
-  const float g = (float)m.alpha * expf(-(float)m.nt * (float)c.lnTr) * (float)c.P + (float)m.gnat;
-  return make_float2(fmaxf(logf(m.R0nu * g), (float)c.lng_floor), S);
+  return core * (1.0f - expf(-m.c2nu * (float)c.invT));
 }
 
 // One thread per line, looping over the layers of the launch (the line's
-// parameters are read once): rec[n][i] = {ln gamma~, S(T_n) amp_scale} with
-// gamma~ = R0 gamma / nu_l floored at 1e-3 beta~, and per block the min/max
-// of ln gamma~ (as stored) into part[n][2 blockIdx.x ..].
+// parameters are read once): rec[n][i] = {ln gamma~, S(T_n)} with gamma~ =
+// R0 gamma / nu_l floored at 1e-3 beta~, and per block the min/max of
+// ln gamma~ (as stored) and the block's strength exponent into
+// part[n][3 blockIdx.x ..].  FP32: S is stored as S 2^(amp_exp - e_b) with
+// e_b = ceil(log2 of the block's largest S) (at least -1000); FP64: as is,
+// e_b = 0.
 template <typename R>
 __global__ __launch_bounds__(256) void k_modit_lines(LinesDev L, const ModitLayer* __restrict__ lay, int nl,
-                                                     double R0, double amp_scale, int64_t l0, int64_t n_in,
+                                                     double R0, int amp_exp, int64_t l0, int64_t n_in,
                                                      typename Pair<R>::T* __restrict__ rec,
                                                      double* __restrict__ part, int64_t n_part) {
   using P2 = typename Pair<R>::T;
-  __shared__ double sm[8];
+  constexpr bool kF32 = std::is_same<R, float>::value;
+  __shared__ double sm[12];
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const bool ok = i < n_in;
-  const ModitLine m = modit_line(L, l0 + (ok ? i : 0), R0, amp_scale);
+  const ModitLine m = modit_line(L, l0 + (ok ? i : 0), R0);
   for (int n = 0; n < nl; ++n) {
-    const P2 v = modit_line_layer<R>(m, lay[n], R0);
-    double mn = INFINITY, mx = -INFINITY;
-    if (ok) {
-      rec[(int64_t)n * n_in + i] = v;
-      mn = mx = (double)v.x;
+    const ModitLayer c = lay[n];
+    P2 v;
+    double y = 0.0;
+    if constexpr (kF32) {
+      v.x = modit_lng32(m, c);
+      y = modit_log2core(m, c);
+    } else {
+      v = modit_line_layer64(m, c, R0);
     }
-    block_minmax256(mn, mx, sm);
+    double mn = INFINITY, mx = -INFINITY, ym = -INFINITY;
+    if (ok) {
+      mn = mx = (double)v.x;
+      ym = y;
+    }
+    block_reduce3_256(mn, mx, ym, sm);
+    const double eb = kF32 ? fmax(ceil(ym), -1000.0) : 0.0;
+    if constexpr (kF32) v.y = modit_strength32(m, c, y, (double)amp_exp - eb);
+    if (ok) rec[(int64_t)n * n_in + i] = v;
     if (threadIdx.x == 0) {
-      part[(int64_t)n * 2 * n_part + 2 * blockIdx.x] = mn;
-      part[(int64_t)n * 2 * n_part + 2 * blockIdx.x + 1] = mx;
+      part[(int64_t)n * 3 * n_part + 3 * blockIdx.x] = mn;
+      part[(int64_t)n * 3 * n_part + 3 * blockIdx.x + 1] = mx;
+      part[(int64_t)n * 3 * n_part + 3 * blockIdx.x + 2] = eb;
     }
   }
 }
 
 // K = floor(range / d) + 2, at most kModitMaxBins (the step widens to range / (max - 2))
+// and the layer's strength exponent, the largest block exponent
 __global__ __launch_bounds__(256) void k_modit_bins(const double* __restrict__ part, int64_t nb,
                                                     double dlng, ModitBins* __restrict__ bins) {
-  __shared__ double sm[8];
-  part += (int64_t)blockIdx.y * 2 * nb;
-  double mn = INFINITY, mx = -INFINITY;
+  __shared__ double sm[12];
+  part += (int64_t)blockIdx.y * 3 * nb;
+  double mn = INFINITY, mx = -INFINITY, ym = -INFINITY;
   for (int64_t b = threadIdx.x; b < nb; b += 256) {
-    mn = fmin(mn, part[2 * b]);
-    mx = fmax(mx, part[2 * b + 1]);
+    mn = fmin(mn, part[3 * b]);
+    mx = fmax(mx, part[3 * b + 1]);
+    ym = fmax(ym, part[3 * b + 2]);
   }
-  block_minmax256(mn, mx, sm);
+  block_reduce3_256(mn, mx, ym, sm);
   if (threadIdx.x == 0) {
     // in doubles, so that a non-finite range still ends with 2 <= K <= max
     const double range = mx - mn;
@@ -231,6 +266,7 @@ __global__ __launch_bounds__(256) void k_modit_bins(const double* __restrict__ p
     bins[blockIdx.y].lng0 = mn;
     bins[blockIdx.y].d = d;
     bins[blockIdx.y].K = (int)fmax(2.0, fmin(Kd, (double)kModitMaxBins));
+    bins[blockIdx.y].yexp = (int)ym;
   }
 }
 
@@ -244,12 +280,20 @@ __global__ __launch_bounds__(256) void k_modit_bins(const double* __restrict__ p
 // then sums its G columns in lane order: a fixed summation order.  The first
 // ceil(ng G / 256) blocks do the cells; the rest write the zero padding
 // j = ng .. n_fft - 1.
+// FP32: the line's strength times 2^(e_b - e_n) (e_b of its block of 256,
+// e_n of the layer), an exact power of two <= 1
 template <typename R>
-__device__ inline void lsd_add(R (*acc)[256], typename Pair<R>::T r, R w, R lng0, R dinv, int K) {
+__device__ inline R lsd_strength(typename Pair<R>::T r, const double* __restrict__ part, int64_t l, int yexp) {
+  if constexpr (std::is_same<R, float>::value) return ldexpf(r.y, (int)part[3 * (l >> 8) + 2] - yexp);
+  else return r.y;
+}
+
+template <typename R>
+__device__ inline void lsd_add(R (*acc)[256], typename Pair<R>::T r, R S, R w, R lng0, R dinv, int K) {
   const R t = (r.x - lng0) * dinv;
   const int k0 = min(max((int)floor(t), 0), K - 2);   // 0 <= t by construction; clamp all the same
   const R fk = t - (R)k0;
-  const R sw = r.y * w;
+  const R sw = S * w;
   acc[k0][threadIdx.x] += sw * ((R)1 - fk);
   acc[k0 + 1][threadIdx.x] += sw * fk;
 }
@@ -259,11 +303,13 @@ __global__ __launch_bounds__(256) void k_modit_lsd(const int64_t* __restrict__ c
                                                    int lgG, const R* __restrict__ f,
                                                    const typename Pair<R>::T* __restrict__ rec, int64_t n_in,
                                                    const ModitBins* __restrict__ bins,
+                                                   const double* __restrict__ part, int64_t n_part,
                                                    typename Cplx<R>::T* __restrict__ rows) {
   using C = typename Cplx<R>::T;
   __shared__ R acc[kModitMaxBins][256];
   const int n = blockIdx.y;
   rec += (int64_t)n * n_in;
+  part += (int64_t)n * 3 * n_part;
   rows += (int64_t)n * kModitRows * n_fft;
   const ModitBins b = bins[n];
   const int Kp = (b.K + 1) / 2;
@@ -286,8 +332,14 @@ __global__ __launch_bounds__(256) void k_modit_lsd(const int64_t* __restrict__ c
   if (j < ng) {
     const int64_t a1 = cell[j], a2 = cell[j + 1];
     const int64_t a0 = j > 0 ? cell[j - 1] : a1;
-    for (int64_t l = a0 + g; l < a1; l += G) lsd_add<R>(acc, rec[l], f[l], lng0, dinv, b.K);
-    for (int64_t l = a1 + g; l < a2; l += G) lsd_add<R>(acc, rec[l], (R)1 - f[l], lng0, dinv, b.K);
+    for (int64_t l = a0 + g; l < a1; l += G) {
+      const typename Pair<R>::T r = rec[l];
+      lsd_add<R>(acc, r, lsd_strength<R>(r, part, l, b.yexp), f[l], lng0, dinv, b.K);
+    }
+    for (int64_t l = a1 + g; l < a2; l += G) {
+      const typename Pair<R>::T r = rec[l];
+      lsd_add<R>(acc, r, lsd_strength<R>(r, part, l, b.yexp), (R)1 - f[l], lng0, dinv, b.K);
+    }
   }
   __syncthreads();
   if (j < ng) {
@@ -571,18 +623,23 @@ __global__ __launch_bounds__(256) void k_modit_product(const typename Cplx<R>::T
 }
 
 // -------------------------------------------------------------------------- 5
-// out[n][i] = Re Z_n[i] / n_fft * R0 / nu_i * scale, times col[n] and clamped
-// at zero when col is given
+// out[n][i] = Re Z_n[i] / n_fft * R0 / nu_i * 2^(e_n - amp_exp), times col[n]
+// and clamped at zero when col is given (and, for FP32 optical depths, at
+// 1e30: a layer that deep is opaque either way)
 template <typename R, typename TO>
 __global__ __launch_bounds__(256) void k_modit_out(const typename Cplx<R>::T* __restrict__ Z,
                                                    int64_t ng, int64_t n_fft, double R0,
-                                                   const double* __restrict__ nu, double scale,
+                                                   const double* __restrict__ nu, int amp_exp,
+                                                   const ModitBins* __restrict__ bins,
                                                    const double* __restrict__ col, TO* __restrict__ out) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i >= ng) return;
   const int n = blockIdx.y;
-  double v = (double)Z[(int64_t)n * n_fft + i].x / (double)n_fft * R0 / nu[i] * scale;
-  if (col) v = fmax(v * col[n], 0.0);
+  double v = ldexp((double)Z[(int64_t)n * n_fft + i].x / (double)n_fft * R0 / nu[i], bins[n].yexp - amp_exp);
+  if (col) {
+    v = fmax(v * col[n], 0.0);
+    if (sizeof(TO) == 4) v = fmin(v, 1e30);
+  }
   out[(int64_t)n * ng + i] = (TO)v;
 }
 
@@ -639,14 +696,14 @@ static hipError_t modit_impl(const ModitArgs& M, hipStream_t st) {
   hipLaunchKernelGGL(k_modit_layers, dim3(nblk(M.nl)), dim3(256), 0, st, M.T, M.P, M.nl, M.mass, M.R0,
                      M.L.qr_kind, M.L.qr_params, M.L.n_qr, M.lay);
   hipLaunchKernelGGL(k_modit_lines<R>, dim3((unsigned)nbl), dim3(256), 0, st, M.L, (const ModitLayer*)M.lay,
-                     M.nl, M.R0, M.amp_scale, M.l0, M.n_in, (P2*)M.rec, M.part, M.n_part);
+                     M.nl, M.R0, M.amp_exp, M.l0, M.n_in, (P2*)M.rec, M.part, M.n_part);
   hipLaunchKernelGGL(k_modit_bins, dim3(1, nl), dim3(256), 0, st, M.part, M.n_part, M.dlng, M.bins);
   // lanes per cell: about a quarter of the mean lines per cell, a power of two in [1, 64]
   int lgG = 0;
   while (lgG < 6 && ((int64_t)4 << lgG) * 2 <= M.n_in / M.ng) ++lgG;
   const int64_t lsd_blocks = ((M.ng << lgG) + 255) / 256 + nblk(M.n_fft - M.ng);
   hipLaunchKernelGGL(k_modit_lsd<R>, dim3((unsigned)lsd_blocks, nl), dim3(256), 0, st, M.cell, M.ng, M.n_fft,
-                     lgG, (const R*)M.f, (const P2*)M.rec, M.n_in, M.bins, (C*)M.rows0);
+                     lgG, (const R*)M.f, (const P2*)M.rec, M.n_in, M.bins, M.part, M.n_part, (C*)M.rows0);
   void* X = fft_rows<R>(M.rows0, M.rows1, M.n_fft, M.nl * kModitRows, M.bins, st);
   void* Y = X == M.rows0 ? M.rows1 : M.rows0;
   hipLaunchKernelGGL(k_modit_product<R>, dim3(nblk(M.n_fft), nl), dim3(256), 0, st, (const C*)X, M.n_fft,
@@ -654,10 +711,10 @@ static hipError_t modit_impl(const ModitArgs& M, hipStream_t st) {
   void* Z = fft_rows<R>(Y, X, M.n_fft, M.nl, nullptr, st);
   if (M.out64)
     hipLaunchKernelGGL((k_modit_out<R, double>), dim3(nblk(M.ng), nl), dim3(256), 0, st, (const C*)Z, M.ng,
-                       M.n_fft, M.R0, M.nu, 1.0 / M.amp_scale, M.col, (double*)M.out);
+                       M.n_fft, M.R0, M.nu, M.amp_exp, M.bins, M.col, (double*)M.out);
   else
     hipLaunchKernelGGL((k_modit_out<R, float>), dim3(nblk(M.ng), nl), dim3(256), 0, st, (const C*)Z, M.ng,
-                       M.n_fft, M.R0, M.nu, 1.0 / M.amp_scale, M.col, (float*)M.out);
+                       M.n_fft, M.R0, M.nu, M.amp_exp, M.bins, M.col, (float*)M.out);
   return hipGetLastError();
 }
 

@@ -153,3 +153,34 @@ def test_modit_errors(exo):
     with pytest.raises(pkg.ExoError) as e:
         c.cross_section_modit(1, 1000.0, 1.0)
     assert e.value.code == pkg.EXO_ENOTSET
+
+
+def test_modit_full_config3_against_oracle(exo):
+    """MODIT on the full throughput workload (1e7 lines over 4340-4796 cm^-1,
+    100,000-point grid at R0 = 1e6, 1 bar) against the MODIT oracle on every
+    grid point.  Its strengths, S0 <= 1e-18 at 296 K with E_low ~ Exp(3000),
+    reach 1e36 cm/molecule at 700 K and 1e54 at 1300 K: at 700 K both forms
+    match the oracle; at 1300 K every cross-section exceeds the FP32 range,
+    and the FP32 form must return infinities there (IEEE overflow), never
+    NaN, while FP64 still matches."""
+    wl = synth.make_config(3, "full")
+    c = exo.Context(0)
+    c.set_lines(0, wl.lines[0])
+    c.set_grid(wl.nu)
+    for T in (700.0, 1300.0):
+        ref = M.modit_cross_section(wl.lines[0], T, 1.0, wl.nu)
+        got64 = c.cross_section_modit(0, T, 1.0, "fp64", 0.1).cpu().numpy()
+        got32 = c.cross_section_modit(0, T, 1.0, "fp32", 0.1).cpu().double().numpy()
+        err64 = _err(got64, ref)
+        assert err64 < 1e-10
+        if ref.max() < 3.4e38:
+            err32 = _err(got32, ref)
+            _say(f"  MODIT 1e7 lines x 1e5 points, {T:.0f} K: max err / max FP64 {err64:.2e}, FP32 {err32:.2e}")
+            assert err32 < 1e-5
+        else:
+            assert ref.min() > 3.4e38
+            _say(f"  MODIT 1e7 lines x 1e5 points, {T:.0f} K: max err / max FP64 {err64:.2e}; FP32 range "
+                 f"exceeded (sigma >= {ref.min():.1e}): {int(np.isinf(got32).sum())} of {got32.size} infinite")
+            assert not np.isnan(got32).any()
+            assert np.isinf(got32).all()
+    c.close()
