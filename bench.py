@@ -58,6 +58,8 @@ def parse():
     ap.add_argument("--serve-requests", type=int, default=1000,
                     help="requests of the Poisson serving run (0: skip)")
     ap.add_argument("--serve-streams", type=int, default=4, help="serving slots (1..16)")
+    ap.add_argument("--serve-policy", nargs="+", default=["fifo", "shortest"], choices=["fifo", "shortest"],
+                    help="admission orders to measure, each at every load")
     ap.add_argument("--serve-capacity-requests", type=int, default=200,
                     help="requests of the closed-loop capacity run that sets the arrival rate")
     ap.add_argument("--no-config3", action="store_true", help="skip the full config-3 direct-sum spectrum")
@@ -606,15 +608,17 @@ def modit_emission_bench(wl=None, reps=5):
 SERVE_MARGIN = 260   # output margin (points) at R0 = 1e6: rotation + RV + 6-sigma IP reach < 200
 
 
-def serving_bench(n_req, loads=(0.9,), n_streams=4, budget=48 << 30, n_cap=200):
+def serving_bench(n_req, loads=(0.9,), n_streams=4, budget=48 << 30, n_cap=200, policies=("fifo",)):
     """Continuous batching on a stream shaped like the serving configuration:
     16 resident lists (1e3-1e6 lines, 3900-5100 cm^-1), windows of 2e3-1e5
     points on an R0 = 1e6 grid, 50-200 layers, HMC-like parameter walk.
     Capacity is measured closed-loop first (n_cap requests submitted at
     once); then n_req Poisson arrivals at each load x capacity give the
     latency distribution, from each request's scheduled arrival to its
-    spectrum on the device.  The top-level latency fields are those of the
-    first load."""
+    spectrum on the device, for each admission policy ("fifo": arrival
+    order; "shortest": fewest evaluations first, a request passed over at
+    most 16 times; the same arrival sequence for both).  The top-level
+    latency fields are those of the first policy at the first load."""
     import torch
     import synth
     from paper_2105_14782_amd import api, serve
@@ -645,19 +649,22 @@ def serving_bench(n_req, loads=(0.9,), n_streams=4, budget=48 << 30, n_cap=200):
     evals = lambda reqs: sum((lists[a.species[0]].n + lists[a.species[1]].n) * a.grid_len * len(a.P_bar)
                              for a, _ in reqs)
     runs = []
-    for rho in loads:
-        rate = rho * cap["spectra_per_s"]
-        reqs = synth.serving_requests(n_req, rate, nu_master=nu)
-        arr = np.array([q.arrival_s for q in reqs])
-        st0 = srv.stats()
-        res = serve.run_stream(srv, args(reqs), arr, progress=max(250, n_req // 20))
-        st1 = srv.stats()
-        lat = res["latency_s"]
-        runs.append({"load": rho, "arrival_rate_hz": rate, "spectra_per_s": res["spectra_per_s"],
-                     "p50_ms": res["p50_ms"], "p99_ms": res["p99_ms"],
-                     "p90_ms": float(np.percentile(lat, 90) * 1e3), "max_ms": float(lat.max() * 1e3),
-                     "bypasses": st1["bypasses"] - st0["bypasses"]})
-        print(f"serving: load {rho}: p50 {res['p50_ms']:.0f} ms, p99 {res['p99_ms']:.0f} ms", file=sys.stderr, flush=True)
+    for policy in policies:
+        srv.set_policy(policy, 16)
+        for rho in loads:
+            rate = rho * cap["spectra_per_s"]
+            reqs = synth.serving_requests(n_req, rate, nu_master=nu)
+            arr = np.array([q.arrival_s for q in reqs])
+            st0 = srv.stats()
+            res = serve.run_stream(srv, args(reqs), arr, progress=max(250, n_req // 20))
+            st1 = srv.stats()
+            lat = res["latency_s"]
+            runs.append({"policy": policy, "load": rho, "arrival_rate_hz": rate,
+                         "spectra_per_s": res["spectra_per_s"], "p50_ms": res["p50_ms"], "p99_ms": res["p99_ms"],
+                         "p90_ms": float(np.percentile(lat, 90) * 1e3), "max_ms": float(lat.max() * 1e3),
+                         "bypasses": st1["bypasses"] - st0["bypasses"]})
+            print(f"serving: {policy}, load {rho}: p50 {res['p50_ms']:.0f} ms, p99 {res['p99_ms']:.0f} ms",
+                  file=sys.stderr, flush=True)
     st = srv.stats()
     srv.close()
     ctx.close()
@@ -710,7 +717,8 @@ def main():
         return
     if args.serving_only:
         print(json.dumps({"serving": serving_bench(args.serve_requests, args.serve_load, n_streams=args.serve_streams,
-                                                   n_cap=args.serve_capacity_requests)}), flush=True)
+                                                   n_cap=args.serve_capacity_requests,
+                                                   policies=args.serve_policy)}), flush=True)
         return
     import torch
     import synth
@@ -891,7 +899,7 @@ def main():
     ctx.close()
     if args.serve_requests > 0:
         out["serving"] = serving_bench(args.serve_requests, args.serve_load, n_streams=args.serve_streams,
-                                       n_cap=args.serve_capacity_requests)
+                                       n_cap=args.serve_capacity_requests, policies=args.serve_policy)
     wl3 = None
     if not args.no_config3 or not args.no_modit:
         wl3 = synth.make_config(3, "full")

@@ -10,12 +10,16 @@
  * Model of operation:
  *   - Requests are queued in arrival order (exo_server_submit copies every
  *     host array it needs).
- *   - A dispatcher thread admits the head of the queue as soon as a stream
+ *   - A dispatcher thread admits the preferred request as soon as a stream
  *     slot is free AND a contiguous region of the device memory budget large
- *     enough for the request's workspace is free (first fit).  While the
- *     head waits for memory, later requests (up to 64 places behind it) that
- *     fit may go first, at most 8 of them per waiting head; after that the
- *     head is admitted before any other.  The budget is one device
+ *     enough for the request's workspace is free (first fit).  The preferred
+ *     request is the head of the queue (EXO_SERVE_FIFO, the default), or
+ *     with EXO_SERVE_SHORTEST_FIRST the one with the fewest line x grid
+ *     point x layer evaluations among the first 64 queued, unless one of
+ *     those has been passed over max_passes times (then the earliest such).
+ *     While the preferred request waits for memory, other requests (among
+ *     the first 64) that fit may go first, at most 8 of them per waiting
+ *     request; after that it is admitted before any other.  The budget is one device
  *     allocation made at creation; nothing is allocated while serving.
  *     Admitted requests run concurrently on separate HIP streams (default
  *     priority) and overlap on the device; a finished request frees its slot
@@ -36,6 +40,11 @@ extern "C" {
 
 typedef struct exo_server exo_server;
 
+typedef enum {
+  EXO_SERVE_FIFO = 0,           /* arrival order                                  */
+  EXO_SERVE_SHORTEST_FIRST = 1  /* fewest evaluations first, passes bounded      */
+} exo_serve_policy;
+
 typedef struct {
   int64_t submitted, admitted, completed, failed, rejected;
   int64_t queued, in_flight;
@@ -48,6 +57,12 @@ typedef struct {
  * device-memory budget of `mem_budget_bytes` for request workspaces
  * (allocated once, here).  Errors: EXO_EINVAL, EXO_ENOMEM, EXO_EDEVICE. */
 int exo_server_create(exo_ctx* ctx, int n_streams, size_t mem_budget_bytes, exo_server** out);
+
+/* Admission order (see above) for the requests admitted from now on.
+ * max_passes (1..2^20, EXO_SERVE_SHORTEST_FIRST): how often a request may be
+ * passed over by later arrivals before it is preferred; it bounds the extra
+ * wait of a large request.  Errors: EXO_EINVAL. */
+int exo_server_set_policy(exo_server* srv, int policy, int max_passes);
 
 /* Drain all queued and running requests, then release the server. */
 int exo_server_destroy(exo_server* srv);

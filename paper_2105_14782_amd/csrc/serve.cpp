@@ -48,7 +48,9 @@ struct Request {
   size_t bytes = 0;
   size_t region = 0;
   int slot = -1;
-  int bypassed = 0;   // later requests admitted while this one waited at the head
+  int bypassed = 0;   // later requests admitted while this one waited at the head for memory
+  int passed = 0;     // shortest first: later requests admitted ahead of this one
+  double work = 0;    // shortest first: line x point x layer evaluations
   double t_arrival = 0, t_admit = 0, t_done = 0;   // CLOCK_MONOTONIC seconds
   int status = EXO_OK;
   std::string msg;
@@ -120,6 +122,8 @@ struct exo_server {
   int64_t next_id = 1;
   int64_t submitted = 0, admitted = 0, completed = 0, failed = 0, rejected = 0, in_flight = 0;
   int64_t peak_in_flight = 0, bypasses = 0;
+  int policy = EXO_SERVE_FIFO;
+  int max_passes = 16;
   bool stop = false;
   std::thread dispatcher;
 };
@@ -142,6 +146,21 @@ void on_stream_done(void* p) {
   }
   a->srv->cv.notify_all();
   delete a;
+}
+
+// The request admission prefers: the queue head (FIFO), or (shortest first)
+// the earliest request of the look-ahead window that has been passed over
+// max_passes times, else the window's smallest request (earliest on ties).
+std::deque<std::shared_ptr<Request>>::iterator preferred(exo_server* s) {
+  auto it = s->queue.begin();
+  if (s->policy == EXO_SERVE_FIFO) return it;
+  const auto end = s->queue.size() > kBypassWindow ? s->queue.begin() + kBypassWindow : s->queue.end();
+  auto best = it;
+  for (auto q = it; q != end; ++q) {
+    if ((*q)->passed >= s->max_passes) return q;
+    if ((*q)->work < (*best)->work) best = q;
+  }
+  return best;
 }
 
 int free_slot(exo_server* s) {
@@ -174,25 +193,28 @@ void run_dispatcher(exo_server* s) {
     s->finished.clear();
     if (retired) s->done_cv.notify_all();
     if (s->stop && s->queue.empty() && s->in_flight == 0) break;
-    // admit in arrival order while a slot and a memory region are free; a
-    // head that waits for memory lets up to kMaxBypass later requests that
-    // fit go first (looking kBypassWindow requests ahead)
+    // admit while a slot and a memory region are free, the preferred request
+    // first (the head in arrival order, or by the shortest-first rule); one
+    // that waits for memory lets up to kMaxBypass other requests that fit go
+    // first (looking kBypassWindow requests ahead)
     bool admitted_any = false;
     while (!s->queue.empty()) {
       const int si = free_slot(s);
       if (si < 0) break;
       size_t off;
-      auto pick = s->queue.begin();
+      auto pick = preferred(s);
       if (!s->regions.alloc((*pick)->bytes, &off)) {
         Request* head = pick->get();
         if (head->bypassed >= kMaxBypass) break;  // wait for memory
         const auto end = s->queue.size() > kBypassWindow ? s->queue.begin() + kBypassWindow : s->queue.end();
-        for (++pick; pick != end; ++pick)
-          if (s->regions.alloc((*pick)->bytes, &off)) break;
+        for (pick = s->queue.begin(); pick != end; ++pick)
+          if (pick->get() != head && s->regions.alloc((*pick)->bytes, &off)) break;
         if (pick == end) break;  // nothing fits: wait for memory
         ++head->bypassed;
         ++s->bypasses;
       }
+      // every earlier arrival still queued has been passed over once more
+      for (auto q = s->queue.begin(); q != pick; ++q) ++(*q)->passed;
       std::shared_ptr<Request> r = *pick;
       s->queue.erase(pick);
       r->region = off;
@@ -263,6 +285,20 @@ extern "C" int exo_server_create(exo_ctx* ctx, int n_streams, size_t budget, exo
   return EXO_OK;
 }
 
+extern "C" int exo_server_set_policy(exo_server* s, int policy, int max_passes) {
+  if (!s) return set_err(EXO_EINVAL, "NULL server");
+  if (policy != EXO_SERVE_FIFO && policy != EXO_SERVE_SHORTEST_FIRST)
+    return set_err(EXO_EINVAL, "unknown admission policy %d", policy);
+  if (max_passes < 1 || max_passes > (1 << 20)) return set_err(EXO_EINVAL, "max_passes must be in 1..2^20");
+  {
+    std::lock_guard<std::mutex> g(s->mu);
+    s->policy = policy;
+    s->max_passes = max_passes;
+  }
+  s->cv.notify_all();
+  return EXO_OK;
+}
+
 extern "C" int exo_server_destroy(exo_server* s) {
   if (!s) return EXO_OK;
   {
@@ -306,6 +342,8 @@ extern "C" int exo_server_submit(exo_server* s, const exo_atmos* a, const exo_re
   if (bytes == 0) return set_err(EXO_EINVAL, "invalid request");
   auto q = std::make_shared<Request>();
   q->bytes = (bytes + kAlign - 1) & ~(kAlign - 1);
+  for (int m = 0; m < a->n_species; ++m) q->work += (double)s->ctx->sp[a->species[m]].n;
+  q->work *= (double)gl * (double)a->n_layers;
   if (q->bytes > s->cap) {
     std::lock_guard<std::mutex> g(s->mu);
     ++s->rejected;

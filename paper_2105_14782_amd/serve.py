@@ -34,6 +34,7 @@ def _bind(lib):
     sig = {
         "exo_server_create": ([V, I, ctypes.c_size_t, ctypes.POINTER(V)], I),
         "exo_server_destroy": ([V], I),
+        "exo_server_set_policy": ([V, I, I], I),
         "exo_server_submit": ([V, ctypes.POINTER(L.ExoAtmos), ctypes.POINTER(L.ExoResponse), I, V, D,
                                ctypes.POINTER(I64)], I),
         "exo_server_wait": ([V, I64, D, ctypes.POINTER(D), ctypes.POINTER(D)], I),
@@ -78,6 +79,13 @@ class Server:
             self.close()
         except Exception:
             pass
+
+    POLICIES = {"fifo": 0, "shortest": 1}
+
+    def set_policy(self, policy: str = "fifo", max_passes: int = 16):
+        """Admission order: "fifo" (arrival order) or "shortest" (fewest
+        evaluations first; a request is passed over at most max_passes times)."""
+        L.check(self._lib.exo_server_set_policy(self._h, self.POLICIES[policy], int(max_passes)))
 
     def workspace_bytes(self, atmos: Atmos, response: Optional[Response], precision="fp32") -> int:
         a, keep = atmos.to_c()

@@ -248,3 +248,53 @@ def test_full_scale_serving_requests_against_oracle():
               f"{q.n_layers} layers: max rel err {err:.2e} (oracle {time.monotonic() - t:.1f} s)", flush=True)
         assert err < 1e-4
     ctx.close()
+
+
+def test_shortest_first_policy_order_and_pass_bound(setup):
+    """With the shortest-first policy and max_passes = 1 on one slot: while a
+    large request runs, a second large one and three small ones queue.  The
+    admissions follow the rule (the fewest evaluations first, but a request
+    passed over once is preferred next), which puts the large one second,
+    not last; results are bitwise those of the synchronous API."""
+    import time
+    from dataclasses import replace
+    api, ctx, lists, nu, reqs = setup
+    from paper_2105_14782_amd import serve
+    big = replace(reqs[0], grid_begin=2000, grid_len=150000, n_layers=200)
+    qs = [replace(big, theta=reqs[1].theta)] + [replace(q, grid_len=n, n_layers=20)
+                                                for q, n in zip(reqs[2:5], (3000, 2000, 4000))]
+    args = [_req_args(api, nu, lists, q) for q in [big] + qs]
+    work = [(lists[q.species[0]].n + lists[q.species[1]].n) * q.grid_len * q.n_layers for q in qs]
+    # the rule, applied to the four queued requests (arrival order = list order)
+    queue, passed, expect = list(range(4)), [0] * 4, []
+    while queue:
+        forced = [k for k in queue if passed[k] >= 1]
+        pick = forced[0] if forced else min(queue, key=lambda k: (work[k], k))
+        for k in queue[:queue.index(pick)]:
+            passed[k] += 1
+        queue.remove(pick)
+        expect.append(pick + 1)
+    srv = serve.Server(ctx, n_streams=1, mem_budget_bytes=8 << 30)
+    srv.set_policy("shortest", max_passes=1)
+    t0 = time.monotonic()
+    tickets = [srv.submit(*args[0], arrival_s=t0)]
+    for _ in range(2000):            # the first request holds the slot before the others queue
+        if srv.stats()["admitted"] >= 1:
+            break
+        time.sleep(0.001)
+    tickets += [srv.submit(a, r, arrival_s=t0) for a, r in args[1:]]
+    res = [srv.wait(t) for t in tickets]
+    st = srv.stats()
+    srv.close()
+    order = [int(k) for k in np.argsort([r.queue_s for r in res], kind="stable")]
+    print(f"  work {work}; admission order {order}, expected {[0] + expect}", flush=True)
+    assert st["completed"] == 5 and st["failed"] == 0
+    assert order == [0] + expect
+    assert expect.index(1) < 3          # the large request was not left to the end
+    for k, ((a, r), x) in enumerate(zip(args, res)):
+        assert torch.equal(x.flux.cpu(), ctx.emission_flux(a, r).cpu()), k
+    import paper_2105_14782_amd as pkg
+    bad = serve.Server(ctx, n_streams=1, mem_budget_bytes=1 << 20)
+    with pytest.raises(pkg.ExoError):
+        bad.set_policy("shortest", max_passes=0)
+    bad.close()
